@@ -1,0 +1,153 @@
+"""Benchmark of the CoFEM hot path on one MI355X.
+
+A step is one EM iteration of Alg. 2 over the whole batch: the E-step (batched CG over all
+T*C*(K+1) right-hand sides, diagonal and log-determinant estimators, responsibilities) and the
+M-step.  Workload: T=64 tasks, C=4 clusters, D=4096, N_t=1024, K=32 probes, CG tolerance 1e-6
+with at most 200 steps, synthetic Gaussian sensing data (see synth/).  Inputs are resident in
+device memory before timing starts.
+
+Printed (one JSON line): CG right-hand-side iterations per second over the timed EM iterations
+(value), the EM iteration time (ms_per_step), the roofline position of the dominant kernel
+(timed with HIP events on the library's stream) and the FP64 oracle's rate on a bounded
+sample on the host CPU.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}     # MI355X dense matrix-core peaks
+HBM_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="prec")
+    ap.add_argument("--math", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tasks", type=int, default=4)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, ntasks):
+    """The FP64 oracle on a bounded sample: `ntasks` tasks (spread over the true clusters), one
+    full E-step with the workload's CG policy."""
+    from oracle import cofem, cg as ocg
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()
+                       if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    cfg = w.cfg
+    tasks = list(np.linspace(0, cfg.T - 1, ntasks).round().astype(int))
+    pol = ocg.CGPolicy(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters)
+    Phi, y = w.phi_list(), w.y_list()
+    b = cofem.rhs([Phi[t] for t in tasks], [y[t] for t in tasks], w.beta)
+    b_full = [None] * cfg.T
+    for i, t in enumerate(tasks):
+        b_full[t] = b[i]
+    t0 = time.perf_counter()
+    ref = cofem.estep(Phi, b_full, w.beta, w.alpha0, w.log_pi, cfg.K, pol, seed=1, it=0,
+                      t_sel=tasks)
+    dt = time.perf_counter() - t0
+    rhs_iters = int(ref["iters"].sum())
+    return {"value": rhs_iters / dt, "unit": "RHS-iters/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "tasks %s of the workload, one E-step (K=%d, tol %g, <=%d CG steps), "
+                      "%d RHS-iterations in %.1f s; FP64 numpy/OpenBLAS"
+                      % (tasks, cfg.K, cfg.tol, cfg.max_iters, rhs_iters, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (tasks would shard "
+              "across GPUs with one all-reduce of the M-step sums per EM iteration; not built). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2310_00420_amd import Cmtcs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = synth.make(a.config)
+    cfg = w.cfg
+    rows = int(w.row_off[-1])
+    phi = torch.from_numpy(w.Phi).to(dev)
+    y = torch.from_numpy(w.y).to(dev)
+    m = Cmtcs(phi, w.row_off, y, w.beta, cfg.C, math=a.math, max_iters=cfg.max_iters,
+              max_K=cfg.K)
+    alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
+    log_pi = torch.tensor(w.log_pi, device=dev)
+    kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1)
+
+    def em_iteration(it):
+        out = m.estep(alpha, log_pi, cfg.K, em_iter=it, stats=True, **kw)
+        m.mstep(out["mu"], out["s"], out["q"], alpha)
+        return out
+
+    for it in range(a.warmup):
+        em_iteration(it)
+    torch.cuda.synchronize()
+    m.profile(True)
+    iters = []
+    t0 = time.perf_counter()
+    for it in range(a.warmup, a.warmup + a.steps):
+        out = em_iteration(it)
+        iters.append(out["iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = m.profile(False)
+    rhs_iters = int(sum(int(i.sum().item()) for i in iters))
+    max_steps = int(max(int(i.max().item()) for i in iters))
+
+    # roofline of the dominant kernel: algorithmic flops = 2 N D per RHS-iteration per product
+    N = rows // cfg.T
+    name = max(("phi_v", "phit_w"), key=lambda k: prof[k][0])
+    tot_ms, launches = prof[name]
+    flops = 2.0 * N * cfg.D * rhs_iters
+    achieved = flops / (tot_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[a.math]
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None, "kernel": name,
+            "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
+            "flop_per_launch": flops / max(launches, 1)}
+    res = {
+        "metric": "CG RHS-iters/sec + EM iter time, D=4096 T=64 C=4 K=32; MFMA/HBM roofline %",
+        "value": rhs_iters / dt, "unit": "RHS-iters/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": a.math,
+        "data": "synthetic: Phi_t iid N(0,1/N) stored fp32, %d true clusters with %d-sparse "
+                "shared supports, sigma %g, seeds data %d / init %d / probes 1"
+                % (cfg.groups, cfg.sparsity, cfg.sigma, synth.DATA_SEED, synth.INIT_SEED),
+        "config": {"workload": "CoFEM EM iteration (E-step + M-step), T=%d C=%d D=%d N=%d K=%d, "
+                               "CG tol %g, <=%d steps" % (cfg.T, cfg.C, cfg.D, N, cfg.K, cfg.tol,
+                                                          cfg.max_iters),
+                   "T": cfg.T, "C": cfg.C, "D": cfg.D, "N": N, "K": cfg.K, "math": a.math},
+        "roofline": roof,
+        "detail": {"rhs_iters_per_em_iter": rhs_iters / a.steps, "max_cg_steps": max_steps,
+                   "kernel_ms_per_em_iter": {k: round(v[0] / a.steps, 3)
+                                             for k, v in prof.items()},
+                   "launches_per_em_iter": {k: v[1] / a.steps for k, v in prof.items()}},
+    }
+    if not a.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, a.cpu_tasks)
+    m.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,206 @@
+/*
+ * cmtcs.h -- C ABI of the MI355X (gfx950) library for covariance-free EM (CoFEM) on clustered
+ * multi-task compressive sensing (Lin & Ba, arXiv 2310.00420).
+ *
+ * Model (Sec. 2, Eq. (cmtcs)): task t has measurements y_t = Phi_t z_t + noise, Phi_t is
+ * N_t x D, the noise precision is beta, and z_t belongs to one of C clusters with prior
+ * precisions alpha_c (a C x D array) and prior probabilities pi_c.
+ *
+ * The library implements the E-step of CoFEM (Alg. 2) on the GPU: for every task t and cluster
+ * c it solves, with the conjugate-gradient method of Alg. 1,
+ *       A_tc x = b,   A_tc = beta Phi_t^T Phi_t + diag(alpha_c)            (Eq. (lin-sys))
+ * for the posterior-mean right-hand side b_t = beta Phi_t^T y_t and K Rademacher probes
+ * p_tck (Sec. 3.1), then forms the posterior mean mu_tc, the diagonal estimate s_tc
+ * (Eq. (diag-est)), the log-determinant estimate nu_tc from the CG coefficients (Eqs. (tridiag),
+ * (hutch-trace), (logdet-est), Sec. 3.2) and the cluster responsibilities q_tc (Eq. (estep));
+ * and the M-step of Eq. (mstep).  A is never formed: each CG step applies Phi_t and Phi_t^T to
+ * all right-hand sides of a task at once (Sec. 3.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked HOST.  Arrays are
+ *    dense, row-major, without padding, in the element type stated at each argument.
+ *  - Work is enqueued on the stream given to cmtcs_create and is asynchronous: outputs are
+ *    valid once that stream has been synchronised.  The library never allocates device memory
+ *    after cmtcs_create returns.
+ *  - Every function returns a cmtcs_status_t; on anything but CMTCS_OK, cmtcs_last_error()
+ *    returns a message for the calling thread.  Argument errors are detected on the host before
+ *    any work is enqueued, and then no output is written.  No C++ exception crosses the ABI.
+ *  - Numerical outcomes of individual solves (max iterations reached, breakdown) are not
+ *    errors: they are reported per right-hand side through cmtcs_cg_stats_t.
+ *  - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef CMTCS_H
+#define CMTCS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cmtcs_handle_s* cmtcs_handle_t;
+
+typedef enum {
+  CMTCS_OK = 0,
+  CMTCS_E_INVALID = 1,      /* bad argument: null pointer, bad size, inconsistent options   */
+  CMTCS_E_HIP = 2,          /* a HIP runtime call failed (message names the call)           */
+  CMTCS_E_NOMEM = 3,        /* workspace allocation failed in cmtcs_create                  */
+  CMTCS_E_UNSUPPORTED = 4   /* valid request outside what this build implements             */
+} cmtcs_status_t;
+
+/* Storage type of Phi in device memory. */
+typedef enum { CMTCS_F32 = 0, CMTCS_BF16 = 1, CMTCS_F16 = 2 } cmtcs_dtype_t;
+
+/* Arithmetic of the operator products and of the CG vectors.
+ *  CMTCS_MATH_F64: Phi products on FP64 matrix cores, CG vectors x, r, d, A d in FP64.
+ *  CMTCS_MATH_F32: Phi products on FP32 matrix cores, CG vectors in FP32.
+ *  CMTCS_MATH_MIXED: Phi stored in 16 bits (phi_dtype BF16/F16), the CG direction rounded to
+ *                    the same 16-bit type, products on 16-bit matrix cores with FP32
+ *                    accumulation; CG vectors in FP32; the recursive residual is replaced by
+ *                    the true residual b - A x, computed with FP64 products from the FP32
+ *                    copy of Phi, every refine_every steps and when a solve stops.
+ *  In every mode the CG scalars (r.r, d.Ad, gamma, xi), the tridiagonal eigenproblems, the
+ *  log-determinants and the responsibilities are FP64. */
+typedef enum { CMTCS_MATH_F64 = 0, CMTCS_MATH_F32 = 1, CMTCS_MATH_MIXED = 2 } cmtcs_math_t;
+
+/* Per-right-hand-side CG outcome codes (values of cmtcs_cg_stats_t.status). */
+enum {
+  CMTCS_CG_CONVERGED = 0,   /* tolerance met, the fixed step count done, or r = 0 exactly   */
+  CMTCS_CG_MAX_ITER = 1,    /* tolerance mode: max_iters steps without meeting tol          */
+  CMTCS_CG_BREAKDOWN = 2    /* d.Ad <= 0 or a non-finite scalar; the solve stopped before it */
+};
+
+/* Problem data: fixed for the lifetime of a handle.  The library reads phi, phi_f32 and y
+ * in place (it does not copy them), so they must stay valid and unchanged until destroy. */
+typedef struct {
+  int32_t T;                /* tasks, >= 1                                                  */
+  int32_t C;                /* clusters, >= 1                                               */
+  int32_t D;                /* signal length, a positive multiple of 16, <= 16384           */
+  const int64_t* row_off;   /* HOST, T+1 non-decreasing prefix sums of N_t, row_off[0] = 0;
+                               N_t = 0 is allowed (then A_tc = diag(alpha_c))               */
+  const void* phi;          /* device [row_off[T]][D] in phi_dtype: the stacked Phi_t       */
+  cmtcs_dtype_t phi_dtype;  /* F32 for MATH_F64 / MATH_F32; BF16 or F16 for MATH_MIXED      */
+  const float* phi_f32;     /* device [row_off[T]][D] FP32 Phi; required by MATH_MIXED for
+                               the true residual, ignored otherwise                         */
+  const float* y;           /* device [row_off[T]] measurements, stacked like Phi           */
+  double beta;              /* noise precision, > 0                                         */
+  cmtcs_math_t math;        /* arithmetic, see cmtcs_math_t                                 */
+  int32_t max_rhs;          /* largest number of right-hand sides per task any later call
+                               uses: >= C*(K+1) for cmtcs_estep, >= R_per_task for
+                               cmtcs_solve                                                   */
+  int32_t max_iters;        /* largest CG step count any later call uses (1..4096)          */
+  int32_t max_K;            /* largest probe count any later cmtcs_estep uses (>= 0)        */
+} cmtcs_problem_t;
+
+/* Options of one call.  CG stopping (the paper runs CG "until convergence" in Alg. 1 and for
+ * U steps in Sec. 3.1): with fixed_iters = U > 0 every right-hand side takes exactly U steps;
+ * otherwise a right-hand side stops after the first step u with ||r_{u+1}|| <= tol ||b||
+ * (recursive residual) or after max_iters steps.  Either mode stops a right-hand side before a
+ * step whose d.Ad is not positive and finite, and after a step whose r.r is 0 or not finite. */
+typedef struct {
+  int32_t K;                /* probes per (task, cluster) for cmtcs_estep, >= 1             */
+  int32_t max_iters;        /* tolerance mode step cap, 1..problem.max_iters                */
+  int32_t fixed_iters;      /* > 0: fixed mode with this many steps (<= problem.max_iters)  */
+  double tol;               /* tolerance mode threshold, >= 0                               */
+  int32_t refine_every;     /* MATH_MIXED: true-residual replacement period m >= 1;
+                               ignored in the other modes                                   */
+  uint64_t seed;            /* probe generator key (see cmtcs_estep)                        */
+  uint64_t em_iter;         /* EM iteration index mixed into the probe key                  */
+  const int8_t* probes;     /* optional device [T][C][K][D] of +1/-1 replacing the
+                               generated probes; NULL = generated                           */
+  double alpha_max;         /* M-step cap on alpha, > 0 (see cmtcs_mstep)                   */
+} cmtcs_opts_t;
+
+/* Optional per-right-hand-side outputs, device pointers, each may be NULL.  For cmtcs_estep
+ * the right-hand sides of task t are indexed j = c*(K+1) + k with k = 0 the mean system and
+ * k = 1..K the probes; for cmtcs_solve j is the caller's column.  Arrays are [T][R]. */
+typedef struct {
+  int32_t* iters;           /* CG steps taken                                               */
+  uint8_t* status;          /* CMTCS_CG_* code                                              */
+  double* ritz_min;         /* cmtcs_estep only, [T][C][K]: smallest eigenvalue of the
+                               probe's tridiagonal (Eq. (tridiag)); NaN if it took 0 steps  */
+  double* ritz_max;         /* cmtcs_estep only, [T][C][K]: largest eigenvalue              */
+} cmtcs_cg_stats_t;
+
+/* Creates a handle for one problem on `stream` (a hipStream_t; NULL = the null stream) and
+ * the current HIP device.  Allocates the whole workspace for the sizes in *prob and computes
+ * b_t = beta Phi_t^T y_t once (Eq. (lin-sys)), since b does not depend on alpha.
+ * On success *out receives the handle; on failure *out is set to NULL. */
+cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* prob, void* stream);
+
+/* Releases the workspace after the handle's stream has drained.  NULL is accepted. */
+cmtcs_status_t cmtcs_destroy(cmtcs_handle_t h);
+
+/* One CoFEM E-step (Alg. 2, inner loop over t and c), for all tasks and clusters.
+ *   alpha   [C][D] float, > 0: current prior precisions
+ *   log_pi  [C] double: log prior cluster probabilities
+ *   mu      [T][C][D] float out: CG solution of the mean system of (t, c)
+ *   s       [T][C][D] float out: (1/K) sum_k p_k (.) x_k (Eq. (diag-est))
+ *   logdet  [T][C] double out: nu-bar, the estimate of log det Sigma_tc (Eq. (logdet-est))
+ *   ell     [T][C] double out: nu-bar + sum_d log alpha_cd + b_t . mu_tc (Eq. (estep))
+ *   q       [T][C] double out: softmax over c of ell_tc / 2 + log_pi_c (Eq. (estep))
+ *   stats   optional outputs (may be NULL)
+ * Probes: unless opts->probes is given, entry d of probe k (0-based) of pair (t, c) is
+ * +1 or -1 from bit d mod 64 of word floor(d/64) (bit 0 -> +1, 1 -> -1), where word m is the
+ * SplitMix64 output mix(key + (i+1) G), i = ((t C + c) K + k) ceil(D/64) + m, the key is
+ * mix(seed + (em_iter+1) G), G = 0x9E3779B97F4A7C15, and mix is SplitMix64's finaliser
+ * (Steele, Lea & Flood, OOPSLA 2014).  Probes are fresh per EM iteration, task and cluster
+ * (Alg. 2).  A probe whose tridiagonal has a non-positive eigenvalue is left out of the
+ * average of Eq. (logdet-est). */
+cmtcs_status_t cmtcs_estep(cmtcs_handle_t h, const float* alpha, const double* log_pi,
+                           const cmtcs_opts_t* opts, float* mu, float* s, double* logdet,
+                           double* ell, double* q, cmtcs_cg_stats_t* stats);
+
+/* The M-step of Eq. (mstep) with the diagonal of Sigma replaced by s:
+ *   alpha_cd = Nq_c / den_cd,  Nq_c = sum_t q_tc,  den_cd = sum_t q_tc (mu_tcd^2 + s_tcd).
+ * The paper states no guards; s is a Monte Carlo estimate, so den can be <= 0.  Applied here:
+ * a cluster with Nq_c < 1e-300 keeps its alpha; otherwise alpha_cd = Nq_c / den_cd when
+ * den_cd > Nq_c / alpha_max, else alpha_max.  Sums are FP64 in task order.
+ *   mu, s [T][C][D] float; q [T][C] double; alpha_inout [C][D] float, updated in place. */
+cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, const double* q,
+                           const cmtcs_opts_t* opts, float* alpha_inout);
+
+/* Batched CG (Alg. 1) on caller-supplied right-hand sides: for task t and column j solves
+ * (beta Phi_t^T Phi_t + diag(alpha_{col_cluster[j]})) X[t][j] = B[t][j] from x = 0.
+ *   alpha        [C][D] float
+ *   R_per_task   columns per task, 1..problem.max_rhs
+ *   col_cluster  HOST [R_per_task] int32, each in 0..C-1
+ *   B, X         [T][R_per_task][D], double for MATH_F64, float otherwise
+ *   gamma, xi    optional [T][R_per_task][opts->max_iters or fixed_iters] double outputs: the
+ *                step sizes gamma_u and xi_u of Alg. 1, zero past the steps taken
+ *   stats        optional (iters, status used)
+ * opts->K, seed, em_iter, probes and alpha_max are ignored. */
+cmtcs_status_t cmtcs_solve(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,
+                           const int32_t* col_cluster, const void* B, void* X, double* gamma,
+                           double* xi, const cmtcs_opts_t* opts, cmtcs_cg_stats_t* stats);
+
+/* The operator alone (Eq. (lin-sys), applied matrix-free as in Sec. 3.3):
+ *   AV[t][j] = beta Phi_t^T (Phi_t V[t][j]) + alpha_{col_cluster[j]} (.) V[t][j]
+ * with the same matrix-core products a CG step uses.
+ *   alpha        [C][D] float
+ *   R_per_task   1..problem.max_rhs;  col_cluster HOST [R_per_task] int32 in 0..C-1
+ *   V, AV        [T][R_per_task][D], double for MATH_F64, float otherwise */
+cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,
+                           const int32_t* col_cluster, const void* V, void* AV);
+
+/* Kernel timing for measurement: while enabled, each CG step's two operator products and its
+ * vector update are bracketed by HIP events on the handle's stream and their durations are
+ * summed.  enable = 1 clears the sums and turns timing on; enable = 0 turns it off; any other
+ * value leaves the state unchanged.  When non-NULL, the HOST arrays receive the sums so far
+ * (after the stream has drained): totals_ms[3] in milliseconds and counts[3] in launches, in
+ * the order {Phi V product, Phi^T W product, CG update}. */
+cmtcs_status_t cmtcs_profile(cmtcs_handle_t h, int32_t enable, double* totals_ms,
+                             int64_t* counts);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* cmtcs_last_error(void);
+
+/* Library version string. */
+const char* cmtcs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CMTCS_H */

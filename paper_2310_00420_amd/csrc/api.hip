@@ -1,0 +1,500 @@
+// C ABI of the library (include/cmtcs.h): handle and workspace management, argument checks,
+// and the host loop that drives one batched CG solve (Alg. 1 over all right-hand sides of all
+// tasks, Sec. 3.3) per E-step of Alg. 2.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "../../include/cmtcs.h"
+
+using namespace cmtcs;
+
+namespace {
+
+thread_local std::string g_err;
+
+cmtcs_status_t fail(cmtcs_status_t st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+cmtcs_status_t hip_fail(hipError_t e, const char* what) {
+  return fail(CMTCS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                              \
+  do {                                                   \
+    hipError_t e_ = (expr);                              \
+    if (e_ != hipSuccess) return hip_fail(e_, what);     \
+  } while (0)
+
+int round16(int x) { return (x + 15) / 16 * 16; }
+
+// Steps between host checks of the per-step active counts (early exit of the host loop once
+// every right-hand side has stopped).
+constexpr int kCheckEvery = 8;
+
+}  // namespace
+
+struct cmtcs_handle_s {
+  int T = 0, C = 0, D = 0;
+  double beta = 0.0;
+  cmtcs_math_t math = CMTCS_MATH_F64;
+  int max_rhs = 0, max_iters = 0, max_K = 0, Rp_max = 0;
+  size_t vbytes = 8;
+  std::vector<int64_t> row_off;
+  const float* phi = nullptr;
+  const float* y = nullptr;
+  hipStream_t st = nullptr;
+
+  std::vector<void*> allocs;
+  int64_t* row_off_d = nullptr;
+  int64_t* w_off_d = nullptr;
+  void *X = nullptr, *Rv = nullptr, *Dv = nullptr, *AD = nullptr, *W = nullptr, *b = nullptr;
+  double *rr = nullptr, *thr = nullptr, *gam = nullptr, *xi = nullptr;
+  uint8_t* state = nullptr;
+  int* iters = nullptr;
+  int* act = nullptr;
+  int* colc = nullptr;
+  int4* fwd_tiles = nullptr;
+  int4* adj_tiles = nullptr;
+  int nfwd = 0, nadj = 0, cur_Rp = -1;
+  double *dg = nullptr, *of = nullptr, *zz = nullptr, *tau = nullptr, *rmin = nullptr,
+         *rmax = nullptr, *slog = nullptr;
+  uint8_t* ok = nullptr;
+  int* act_host = nullptr;   // pinned
+
+  // kernel timing (cmtcs_profile)
+  bool prof_on = false;
+  hipEvent_t ev[kCheckEvery][4] = {};
+  bool ev_made = false;
+  int ev_pending = 0;
+  double prof_ms[3] = {0, 0, 0};
+  int64_t prof_n[3] = {0, 0, 0};
+
+  template <typename P>
+  hipError_t alloc(P** p, size_t bytes) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) return e;
+    allocs.push_back(q);
+    *p = (P*)q;
+    return hipSuccess;
+  }
+
+  ~cmtcs_handle_s() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (act_host) (void)hipHostFree(act_host);
+    if (ev_made)
+      for (auto& row : ev)
+        for (auto& e : row) (void)hipEventDestroy(e);
+  }
+
+  // Adds the durations of the `ev_pending` timed steps recorded so far.
+  hipError_t harvest() {
+    for (int i = 0; i < ev_pending; ++i) {
+      hipError_t e = hipEventSynchronize(ev[i][3]);
+      if (e != hipSuccess) return e;
+      for (int k = 0; k < 3; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[i][k], ev[i][k + 1]);
+        if (e != hipSuccess) return e;
+        prof_ms[k] += ms;
+        prof_n[k] += 1;
+      }
+    }
+    ev_pending = 0;
+    return hipSuccess;
+  }
+
+  Geometry geom(int R, int Rp) const {
+    Geometry g;
+    g.T = T; g.C = C; g.D = D; g.R = R; g.Rp = Rp;
+    g.row_off = row_off_d; g.w_off = w_off_d;
+    return g;
+  }
+
+  CgState cg() const {
+    CgState s;
+    s.X = X; s.Rv = Rv; s.Dv = Dv; s.AD = AD;
+    s.rr = rr; s.thr = thr; s.state = state; s.iters = iters;
+    s.gam = gam; s.xi = xi; s.act = act;
+    return s;
+  }
+
+  int ngroups(int Rp) const { return (Rp / 16 + kColGroup - 1) / kColGroup; }
+
+  // Tile tables and W offsets for Rp column slots per task (rebuilt only when Rp changes).
+  cmtcs_status_t prepare(int Rp) {
+    if (Rp == cur_Rp) return CMTCS_OK;
+    const bool f64 = math == CMTCS_MATH_F64;
+    const int fr = fwd_rows_per_tile(f64), ar = adj_rows_per_tile(f64), ng = ngroups(Rp);
+    std::vector<int64_t> woff(T + 1, 0);
+    std::vector<int4> ft, at;
+    for (int t = 0; t < T; ++t) {
+      const int nt = (int)(row_off[t + 1] - row_off[t]);
+      const int np = round16(nt);
+      woff[t + 1] = woff[t] + (int64_t)Rp * np;
+      for (int n0 = 0; n0 < np; n0 += fr)
+        for (int cg = 0; cg < ng; ++cg) ft.push_back(make_int4(t, n0, cg, 0));
+      for (int d0 = 0; d0 < D; d0 += ar)
+        for (int cg = 0; cg < ng; ++cg) at.push_back(make_int4(t, d0, cg, 0));
+    }
+    HIP_TRY(hipMemcpyAsync(w_off_d, woff.data(), sizeof(int64_t) * (T + 1),
+                           hipMemcpyHostToDevice, st), "hipMemcpyAsync(w_off)");
+    if (!ft.empty())
+      HIP_TRY(hipMemcpyAsync(fwd_tiles, ft.data(), sizeof(int4) * ft.size(),
+                             hipMemcpyHostToDevice, st), "hipMemcpyAsync(fwd tiles)");
+    HIP_TRY(hipMemcpyAsync(adj_tiles, at.data(), sizeof(int4) * at.size(),
+                           hipMemcpyHostToDevice, st), "hipMemcpyAsync(adj tiles)");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(prepare)");
+    nfwd = (int)ft.size();
+    nadj = (int)at.size();
+    cur_Rp = Rp;
+    return CMTCS_OK;
+  }
+
+  // Runs CG steps until every right-hand side has stopped or `steps` steps are done.
+  template <typename VT>
+  cmtcs_status_t run_cg(const Geometry& g, const float* alpha, int steps, int fixed) {
+    const CgState s = cg();
+    for (int u = 0; u < steps; ++u) {
+      const int* act_u = act + (size_t)u * T;
+      hipEvent_t* e4 = prof_on ? ev[ev_pending] : nullptr;
+      if (e4) HIP_TRY(hipEventRecord(e4[0], st), "hipEventRecord");
+      HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, st),
+              "launch(phi_v)");
+      if (e4) HIP_TRY(hipEventRecord(e4[1], st), "hipEventRecord");
+      HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
+                                alpha, colc, beta, act_u, st), "launch(phit_w)");
+      if (e4) HIP_TRY(hipEventRecord(e4[2], st), "hipEventRecord");
+      HIP_TRY(launch_cg_update<VT>(g, s, u, steps, fixed, st), "launch(cg_update)");
+      if (e4) {
+        HIP_TRY(hipEventRecord(e4[3], st), "hipEventRecord");
+        if (++ev_pending == kCheckEvery) HIP_TRY(harvest(), "profile events");
+      }
+      if ((u + 1) % kCheckEvery == 0 && u + 1 < steps) {
+        HIP_TRY(hipMemcpyAsync(act_host, act + (size_t)(u + 1) * T, sizeof(int) * T,
+                               hipMemcpyDeviceToHost, st), "hipMemcpyAsync(active counts)");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(active counts)");
+        bool any = false;
+        for (int t = 0; t < T; ++t) any = any || act_host[t] != 0;
+        if (!any) break;
+      }
+    }
+    if (prof_on) HIP_TRY(harvest(), "profile events");
+    return CMTCS_OK;
+  }
+
+  template <typename VT>
+  cmtcs_status_t apply(const float* alpha, int R, const int32_t* col_cluster, const void* V,
+                       void* AV) {
+    const int Rp = round16(R);
+    cmtcs_status_t rs = prepare(Rp);
+    if (rs != CMTCS_OK) return rs;
+    const Geometry g = geom(R, Rp);
+    HIP_TRY(launch_fill_colc(colc, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
+    RhsSource src;
+    src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.key = 0; src.probes = nullptr;
+    HIP_TRY(launch_cg_init<VT>(g, cg(), src, 0.0, 0, st), "launch(cg_init)");
+    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr, st),
+            "launch(phi_v)");
+    HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
+                              alpha, colc, beta, nullptr, st), "launch(phit_w)");
+    CgState s = cg();
+    s.X = AD;   // copy A V out through the solution-copy kernel
+    HIP_TRY(launch_solve_output<VT>(g, s, AV, nullptr, nullptr, 0, nullptr, nullptr, st),
+            "launch(copy out)");
+    return CMTCS_OK;
+  }
+
+  template <typename VT>
+  cmtcs_status_t estep(const float* alpha, const double* log_pi, const cmtcs_opts_t& o,
+                       float* mu, float* sd, double* logdet, double* ell, double* q,
+                       cmtcs_cg_stats_t* stats) {
+    const int K = o.K, R = C * (K + 1), Rp = round16(R);
+    cmtcs_status_t rs = prepare(Rp);
+    if (rs != CMTCS_OK) return rs;
+    const Geometry g = geom(R, Rp);
+    const uint64_t key = probe_key(o.seed, o.em_iter);
+    const int fixed = o.fixed_iters > 0 ? 1 : 0;
+    const int steps = fixed ? o.fixed_iters : o.max_iters;
+    HIP_TRY(launch_fill_colc(colc, R, Rp, K, nullptr, st), "launch(fill_colc)");
+    RhsSource src;
+    src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.key = key; src.probes = o.probes;
+    HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
+    rs = run_cg<VT>(g, alpha, steps, fixed);
+    if (rs != CMTCS_OK) return rs;
+    HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key, o.probes, mu, sd, st),
+            "launch(estep_finalize)");
+    HIP_TRY(launch_sum_log_alpha(C, D, alpha, slog, st), "launch(sum_log_alpha)");
+    HIP_TRY(launch_slq(g, cg(), K, (double)D, dg, of, zz, tau, ok, rmin, rmax, st),
+            "launch(slq)");
+    HIP_TRY(launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, st),
+            "launch(resp)");
+    if (stats != nullptr) {
+      HIP_TRY(launch_stats_estep(g, cg(), stats->iters, stats->status, st), "launch(stats)");
+      const size_t P = (size_t)T * C * K;
+      if (stats->ritz_min != nullptr)
+        HIP_TRY(hipMemcpyAsync(stats->ritz_min, rmin, sizeof(double) * P,
+                               hipMemcpyDeviceToDevice, st), "hipMemcpyAsync(ritz_min)");
+      if (stats->ritz_max != nullptr)
+        HIP_TRY(hipMemcpyAsync(stats->ritz_max, rmax, sizeof(double) * P,
+                               hipMemcpyDeviceToDevice, st), "hipMemcpyAsync(ritz_max)");
+    }
+    return CMTCS_OK;
+  }
+
+  template <typename VT>
+  cmtcs_status_t solve(const float* alpha, int R, const int32_t* col_cluster, const void* B,
+                       void* Xout, double* gout, double* xout, const cmtcs_opts_t& o,
+                       cmtcs_cg_stats_t* stats) {
+    const int Rp = round16(R);
+    cmtcs_status_t rs = prepare(Rp);
+    if (rs != CMTCS_OK) return rs;
+    const Geometry g = geom(R, Rp);
+    const int fixed = o.fixed_iters > 0 ? 1 : 0;
+    const int steps = fixed ? o.fixed_iters : o.max_iters;
+    HIP_TRY(launch_fill_colc(colc, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
+    RhsSource src;
+    src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.key = 0; src.probes = nullptr;
+    HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
+    rs = run_cg<VT>(g, alpha, steps, fixed);
+    if (rs != CMTCS_OK) return rs;
+    HIP_TRY(launch_solve_output<VT>(g, cg(), Xout, gout, xout, steps,
+                                    stats ? stats->iters : nullptr,
+                                    stats ? stats->status : nullptr, st),
+            "launch(solve_output)");
+    return CMTCS_OK;
+  }
+};
+
+namespace {
+
+cmtcs_status_t check_opts(const cmtcs_handle_s* h, const cmtcs_opts_t* o, bool need_K) {
+  if (o == nullptr) return fail(CMTCS_E_INVALID, "opts is NULL");
+  if (o->fixed_iters < 0) return fail(CMTCS_E_INVALID, "fixed_iters < 0");
+  if (o->fixed_iters > 0) {
+    if (o->fixed_iters > h->max_iters)
+      return fail(CMTCS_E_INVALID, "fixed_iters exceeds the handle's max_iters");
+  } else {
+    if (o->max_iters < 1 || o->max_iters > h->max_iters)
+      return fail(CMTCS_E_INVALID, "max_iters must be in 1..handle max_iters");
+    if (!(o->tol >= 0.0)) return fail(CMTCS_E_INVALID, "tol must be >= 0");
+  }
+  if (need_K) {
+    if (o->K < 1 || o->K > h->max_K) return fail(CMTCS_E_INVALID, "K must be in 1..max_K");
+    if ((int64_t)h->C * (o->K + 1) > h->max_rhs)
+      return fail(CMTCS_E_INVALID, "C*(K+1) exceeds the handle's max_rhs");
+  }
+  return CMTCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void* stream) {
+  if (out == nullptr) return fail(CMTCS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (p == nullptr) return fail(CMTCS_E_INVALID, "problem is NULL");
+  if (p->T < 1 || p->C < 1) return fail(CMTCS_E_INVALID, "T and C must be >= 1");
+  if (p->D < 16 || p->D % 16 != 0 || p->D > 16384)
+    return fail(CMTCS_E_INVALID, "D must be a positive multiple of 16, at most 16384");
+  if (p->row_off == nullptr) return fail(CMTCS_E_INVALID, "row_off is NULL");
+  if (p->row_off[0] != 0) return fail(CMTCS_E_INVALID, "row_off[0] must be 0");
+  for (int t = 0; t < p->T; ++t)
+    if (p->row_off[t + 1] < p->row_off[t])
+      return fail(CMTCS_E_INVALID, "row_off must be non-decreasing");
+  const int64_t rows = p->row_off[p->T];
+  if (rows > 0 && (p->phi == nullptr || p->y == nullptr))
+    return fail(CMTCS_E_INVALID, "phi and y must be non-NULL");
+  if (!(p->beta > 0.0)) return fail(CMTCS_E_INVALID, "beta must be > 0");
+  if (p->max_rhs < 1) return fail(CMTCS_E_INVALID, "max_rhs must be >= 1");
+  if (p->max_iters < 1 || p->max_iters > 4096)
+    return fail(CMTCS_E_INVALID, "max_iters must be in 1..4096");
+  if (p->max_K < 0) return fail(CMTCS_E_INVALID, "max_K must be >= 0");
+  if ((int64_t)p->C * (p->max_K + 1) > p->max_rhs && p->max_K > 0)
+    return fail(CMTCS_E_INVALID, "max_rhs must be >= C*(max_K+1)");
+  if (p->math == CMTCS_MATH_MIXED)
+    return fail(CMTCS_E_UNSUPPORTED, "CMTCS_MATH_MIXED is not available in this build");
+  if (p->math != CMTCS_MATH_F64 && p->math != CMTCS_MATH_F32)
+    return fail(CMTCS_E_INVALID, "unknown math mode");
+  if (p->phi_dtype != CMTCS_F32)
+    return fail(CMTCS_E_INVALID, "MATH_F64 and MATH_F32 take an F32 phi");
+  for (int t = 0; t < p->T; ++t)
+    if (p->row_off[t + 1] - p->row_off[t] > (1 << 30))
+      return fail(CMTCS_E_INVALID, "N_t too large");
+
+  cmtcs_handle_s* h = new (std::nothrow) cmtcs_handle_s();
+  if (h == nullptr) return fail(CMTCS_E_NOMEM, "host allocation failed");
+  h->T = p->T; h->C = p->C; h->D = p->D; h->beta = p->beta; h->math = p->math;
+  h->max_rhs = p->max_rhs; h->max_iters = p->max_iters; h->max_K = p->max_K;
+  h->Rp_max = round16(p->max_rhs);
+  h->vbytes = p->math == CMTCS_MATH_F64 ? 8 : 4;
+  h->row_off.assign(p->row_off, p->row_off + p->T + 1);
+  h->phi = (const float*)p->phi;
+  h->y = p->y;
+  h->st = (hipStream_t)stream;
+
+  const size_t T = h->T, C = h->C, D = h->D, Rpm = h->Rp_max, it = h->max_iters;
+  size_t np_sum = 0, fwd_max = 0;
+  const bool f64 = h->math == CMTCS_MATH_F64;
+  const size_t ngm = (size_t)h->ngroups(h->Rp_max);
+  for (size_t t = 0; t < T; ++t) {
+    const size_t np = (size_t)round16((int)(h->row_off[t + 1] - h->row_off[t]));
+    np_sum += np;
+    fwd_max += (np + fwd_rows_per_tile(f64) - 1) / fwd_rows_per_tile(f64) * ngm;
+  }
+  const size_t adj_max = T * ((D + adj_rows_per_tile(f64) - 1) / adj_rows_per_tile(f64)) * ngm;
+  const size_t vec = T * Rpm * D * h->vbytes;
+  const size_t P = T * C * (size_t)h->max_K;
+  hipError_t e = hipSuccess;
+  auto A = [&](auto** ptr, size_t bytes) {
+    if (e == hipSuccess) e = h->alloc(ptr, bytes);
+  };
+  A(&h->row_off_d, sizeof(int64_t) * (T + 1));
+  A(&h->w_off_d, sizeof(int64_t) * (T + 1));
+  A(&h->X, vec); A(&h->Rv, vec); A(&h->Dv, vec); A(&h->AD, vec);
+  A(&h->W, Rpm * np_sum * h->vbytes);
+  A(&h->b, T * D * h->vbytes);
+  A(&h->rr, sizeof(double) * T * Rpm);
+  A(&h->thr, sizeof(double) * T * Rpm);
+  A(&h->state, T * Rpm);
+  A(&h->iters, sizeof(int) * T * Rpm);
+  A(&h->gam, sizeof(double) * it * T * Rpm);
+  A(&h->xi, sizeof(double) * it * T * Rpm);
+  A(&h->act, sizeof(int) * (it + 1) * T);
+  A(&h->colc, sizeof(int) * Rpm);
+  A(&h->fwd_tiles, sizeof(int4) * fwd_max);
+  A(&h->adj_tiles, sizeof(int4) * adj_max);
+  A(&h->dg, sizeof(double) * it * P);
+  A(&h->of, sizeof(double) * it * P);
+  A(&h->zz, sizeof(double) * it * P);
+  A(&h->tau, sizeof(double) * P);
+  A(&h->rmin, sizeof(double) * P);
+  A(&h->rmax, sizeof(double) * P);
+  A(&h->ok, P);
+  A(&h->slog, sizeof(double) * C);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->act_host, sizeof(int) * T);
+  if (e != hipSuccess) {
+    delete h;
+    if (e == hipErrorOutOfMemory) return fail(CMTCS_E_NOMEM, "workspace allocation failed");
+    return hip_fail(e, "hipMalloc(workspace)");
+  }
+  e = hipMemcpyAsync(h->row_off_d, h->row_off.data(), sizeof(int64_t) * (T + 1),
+                     hipMemcpyHostToDevice, h->st);
+  if (e == hipSuccess) {
+    const Geometry g = h->geom(1, 16);
+    if (f64) e = launch_rhs<double>(g, h->phi, h->y, h->beta, (double*)h->b, h->st);
+    else e = launch_rhs<float>(g, h->phi, h->y, h->beta, (float*)h->b, h->st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+  if (e != hipSuccess) {
+    delete h;
+    return hip_fail(e, "cmtcs_create");
+  }
+  *out = h;
+  return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_destroy(cmtcs_handle_t h) {
+  if (h == nullptr) return CMTCS_OK;
+  hipError_t e = hipStreamSynchronize(h->st);
+  delete h;
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize(destroy)");
+  return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_estep(cmtcs_handle_t h, const float* alpha, const double* log_pi,
+                           const cmtcs_opts_t* opts, float* mu, float* s, double* logdet,
+                           double* ell, double* q, cmtcs_cg_stats_t* stats) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  cmtcs_status_t rs = check_opts(h, opts, true);
+  if (rs != CMTCS_OK) return rs;
+  if (!alpha || !log_pi || !mu || !s || !logdet || !ell || !q)
+    return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  if (h->math == CMTCS_MATH_F64)
+    return h->estep<double>(alpha, log_pi, *opts, mu, s, logdet, ell, q, stats);
+  return h->estep<float>(alpha, log_pi, *opts, mu, s, logdet, ell, q, stats);
+}
+
+cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, const double* q,
+                           const cmtcs_opts_t* opts, float* alpha_inout) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  if (opts == nullptr) return fail(CMTCS_E_INVALID, "opts is NULL");
+  if (!(opts->alpha_max > 0.0)) return fail(CMTCS_E_INVALID, "alpha_max must be > 0");
+  if (!mu || !s || !q || !alpha_inout)
+    return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  HIP_TRY(launch_mstep(h->T, h->C, h->D, mu, s, q, opts->alpha_max, alpha_inout, h->st),
+          "launch(mstep)");
+  return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_solve(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,
+                           const int32_t* col_cluster, const void* B, void* X, double* gamma,
+                           double* xi, const cmtcs_opts_t* opts, cmtcs_cg_stats_t* stats) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  cmtcs_status_t rs = check_opts(h, opts, false);
+  if (rs != CMTCS_OK) return rs;
+  if (R_per_task < 1 || R_per_task > h->max_rhs)
+    return fail(CMTCS_E_INVALID, "R_per_task must be in 1..max_rhs");
+  if (!alpha || !col_cluster || !B || !X)
+    return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  for (int j = 0; j < R_per_task; ++j)
+    if (col_cluster[j] < 0 || col_cluster[j] >= h->C)
+      return fail(CMTCS_E_INVALID, "col_cluster entries must be in 0..C-1");
+  if (h->math == CMTCS_MATH_F64)
+    return h->solve<double>(alpha, R_per_task, col_cluster, B, X, gamma, xi, *opts, stats);
+  return h->solve<float>(alpha, R_per_task, col_cluster, B, X, gamma, xi, *opts, stats);
+}
+
+cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,
+                           const int32_t* col_cluster, const void* V, void* AV) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  if (R_per_task < 1 || R_per_task > h->max_rhs)
+    return fail(CMTCS_E_INVALID, "R_per_task must be in 1..max_rhs");
+  if (!alpha || !col_cluster || !V || !AV)
+    return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  for (int j = 0; j < R_per_task; ++j)
+    if (col_cluster[j] < 0 || col_cluster[j] >= h->C)
+      return fail(CMTCS_E_INVALID, "col_cluster entries must be in 0..C-1");
+  if (h->math == CMTCS_MATH_F64) return h->apply<double>(alpha, R_per_task, col_cluster, V, AV);
+  return h->apply<float>(alpha, R_per_task, col_cluster, V, AV);
+}
+
+cmtcs_status_t cmtcs_profile(cmtcs_handle_t h, int32_t enable, double* totals_ms,
+                             int64_t* counts) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  if (enable == 1) {
+    if (!h->ev_made) {
+      for (auto& row : h->ev)
+        for (auto& e : row) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+      h->ev_made = true;
+    }
+    HIP_TRY(h->harvest(), "profile events");
+    for (int k = 0; k < 3; ++k) { h->prof_ms[k] = 0; h->prof_n[k] = 0; }
+    h->prof_on = true;
+  } else if (enable == 0) {
+    HIP_TRY(h->harvest(), "profile events");
+    h->prof_on = false;
+  }
+  if (totals_ms != nullptr || counts != nullptr) {
+    HIP_TRY(hipStreamSynchronize(h->st), "hipStreamSynchronize(profile)");
+    HIP_TRY(h->harvest(), "profile events");
+    for (int k = 0; k < 3; ++k) {
+      if (totals_ms) totals_ms[k] = h->prof_ms[k];
+      if (counts) counts[k] = h->prof_n[k];
+    }
+  }
+  return CMTCS_OK;
+}
+
+const char* cmtcs_last_error(void) { return g_err.c_str(); }
+
+const char* cmtcs_version(void) { return "cmtcs 0.1.0 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+// Internal declarations of the cmtcs HIP library: device helpers shared by the kernel files and
+// the host-side launchers the C ABI layer (api.hip) calls.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cmtcs {
+
+// ---------------------------------------------------------------------------------------------
+// Vector types used for wide loads and stores.
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int N> struct VecOf;
+template <> struct VecOf<float, 1> { typedef float type; };
+template <> struct VecOf<float, 2> { typedef f2 type; };
+template <> struct VecOf<float, 4> { typedef f4 type; };
+template <> struct VecOf<double, 1> { typedef double type; };
+template <> struct VecOf<double, 2> { typedef d2 type; };
+template <> struct VecOf<double, 4> { typedef d4 type; };
+
+// ---------------------------------------------------------------------------------------------
+// 16x16x4 matrix-core tiles.  For both element types a wave computes D = A B + C with A 16x4,
+// B 4x16: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].  Accumulator element r
+// (r = 0..3) of lane l holds D[out_row(l / 16, r)][l % 16]; the FP32 and FP64 instructions
+// differ here (rows 4 (l/16) + r versus l/16 + 4 r).  a_row(i) is a permutation of the 16 rows of
+// A chosen so that row a_row(out_row(g, r)) = 4 g + r: a lane then holds four consecutive rows.
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc_t;
+  __device__ static inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int out_row(int g, int r) { return g + 4 * r; }
+  __device__ static inline int a_row(int i) { return 4 * (i & 3) + (i >> 2); }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc_t;
+  __device__ static inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int out_row(int g, int r) { return 4 * g + r; }
+  __device__ static inline int a_row(int i) { return i; }
+};
+
+// ---------------------------------------------------------------------------------------------
+// Counter-based Rademacher probes (SplitMix64 finaliser; Steele, Lea & Flood 2014).
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+__host__ __device__ inline uint64_t sm64_mix(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Key of the probe stream of one EM iteration.
+__host__ __device__ inline uint64_t probe_key(uint64_t seed, uint64_t em_iter) {
+  return sm64_mix(seed + (em_iter + 1ull) * kGolden);
+}
+
+// Entry d of probe k of pair (t, c): +1 or -1.
+__device__ inline double probe_entry(uint64_t key, int t, int c, int k, int d, int C, int K,
+                                     int D) {
+  const uint64_t words = (uint64_t)((D + 63) >> 6);
+  const uint64_t i = (((uint64_t)t * C + c) * K + k) * words + (uint64_t)(d >> 6);
+  const uint64_t w = sm64_mix(key + (i + 1ull) * kGolden);
+  return ((w >> (d & 63)) & 1ull) ? -1.0 : 1.0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Fixed-order block reduction of doubles (deterministic run to run).  All threads of the block
+// must call it; every thread receives the sum.  `sh` needs BS/64 doubles of shared memory.
+template <int BS>
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < BS / 64; ++i) s += sh[i];
+  return s;
+}
+
+// Internal state of a right-hand side during CG.
+constexpr uint8_t kActive = 255;
+
+// ---------------------------------------------------------------------------------------------
+// Geometry of one batched solve: every task has Rp column slots (a multiple of 16; the first R
+// are right-hand sides, the rest zero padding) and W_t = Phi_t V_t is stored [Rp][np_t] with
+// np_t = N_t rounded up to 16, task t starting at element w_off[t].
+struct Geometry {
+  int T, C, D, R, Rp;
+  const int64_t* row_off;   // device [T+1]
+  const int64_t* w_off;     // device [T+1]
+};
+
+// Wave tiles of the two operator products, one int4 per tile:
+//   fwd  (W = Phi V):             {t, n0, column group, 0}
+//   adj  (A V = beta Phi^T W + alpha V): {t, d0, column group, 0}
+constexpr int kColGroup = 9;   // 16-column fragments per wave tile (144 columns)
+
+// Launchers (k_operator.hip).  `act` is the [T] count of active right-hand sides for the
+// current step (tasks with a zero count are skipped) or null.
+template <typename VT>
+hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                        const VT* V, VT* W, const int* act, hipStream_t st);
+template <typename VT>
+hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                         const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
+                         double beta, const int* act, hipStream_t st);
+int fwd_rows_per_tile(bool f64);
+int adj_rows_per_tile(bool f64);
+
+// Launchers (k_cg.hip).
+struct CgState {
+  void* X; void* Rv; void* Dv; void* AD;   // [T][Rp][D] vectors of the element type
+  double* rr;        // [T*Rp] current r.r
+  double* thr;       // [T*Rp] tol^2 ||b||^2
+  uint8_t* state;    // [T*Rp] kActive or a CMTCS_CG_* code
+  int* iters;        // [T*Rp]
+  double* gam;       // [max_iters][T*Rp]
+  double* xi;        // [max_iters][T*Rp]
+  int* act;          // [(max_iters+1)][T] active counts per step
+};
+// Source of the right-hand sides for cg_init.
+struct RhsSource {
+  int kind;                 // 0: estep (mean b_t and probes), 1: explicit B [T][R][D]
+  const void* b;            // kind 0: [T][D] b_t of the element type
+  const void* B;            // kind 1
+  int K;                    // kind 0
+  uint64_t key;             // kind 0: probe key
+  const int8_t* probes;     // kind 0: optional explicit probes [T][C][K][D]
+};
+template <typename VT>
+hipError_t launch_cg_init(const Geometry& g, const CgState& s, const RhsSource& src,
+                          double tol, int max_steps, hipStream_t st);
+template <typename VT>
+hipError_t launch_cg_update(const Geometry& g, const CgState& s, int u, int steps, int fixed,
+                            hipStream_t st);
+template <typename VT>
+hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, uint64_t key,
+                                 const int8_t* probes, float* mu, float* sdiag, hipStream_t st);
+template <typename VT>
+hipError_t launch_solve_output(const Geometry& g, const CgState& s, void* X, double* gam_out,
+                               double* xi_out, int steps, int* iters_out, uint8_t* status_out,
+                               hipStream_t st);
+hipError_t launch_fill_colc(int* colc, int R, int Rp, int K, const int32_t* host_map,
+                            hipStream_t st);
+hipError_t launch_zero_i32(int* p, long n, hipStream_t st);
+hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iters_out,
+                              uint8_t* status_out, hipStream_t st);
+
+// Launchers (k_slq.hip).
+hipError_t launch_slq(const Geometry& g, const CgState& s, int K, double pnorm2, double* dg,
+                      double* of, double* zz, double* tau, uint8_t* ok, double* rmin,
+                      double* rmax, hipStream_t st);
+
+// Launchers (k_em.hip).
+template <typename VT>
+hipError_t launch_rhs(const Geometry& g, const float* phi, const float* y, double beta, VT* b,
+                      hipStream_t st);
+hipError_t launch_sum_log_alpha(int C, int D, const float* alpha, double* slog, hipStream_t st);
+template <typename VT>
+hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
+                       const double* tau, const uint8_t* ok, const double* slog,
+                       const double* log_pi, double* logdet, double* ell, double* q,
+                       hipStream_t st);
+hipError_t launch_mstep(int T, int C, int D, const float* mu, const float* sdiag,
+                        const double* q, double alpha_max, float* alpha, hipStream_t st);
+
+}  // namespace cmtcs

@@ -1,0 +1,354 @@
+// Conjugate gradient (Alg. 1) over every right-hand side of every task at once (Sec. 3.3), and
+// the estimators read straight off the CG solutions: the posterior mean mu_tc (the mean system
+// of Eq. (lin-sys)) and the diagonal estimate s_tc = (1/K) sum_k p_k (.) x_k (Eq. (diag-est)).
+//
+// One workgroup owns one right-hand side (a column of D elements, held in registers), so both
+// reductions of a CG step (d.Ad and the new r.r) finish inside the workgroup and the whole
+// vector update of Alg. 1 (gamma, x, r, xi, d) is a single kernel.  Scalars are FP64 and the
+// reduction order is fixed, so results are identical run to run.
+#include "internal.h"
+#include "../../include/cmtcs.h"
+
+namespace cmtcs {
+
+template <typename VT, int BS, int EPT>
+__global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restrict__ Rv,
+                                                VT* __restrict__ Dv, double* __restrict__ rr,
+                                                double* __restrict__ thr,
+                                                uint8_t* __restrict__ state,
+                                                int* __restrict__ iters, int* __restrict__ act,
+                                                int kind, const VT* __restrict__ b,
+                                                const VT* __restrict__ B, int K, uint64_t key,
+                                                const int8_t* __restrict__ probes, double tol2,
+                                                int C, int R, int Rp, int D) {
+  __shared__ double sh[BS / 64];
+  const int col = blockIdx.x;
+  const int t = col / Rp, j = col % Rp;
+  const int64_t base = (int64_t)col * D;
+  if (j >= R) {   // padding slot: keep it zero so the operator products see zero columns
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int d = threadIdx.x + e * BS;
+      if (d < D) { X[base + d] = 0; Rv[base + d] = 0; Dv[base + d] = 0; }
+    }
+    return;
+  }
+  int c = 0, k = 0;
+  if (kind == 0) { c = j / (K + 1); k = j % (K + 1); }
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int d = threadIdx.x + e * BS;
+    if (d >= D) continue;
+    VT v;
+    if (kind == 0) {
+      if (k == 0) v = b[(int64_t)t * D + d];
+      else if (probes != nullptr)
+        v = (VT)probes[(((int64_t)t * C + c) * K + (k - 1)) * D + d];
+      else v = (VT)probe_entry(key, t, c, k - 1, d, C, K, D);
+    } else {
+      v = B[((int64_t)t * R + j) * D + d];
+    }
+    X[base + d] = 0;
+    Rv[base + d] = v;
+    Dv[base + d] = v;
+    acc += (double)v * (double)v;
+  }
+  const double r0 = block_sum<BS>(acc, sh);
+  if (threadIdx.x == 0) {
+    rr[col] = r0;
+    thr[col] = tol2 * r0;
+    iters[col] = 0;
+    uint8_t st;
+    if (!isfinite(r0)) st = CMTCS_CG_BREAKDOWN;
+    else if (r0 > 0.0) st = kActive;
+    else st = CMTCS_CG_CONVERGED;   // b = 0: x = 0 is exact
+    state[col] = st;
+    if (st == kActive) atomicAdd(&act[t], 1);
+  }
+}
+
+// One step u of Alg. 1 for every active right-hand side (Alg. 1, lines 3-7):
+//   gamma = r.r / d.Ad;  x += gamma d;  r -= gamma Ad;  xi = r'.r' / r.r;  d = r' + xi d.
+template <typename VT, int BS, int EPT>
+__global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __restrict__ Rv,
+                                                  VT* __restrict__ Dv,
+                                                  const VT* __restrict__ AD,
+                                                  double* __restrict__ rr,
+                                                  const double* __restrict__ thr,
+                                                  uint8_t* __restrict__ state,
+                                                  int* __restrict__ iters,
+                                                  double* __restrict__ gam,
+                                                  double* __restrict__ xi, int* __restrict__ act,
+                                                  int u, int steps, int fixed, int T, int R,
+                                                  int Rp, int D) {
+  __shared__ double sh[BS / 64];
+  const int t = blockIdx.x / R, j = blockIdx.x % R;
+  const int64_t idx = (int64_t)t * Rp + j;
+  if (state[idx] != kActive) return;
+  const double rr_old = rr[idx];   // read by every thread before thread 0 rewrites it
+  const int64_t base = idx * D;
+  VT dv[EPT], av[EPT];
+  double pd = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int d = threadIdx.x + e * BS;
+    if (d < D) {
+      dv[e] = Dv[base + d];
+      av[e] = AD[base + d];
+      pd += (double)dv[e] * (double)av[e];
+    } else {
+      dv[e] = 0; av[e] = 0;
+    }
+  }
+  const double dAd = block_sum<BS>(pd, sh);
+  if (!(dAd > 0.0) || !isfinite(dAd)) {
+    if (threadIdx.x == 0) state[idx] = CMTCS_CG_BREAKDOWN;
+    return;
+  }
+  const double g = rr_old / dAd;
+  const VT gv = (VT)g;
+  VT rv[EPT];
+  double pr = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int d = threadIdx.x + e * BS;
+    if (d < D) {
+      const VT xv = X[base + d] + gv * dv[e];
+      rv[e] = Rv[base + d] - gv * av[e];
+      X[base + d] = xv;
+      pr += (double)rv[e] * (double)rv[e];
+    } else {
+      rv[e] = 0;
+    }
+  }
+  const double rrn = block_sum<BS>(pr, sh);
+  const double x_ = rrn / rr_old;
+  const VT xv_ = (VT)x_;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int d = threadIdx.x + e * BS;
+    if (d < D) {
+      Rv[base + d] = rv[e];
+      Dv[base + d] = rv[e] + xv_ * dv[e];
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int64_t ncol = (int64_t)T * Rp;
+    gam[(int64_t)u * ncol + idx] = g;
+    xi[(int64_t)u * ncol + idx] = x_;
+    rr[idx] = rrn;
+    iters[idx] = u + 1;
+    uint8_t st = kActive;
+    if (!isfinite(rrn)) st = CMTCS_CG_BREAKDOWN;
+    else if (rrn == 0.0 || (fixed == 0 && rrn <= thr[idx])) st = CMTCS_CG_CONVERGED;
+    else if (u + 1 >= steps) st = fixed ? CMTCS_CG_CONVERGED : CMTCS_CG_MAX_ITER;
+    state[idx] = st;
+    if (st == kActive) atomicAdd(&act[(int64_t)(u + 1) * T + t], 1);
+  }
+}
+
+// mu_tc = x of the mean system; s_tc = (1/K) sum_k p_k (.) x_k  (Eq. (diag-est)).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_estep_finalize(const VT* __restrict__ X, int K,
+                                                        uint64_t key,
+                                                        const int8_t* __restrict__ probes,
+                                                        float* __restrict__ mu,
+                                                        float* __restrict__ sdiag, int C, int Rp,
+                                                        int D) {
+  const int tc = blockIdx.x;
+  const int t = tc / C, c = tc % C;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  const int64_t base = ((int64_t)t * Rp + (int64_t)c * (K + 1)) * D + d;
+  mu[(int64_t)tc * D + d] = (float)X[base];
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double p = probes != nullptr
+                         ? (double)probes[(((int64_t)t * C + c) * K + k) * D + d]
+                         : probe_entry(key, t, c, k, d, C, K, D);
+    acc += p * (double)X[base + (int64_t)(k + 1) * D];
+  }
+  sdiag[(int64_t)tc * D + d] = (float)(acc / (double)K);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_copy_cols(const VT* __restrict__ X,
+                                                   VT* __restrict__ out, int R, int Rp, int D) {
+  const int col = blockIdx.x;
+  const int t = col / R, j = col % R;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  out[(int64_t)col * D + d] = X[((int64_t)t * Rp + j) * D + d];
+}
+
+__global__ __launch_bounds__(256) void k_coef_out(const double* __restrict__ gam,
+                                                  const double* __restrict__ xi,
+                                                  const int* __restrict__ iters,
+                                                  double* __restrict__ gout,
+                                                  double* __restrict__ xout, int T, int R,
+                                                  int Rp, int steps) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)T * R * steps;
+  if (i >= total) return;
+  const int u = (int)(i % steps);
+  const int64_t col = i / steps;
+  const int t = (int)(col / R), j = (int)(col % R);
+  const int64_t idx = (int64_t)t * Rp + j;
+  const bool live = u < iters[idx];
+  const int64_t src = (int64_t)u * T * Rp + idx;
+  if (gout != nullptr) gout[i] = live ? gam[src] : 0.0;
+  if (xout != nullptr) xout[i] = live ? xi[src] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_stats_out(const int* __restrict__ iters,
+                                                   const uint8_t* __restrict__ state,
+                                                   int32_t* __restrict__ iout,
+                                                   uint8_t* __restrict__ sout, int T, int R,
+                                                   int Rp) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)T * R) return;
+  const int t = (int)(i / R), j = (int)(i % R);
+  const int64_t idx = (int64_t)t * Rp + j;
+  if (iout != nullptr) iout[i] = iters[idx];
+  if (sout != nullptr) sout[i] = state[idx];
+}
+
+__global__ __launch_bounds__(256) void k_fill_colc(int* __restrict__ colc, int R, int Rp, int K,
+                                                   int from_map) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= Rp) return;
+  if (j >= R) colc[j] = -1;
+  else if (!from_map) colc[j] = j / (K + 1);
+}
+
+__global__ __launch_bounds__(256) void k_zero_i32(int* __restrict__ p, long n) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers.  The column of D elements is held in registers: EPT elements per thread.
+
+template <typename VT, int BS, int EPT>
+static hipError_t init_one(const Geometry& g, const CgState& s, const RhsSource& src,
+                           double tol2, hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_init<VT, BS, EPT>), dim3(g.T * g.Rp), dim3(BS), 0, st, (VT*)s.X,
+                     (VT*)s.Rv, (VT*)s.Dv, s.rr, s.thr, s.state, s.iters, s.act, src.kind,
+                     (const VT*)src.b, (const VT*)src.B, src.K, src.key, src.probes, tol2, g.C,
+                     g.R, g.Rp, g.D);
+  return hipGetLastError();
+}
+
+template <typename VT, int BS, int EPT>
+static hipError_t update_one(const Geometry& g, const CgState& s, int u, int steps, int fixed,
+                             hipStream_t st) {
+  hipLaunchKernelGGL((k_cg_update<VT, BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, (VT*)s.X,
+                     (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state, s.iters,
+                     s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D);
+  return hipGetLastError();
+}
+
+// Dispatch on D: 256 threads with up to 16 elements each (D <= 4096), else 1024 threads.
+#define CMTCS_DISPATCH_D(FN, ...)                                                  \
+  do {                                                                             \
+    if (g.D <= 256) return FN<VT, 256, 1>(__VA_ARGS__);                            \
+    if (g.D <= 512) return FN<VT, 256, 2>(__VA_ARGS__);                            \
+    if (g.D <= 1024) return FN<VT, 256, 4>(__VA_ARGS__);                           \
+    if (g.D <= 2048) return FN<VT, 256, 8>(__VA_ARGS__);                           \
+    if (g.D <= 4096) return FN<VT, 256, 16>(__VA_ARGS__);                          \
+    if (g.D <= 8192) return FN<VT, 1024, 8>(__VA_ARGS__);                          \
+    return FN<VT, 1024, 16>(__VA_ARGS__);                                          \
+  } while (0)
+
+template <typename VT>
+hipError_t launch_cg_init(const Geometry& g, const CgState& s, const RhsSource& src, double tol,
+                          int max_steps, hipStream_t st) {
+  hipError_t e = launch_zero_i32(s.act, (long)(max_steps + 1) * g.T, st);
+  if (e != hipSuccess) return e;
+  const double tol2 = tol * tol;
+  CMTCS_DISPATCH_D(init_one, g, s, src, tol2, st);
+}
+
+template <typename VT>
+hipError_t launch_cg_update(const Geometry& g, const CgState& s, int u, int steps, int fixed,
+                            hipStream_t st) {
+  CMTCS_DISPATCH_D(update_one, g, s, u, steps, fixed, st);
+}
+
+template <typename VT>
+hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, uint64_t key,
+                                 const int8_t* probes, float* mu, float* sdiag, hipStream_t st) {
+  hipLaunchKernelGGL((k_estep_finalize<VT>), dim3(g.T * g.C, (g.D + 255) / 256), dim3(256), 0,
+                     st, (const VT*)s.X, K, key, probes, mu, sdiag, g.C, g.Rp, g.D);
+  return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_solve_output(const Geometry& g, const CgState& s, void* X, double* gam_out,
+                               double* xi_out, int steps, int* iters_out, uint8_t* status_out,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((k_copy_cols<VT>), dim3(g.T * g.R, (g.D + 255) / 256), dim3(256), 0, st,
+                     (const VT*)s.X, (VT*)X, g.R, g.Rp, g.D);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (gam_out != nullptr || xi_out != nullptr) {
+    const int64_t total = (int64_t)g.T * g.R * steps;
+    hipLaunchKernelGGL(k_coef_out, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       s.gam, s.xi, s.iters, gam_out, xi_out, g.T, g.R, g.Rp, steps);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (iters_out != nullptr || status_out != nullptr) {
+    const int64_t total = (int64_t)g.T * g.R;
+    hipLaunchKernelGGL(k_stats_out, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       s.iters, s.state, iters_out, status_out, g.T, g.R, g.Rp);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iters_out,
+                              uint8_t* status_out, hipStream_t st) {
+  if (iters_out == nullptr && status_out == nullptr) return hipSuccess;
+  const int64_t total = (int64_t)g.T * g.R;
+  hipLaunchKernelGGL(k_stats_out, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     s.iters, s.state, iters_out, status_out, g.T, g.R, g.Rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_colc(int* colc, int R, int Rp, int K, const int32_t* host_map,
+                            hipStream_t st) {
+  if (host_map != nullptr) {
+    hipError_t e = hipMemcpyAsync(colc, host_map, sizeof(int32_t) * R, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_fill_colc, dim3((Rp + 255) / 256), dim3(256), 0, st, colc, R, Rp, K,
+                     host_map != nullptr ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int* p, long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_cg_init<double>(const Geometry&, const CgState&, const RhsSource&,
+                                           double, int, hipStream_t);
+template hipError_t launch_cg_init<float>(const Geometry&, const CgState&, const RhsSource&,
+                                          double, int, hipStream_t);
+template hipError_t launch_cg_update<double>(const Geometry&, const CgState&, int, int, int,
+                                             hipStream_t);
+template hipError_t launch_cg_update<float>(const Geometry&, const CgState&, int, int, int,
+                                            hipStream_t);
+template hipError_t launch_estep_finalize<double>(const Geometry&, const CgState&, int, uint64_t,
+                                                  const int8_t*, float*, float*, hipStream_t);
+template hipError_t launch_estep_finalize<float>(const Geometry&, const CgState&, int, uint64_t,
+                                                 const int8_t*, float*, float*, hipStream_t);
+template hipError_t launch_solve_output<double>(const Geometry&, const CgState&, void*, double*,
+                                                double*, int, int*, uint8_t*, hipStream_t);
+template hipError_t launch_solve_output<float>(const Geometry&, const CgState&, void*, double*,
+                                               double*, int, int*, uint8_t*, hipStream_t);
+
+}  // namespace cmtcs

@@ -1,0 +1,141 @@
+// EM pieces around the batched solves (Alg. 2): the mean right-hand side b_t = beta Phi_t^T y_t
+// (Eq. (lin-sys)), the responsibilities q_tc (Eq. (estep)) and the alpha update (Eq. (mstep)).
+// All sums are FP64 in a fixed order.
+#include "internal.h"
+
+namespace cmtcs {
+
+// b_t[d] = beta sum_n Phi_t[n][d] y_t[n]: one thread per (t, d), rows read coalesced.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_rhs(const float* __restrict__ phi,
+                                             const int64_t* __restrict__ row_off,
+                                             const float* __restrict__ y, double beta,
+                                             VT* __restrict__ b, int D) {
+  const int t = blockIdx.x;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  const int64_t r0 = row_off[t], r1 = row_off[t + 1];
+  double acc = 0.0;
+  for (int64_t n = r0; n < r1; ++n) acc += (double)phi[n * D + d] * (double)y[n];
+  b[(int64_t)t * D + d] = (VT)(beta * acc);
+}
+
+// sum_d log alpha_cd, one block per cluster.
+__global__ __launch_bounds__(256) void k_sum_log_alpha(const float* __restrict__ alpha,
+                                                       double* __restrict__ slog, int D) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int d = threadIdx.x; d < D; d += 256) acc += log((double)alpha[(int64_t)c * D + d]);
+  const double s = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) slog[c] = s;
+}
+
+// Per task t (one block):
+//   nu_tc  = -(1/K') sum_k tau_tck over the K' probes with a positive spectrum (Eq. (logdet-est))
+//   ell_tc = nu_tc + sum_d log alpha_cd + b_t . mu_tc   (Eq. (estep): beta y^T Phi mu = b . mu)
+//   q_tc   = softmax over c of z_tc = ell_tc / 2 + log pi_c
+template <typename VT>
+__global__ __launch_bounds__(256) void k_resp(const VT* __restrict__ X, const VT* __restrict__ b,
+                                              const double* __restrict__ tau,
+                                              const uint8_t* __restrict__ ok,
+                                              const double* __restrict__ slog,
+                                              const double* __restrict__ log_pi,
+                                              double* __restrict__ logdet,
+                                              double* __restrict__ ell, double* __restrict__ q,
+                                              int C, int K, int Rp, int D) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
+  const VT* bt = b + (int64_t)t * D;
+  for (int c = 0; c < C; ++c) {
+    const VT* mu = X + ((int64_t)t * Rp + (int64_t)c * (K + 1)) * D;
+    double acc = 0.0;
+    for (int d = threadIdx.x; d < D; d += 256) acc += (double)bt[d] * (double)mu[d];
+    const double dot = block_sum<256>(acc, sh);
+    if (threadIdx.x == 0) {
+      double st = 0.0;
+      int keff = 0;
+      for (int k = 0; k < K; ++k) {
+        const int64_t p = ((int64_t)t * C + c) * K + k;
+        if (ok[p]) { st += tau[p]; ++keff; }
+      }
+      const double nu = keff > 0 ? -st / (double)keff : NAN;
+      logdet[(int64_t)t * C + c] = nu;
+      ell[(int64_t)t * C + c] = nu + slog[c] + dot;
+    }
+  }
+  if (threadIdx.x == 0) {
+    double m = -INFINITY;
+    for (int c = 0; c < C; ++c) m = fmax(m, 0.5 * ell[(int64_t)t * C + c] + log_pi[c]);
+    // q_c = exp(z_c - m) / sum_c' exp(z_c' - m): the same softmax as exp(z_c - logsumexp z),
+    // normalised by a division so that the q of a task sum to 1 within a few roundings even
+    // when |z| is large
+    double se = 0.0;
+    for (int c = 0; c < C; ++c) se += exp(0.5 * ell[(int64_t)t * C + c] + log_pi[c] - m);
+    for (int c = 0; c < C; ++c)
+      q[(int64_t)t * C + c] = exp(0.5 * ell[(int64_t)t * C + c] + log_pi[c] - m) / se;
+  }
+}
+
+// alpha_cd = Nq_c / den_cd with the guards stated in the ABI header; one thread per (c, d).
+__global__ __launch_bounds__(256) void k_mstep(const float* __restrict__ mu,
+                                               const float* __restrict__ sdiag,
+                                               const double* __restrict__ q, double alpha_max,
+                                               float* __restrict__ alpha, int T, int C, int D) {
+  const int c = blockIdx.y;
+  const int d = blockIdx.x * 256 + threadIdx.x;
+  if (d >= D) return;
+  double nq = 0.0, den = 0.0;
+  for (int t = 0; t < T; ++t) {
+    const double w = q[(int64_t)t * C + c];
+    const int64_t i = ((int64_t)t * C + c) * D + d;
+    const double m = (double)mu[i];
+    nq += w;
+    den += w * (m * m + (double)sdiag[i]);
+  }
+  if (nq < 1e-300) return;
+  alpha[(int64_t)c * D + d] = den > nq / alpha_max ? (float)(nq / den) : (float)alpha_max;
+}
+
+template <typename VT>
+hipError_t launch_rhs(const Geometry& g, const float* phi, const float* y, double beta, VT* b,
+                      hipStream_t st) {
+  hipLaunchKernelGGL((k_rhs<VT>), dim3(g.T, (g.D + 255) / 256), dim3(256), 0, st, phi,
+                     g.row_off, y, beta, b, g.D);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_log_alpha(int C, int D, const float* alpha, double* slog, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_log_alpha, dim3(C), dim3(256), 0, st, alpha, slog, D);
+  return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
+                       const double* tau, const uint8_t* ok, const double* slog,
+                       const double* log_pi, double* logdet, double* ell, double* q,
+                       hipStream_t st) {
+  hipLaunchKernelGGL((k_resp<VT>), dim3(g.T), dim3(256), 0, st, (const VT*)s.X, b, tau, ok, slog,
+                     log_pi, logdet, ell, q, g.C, K, g.Rp, g.D);
+  return hipGetLastError();
+}
+
+hipError_t launch_mstep(int T, int C, int D, const float* mu, const float* sdiag,
+                        const double* q, double alpha_max, float* alpha, hipStream_t st) {
+  hipLaunchKernelGGL(k_mstep, dim3((D + 255) / 256, C), dim3(256), 0, st, mu, sdiag, q,
+                     alpha_max, alpha, T, C, D);
+  return hipGetLastError();
+}
+
+template hipError_t launch_rhs<double>(const Geometry&, const float*, const float*, double,
+                                       double*, hipStream_t);
+template hipError_t launch_rhs<float>(const Geometry&, const float*, const float*, double,
+                                      float*, hipStream_t);
+template hipError_t launch_resp<double>(const Geometry&, const CgState&, int, const double*,
+                                        const double*, const uint8_t*, const double*,
+                                        const double*, double*, double*, double*, hipStream_t);
+template hipError_t launch_resp<float>(const Geometry&, const CgState&, int, const float*,
+                                       const double*, const uint8_t*, const double*,
+                                       const double*, double*, double*, double*, hipStream_t);
+
+}  // namespace cmtcs

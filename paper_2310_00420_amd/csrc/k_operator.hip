@@ -1,0 +1,225 @@
+// Matrix-free operator of CoFEM: for every task t, A_tc V = beta Phi_t^T (Phi_t V) + alpha_c (.) V
+// applied to all right-hand sides of the task at once (Sec. 3.3: only products with Phi and
+// Phi^T are needed, A is never formed).  Two matrix-core products per CG step:
+//
+//   fwd:  W_t  = Phi_t V_t          W_t [Rp][np_t], contraction over d (both operands
+//                                    d-contiguous: Phi_t rows and V_t columns)
+//   adj:  AV_t = beta Phi_t^T W_t + alpha_{c(j)} (.) V_t     contraction over n
+//
+// Each wave owns one output tile (16*RF rows x up to 144 columns) and keeps the whole
+// contraction in accumulator registers.  Loads are 16-byte or wider: lane l of the wave reads
+// consecutive elements of one row, and the four k-steps of a 16x16x4 tile take the four
+// consecutive elements in turn (a permutation of the contraction index that both operands
+// share, so the sum is unchanged).  Phi is streamed once per tile from HBM; the shared
+// right-hand-side block (V_t or W_t) is re-read by all tiles of a task and stays in L2, which is
+// why the block index is remapped so that the tiles of one task run on the same XCD.
+#include "internal.h"
+
+namespace cmtcs {
+
+// Workgroups are dispatched round-robin over the 8 XCDs; map the hardware block index to a
+// logical one so that each XCD receives a contiguous range of logical blocks.
+__device__ inline int xcd_block(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, rem) + i;
+}
+
+template <typename VT> struct OpCfg;
+template <> struct OpCfg<double> { static constexpr int kFwdRF = 2, kAdjRF = 2; };
+template <> struct OpCfg<float> { static constexpr int kFwdRF = 4, kAdjRF = 4; };
+
+int fwd_rows_per_tile(bool f64) { return 16 * (f64 ? OpCfg<double>::kFwdRF : OpCfg<float>::kFwdRF); }
+int adj_rows_per_tile(bool f64) { return 16 * (f64 ? OpCfg<double>::kAdjRF : OpCfg<float>::kAdjRF); }
+
+template <typename VT, int RF>
+__global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
+                                               const int64_t* __restrict__ row_off,
+                                               const int64_t* __restrict__ w_off,
+                                               const int4* __restrict__ tiles, int ntiles,
+                                               const VT* __restrict__ V, VT* __restrict__ W,
+                                               const int* __restrict__ act, int D, int Rp) {
+  typedef typename Mfma<VT>::acc_t acc_t;
+  typedef typename VecOf<VT, 4>::type vt4;
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int4 tl = tiles[tile];
+  const int t = tl.x, n0 = tl.y, cf0 = tl.z * kColGroup;
+  if (act != nullptr && act[t] == 0) return;
+  const int64_t r0 = row_off[t];
+  const int nt = (int)(row_off[t + 1] - r0);
+  const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
+  const int ncf = min(kColGroup, Rp / 16 - cf0);
+
+  const float* prow[RF];
+  bool pval[RF];
+#pragma unroll
+  for (int rf = 0; rf < RF; ++rf) {
+    // matrix row i16 of fragment rf is Phi row n0 + rf*16 + a_row(i16), so that the
+    // accumulator of lane (g4, r) holds the consecutive rows n0 + rf*16 + 4 g4 + r
+    const int row = n0 + rf * 16 + Mfma<VT>::a_row(i16);
+    pval[rf] = row < nt;
+    prow[rf] = phi + (r0 + (pval[rf] ? row : 0)) * (int64_t)D + 4 * g4;
+  }
+  const VT* vbase = V + ((int64_t)t * Rp + cf0 * 16 + i16) * D + 4 * g4;
+
+  acc_t acc[RF][kColGroup];
+#pragma unroll
+  for (int rf = 0; rf < RF; ++rf)
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
+
+  for (int d0 = 0; d0 < D; d0 += 16) {
+    f4 a[RF];
+#pragma unroll
+    for (int rf = 0; rf < RF; ++rf)
+      a[rf] = pval[rf] ? *(const f4*)(prow[rf] + d0) : f4{0.f, 0.f, 0.f, 0.f};
+    vt4 b[kColGroup];
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (cf < ncf) b[cf] = *(const vt4*)(vbase + (int64_t)cf * 16 * D + d0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int cf = 0; cf < kColGroup; ++cf)
+        if (cf < ncf)
+#pragma unroll
+          for (int rf = 0; rf < RF; ++rf)
+            acc[rf][cf] = Mfma<VT>::mma((VT)a[rf][s], b[cf][s], acc[rf][cf]);
+  }
+
+  VT* Wt = W + w_off[t];
+#pragma unroll
+  for (int rf = 0; rf < RF; ++rf) {
+    const int rb = n0 + rf * 16;
+    if (rb >= np) continue;
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      if (cf >= ncf) continue;
+      const int j = (cf0 + cf) * 16 + i16;
+      vt4 o;
+      o[0] = acc[rf][cf][0]; o[1] = acc[rf][cf][1]; o[2] = acc[rf][cf][2]; o[3] = acc[rf][cf][3];
+      *(vt4*)(Wt + (int64_t)j * np + rb + 4 * g4) = o;
+    }
+  }
+}
+
+template <typename VT, int RF>
+__global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
+                                                const int64_t* __restrict__ row_off,
+                                                const int64_t* __restrict__ w_off,
+                                                const int4* __restrict__ tiles, int ntiles,
+                                                const VT* __restrict__ W, const VT* __restrict__ V,
+                                                VT* __restrict__ AV,
+                                                const float* __restrict__ alpha,
+                                                const int* __restrict__ colc, double beta,
+                                                const int* __restrict__ act, int D, int Rp) {
+  typedef typename Mfma<VT>::acc_t acc_t;
+  typedef typename VecOf<VT, 4>::type vt4;
+  typedef typename VecOf<float, RF>::type frf;
+  typedef typename VecOf<VT, RF>::type vrf;
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int4 tl = tiles[tile];
+  const int t = tl.x, d0 = tl.y, cf0 = tl.z * kColGroup;
+  if (act != nullptr && act[t] == 0) return;
+  const int64_t r0 = row_off[t];
+  const int nt = (int)(row_off[t + 1] - r0);
+  const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
+  const int ncf = min(kColGroup, Rp / 16 - cf0);
+  const int dl = d0 + RF * i16;          // first of the RF output rows this lane loads
+  const bool dval = dl < D;
+  const float* pbase = phi + r0 * (int64_t)D + (dval ? dl : 0);
+  const VT* wbase = W + w_off[t] + (int64_t)(cf0 * 16 + i16) * np + 4 * g4;
+
+  acc_t acc[RF][kColGroup];
+#pragma unroll
+  for (int f = 0; f < RF; ++f)
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
+
+  for (int nb = 0; nb < np; nb += 16) {
+    frf a[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int n = nb + 4 * g4 + s;
+      if (dval && n < nt) a[s] = *(const frf*)(pbase + (int64_t)n * D);
+      else a[s] = frf{};
+    }
+    vt4 b[kColGroup];
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (cf < ncf) b[cf] = *(const vt4*)(wbase + (int64_t)cf * 16 * np + nb);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int cf = 0; cf < kColGroup; ++cf)
+        if (cf < ncf)
+#pragma unroll
+          for (int f = 0; f < RF; ++f) {
+            float av;
+            if constexpr (RF == 1) av = a[s]; else av = a[s][f];
+            acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], acc[f][cf]);
+          }
+  }
+
+#pragma unroll
+  for (int cf = 0; cf < kColGroup; ++cf) {
+    if (cf >= ncf) continue;
+    const int j = (cf0 + cf) * 16 + i16;
+    const int c = colc[j];
+    const int64_t col = ((int64_t)t * Rp + j) * D;
+    const float* al = alpha + (int64_t)(c >= 0 ? c : 0) * D;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int d = d0 + RF * Mfma<VT>::out_row(g4, r);
+      if (d >= D) continue;
+      const vrf v = *(const vrf*)(V + col + d);
+      vrf o;
+#pragma unroll
+      for (int f = 0; f < RF; ++f) {
+        const VT a = c >= 0 ? (VT)al[d + f] : (VT)0;
+        o[f] = (VT)beta * acc[f][cf][r] + a * v[f];
+      }
+      *(vrf*)(AV + col + d) = o;
+    }
+  }
+}
+
+template <typename VT>
+hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                        const VT* V, VT* W, const int* act, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  const int blocks = (ntiles + 3) / 4;
+  hipLaunchKernelGGL((k_phi_v<VT, OpCfg<VT>::kFwdRF>), dim3(blocks), dim3(256), 0, st, phi,
+                     g.row_off, g.w_off, tiles, ntiles, V, W, act, g.D, g.Rp);
+  return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                         const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
+                         double beta, const int* act, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  const int blocks = (ntiles + 3) / 4;
+  hipLaunchKernelGGL((k_phit_w<VT, OpCfg<VT>::kAdjRF>), dim3(blocks), dim3(256), 0, st, phi,
+                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
+                     g.Rp);
+  return hipGetLastError();
+}
+
+template hipError_t launch_phi_v<double>(const Geometry&, const float*, const int4*, int,
+                                         const double*, double*, const int*, hipStream_t);
+template hipError_t launch_phi_v<float>(const Geometry&, const float*, const int4*, int,
+                                        const float*, float*, const int*, hipStream_t);
+template hipError_t launch_phit_w<double>(const Geometry&, const float*, const int4*, int,
+                                          const double*, const double*, double*, const float*,
+                                          const int*, double, const int*, hipStream_t);
+template hipError_t launch_phit_w<float>(const Geometry&, const float*, const int4*, int,
+                                         const float*, const float*, float*, const float*,
+                                         const int*, double, const int*, hipStream_t);
+
+}  // namespace cmtcs

@@ -29,7 +29,7 @@ class Config:
     T: int
     C: int
     D: int
-    N: object              # int, or (lo, hi) for N_t ~ Uniform{lo..hi}
+    N: object              # int; (lo, hi) for N_t ~ Uniform{lo..hi}; or a list of T values
     sparsity: int
     groups: int            # number of true clusters (contiguous task blocks)
     K: int = 32
@@ -101,7 +101,9 @@ def make(cfg, data_seed=DATA_SEED, init_seed=INIT_SEED, **over):
         cfg = Config(**{**cfg.__dict__, **over})
     rng = np.random.default_rng(data_seed)
     T, D = cfg.T, cfg.D
-    if isinstance(cfg.N, (tuple, list)):
+    if isinstance(cfg.N, list) and len(cfg.N) == T:
+        Ns = np.asarray(cfg.N, dtype=np.int64)
+    elif isinstance(cfg.N, (tuple, list)):
         Ns = rng.integers(cfg.N[0], cfg.N[1] + 1, size=T)
     else:
         Ns = np.full(T, int(cfg.N))
@@ -116,7 +118,7 @@ def make(cfg, data_seed=DATA_SEED, init_seed=INIT_SEED, **over):
     for t in range(T):
         n = int(Ns[t])
         blk = rng.standard_normal((n, D), dtype=np.float32)
-        blk *= np.float32(1.0 / np.sqrt(n))
+        blk *= np.float32(1.0 / np.sqrt(max(n, 1)))
         Phi[row_off[t]:row_off[t + 1]] = blk
         z[t, supports[labels[t]]] = rng.standard_normal(cfg.sparsity)
         y[row_off[t]:row_off[t + 1]] = (blk.astype(np.float64) @ z[t]

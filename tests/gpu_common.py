@@ -1,0 +1,64 @@
+"""Helpers shared by the GPU tests: building a device problem from a synthetic workload and the
+error metrics used to compare the HIP path with the FP64 oracle."""
+
+import numpy as np
+import torch
+
+import synth
+from paper_2310_00420_amd import Cmtcs
+
+DEV = torch.device("cuda:0")
+
+
+def device_model(w, math="f64", K=None, max_iters=None, max_rhs=None):
+    K = w.cfg.K if K is None else K
+    steps = w.cfg.fixed_iters if w.cfg.fixed_iters > 0 else w.cfg.max_iters
+    max_iters = steps if max_iters is None else max_iters
+    phi = torch.from_numpy(np.ascontiguousarray(w.Phi)).to(DEV)
+    y = torch.from_numpy(np.ascontiguousarray(w.y)).to(DEV)
+    return Cmtcs(phi, w.row_off, y, w.beta, w.cfg.C, math=math, max_iters=max_iters,
+                 max_K=K, max_rhs=max_rhs)
+
+
+def alpha_dev(alpha):
+    return torch.tensor(np.asarray(alpha, np.float32), device=DEV)
+
+
+def log_pi_dev(log_pi):
+    return torch.tensor(np.asarray(log_pi, np.float64), device=DEV)
+
+
+def rel_cols(a, b):
+    """max over the leading indices of ||a - b|| / ||b|| along the last axis."""
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    num = np.linalg.norm(a - b, axis=-1)
+    den = np.linalg.norm(b, axis=-1)
+    return float(np.max(num / np.maximum(den, 1e-300)))
+
+
+def rel_max(a, b):
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
+
+
+def compare_estep(gpu, ref, tasks):
+    """Error metrics of a device E-step against the oracle's on the same tasks."""
+    g = {k: v.cpu().numpy() for k, v in gpu.items()}
+    t = np.asarray(tasks)
+    # ell is a sum of terms of size |nu|; relative to that scale (ell itself can be ~0, e.g.
+    # for a task without measurements, where nu = -sum log alpha exactly)
+    ell_scale = np.maximum(np.abs(ref["ell"]), np.abs(ref["nu"]))
+    # argmax of q is unique only where the top two z = ell/2 + log pi are apart
+    z = 0.5 * ref["ell"]
+    zs = np.sort(z, axis=1)
+    gap = zs[:, -1] - zs[:, -2] if z.shape[1] > 1 else np.full(len(z), np.inf)
+    decided = gap > 1e-6 * np.max(np.abs(ref["nu"]), axis=1)
+    return dict(
+        mu=rel_cols(g["mu"][t], ref["mu"]),
+        s=rel_cols(g["s"][t], ref["s"]),
+        logdet=rel_max(g["logdet"][t], ref["nu"]),
+        ell=float(np.max(np.abs(g["ell"][t] - ref["ell"]) / ell_scale)),
+        q_abs=float(np.max(np.abs(g["q"][t] - ref["q"]))),
+        argmax_equal=bool(np.all((g["q"][t].argmax(1) == ref["q"].argmax(1))[decided])),
+        undecided_tasks=int((~decided).sum()),
+    )

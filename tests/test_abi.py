@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every function include/cmtcs.h declares, and rejects bad
+arguments on the host before any HIP call (no GPU needed for any of this)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2310_00420_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cmtcs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cmtcs_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("cmtcs_create", "cmtcs_destroy", "cmtcs_estep", "cmtcs_mstep", "cmtcs_solve",
+              "cmtcs_apply", "cmtcs_profile", "cmtcs_last_error", "cmtcs_version"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version():
+    assert _lib.load().cmtcs_version().startswith(b"cmtcs")
+
+
+def _problem(**over):
+    T = over.pop("T", 2)
+    row_off = over.pop("row_off", np.array([0, 4, 8], np.int64))
+    p = dict(T=T, C=2, D=32, row_off=row_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+             phi=1, phi_dtype=_lib.CMTCS_F32, phi_f32=None, y=1, beta=1.0,
+             math=_lib.CMTCS_MATH_F64, max_rhs=34, max_iters=10, max_K=16)
+    p.update(over)
+    return _lib.Problem(**p), row_off
+
+
+@pytest.mark.parametrize("over,frag", [
+    (dict(D=30), "multiple of 16"),
+    (dict(D=0), "multiple of 16"),
+    (dict(T=0), "T and C"),
+    (dict(C=0), "T and C"),
+    (dict(beta=0.0), "beta"),
+    (dict(max_iters=0), "max_iters"),
+    (dict(max_rhs=0), "max_rhs"),
+    (dict(max_rhs=20), "max_rhs"),
+    (dict(phi=None), "phi and y"),
+    (dict(row_off=np.array([0, 5, 3], np.int64)), "non-decreasing"),
+    (dict(row_off=np.array([1, 5, 8], np.int64)), "row_off[0]"),
+    (dict(math=_lib.CMTCS_MATH_MIXED), "MATH_MIXED"),
+    (dict(phi_dtype=_lib.CMTCS_BF16), "F32 phi"),
+])
+def test_create_rejects_bad_problems(over, frag):
+    lib = _lib.load()
+    p, keep = _problem(**over)
+    h = ctypes.c_void_p(123)
+    rc = lib.cmtcs_create(ctypes.byref(h), ctypes.byref(p), None)
+    assert rc in (_lib.CMTCS_E_INVALID, _lib.CMTCS_E_UNSUPPORTED)
+    assert h.value is None
+    assert frag in lib.cmtcs_last_error().decode()
+
+
+def test_null_arguments():
+    lib = _lib.load()
+    assert lib.cmtcs_create(None, None, None) == _lib.CMTCS_E_INVALID
+    h = ctypes.c_void_p()
+    assert lib.cmtcs_create(ctypes.byref(h), None, None) == _lib.CMTCS_E_INVALID
+    o = _lib.Opts(K=1, max_iters=1)
+    assert lib.cmtcs_estep(None, None, None, ctypes.byref(o), None, None, None, None, None,
+                           None) == _lib.CMTCS_E_INVALID
+    assert lib.cmtcs_mstep(None, None, None, None, ctypes.byref(o), None) == _lib.CMTCS_E_INVALID
+    assert lib.cmtcs_solve(None, None, 1, None, None, None, None, None, ctypes.byref(o),
+                           None) == _lib.CMTCS_E_INVALID
+    assert lib.cmtcs_apply(None, None, 1, None, None, None) == _lib.CMTCS_E_INVALID
+    assert lib.cmtcs_profile(None, 1, None, None) == _lib.CMTCS_E_INVALID
+    assert lib.cmtcs_destroy(None) == _lib.CMTCS_OK
+
+
+def test_error_raises_from_python():
+    with pytest.raises(_lib.CmtcsError) as e:
+        _lib.check(_lib.load().cmtcs_create(None, None, None))
+    assert e.value.code == _lib.CMTCS_E_INVALID
