@@ -70,15 +70,19 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
 
-  for (int d0 = 0; d0 < D; d0 += 16) {
-    f4 a[RF];
+  // Software pipeline: the loads of chunk c+1 are issued before the matrix-core work of
+  // chunk c, so global-memory latency overlaps the MFMA chain (two register buffers).
+  f4 a0[RF], a1[RF];
+  vt4 b0[kColGroup], b1[kColGroup];
+  auto load = [&](f4 (&a)[RF], vt4 (&b)[kColGroup], int d0) {
 #pragma unroll
     for (int rf = 0; rf < RF; ++rf)
       a[rf] = pval[rf] ? *(const f4*)(prow[rf] + d0) : f4{0.f, 0.f, 0.f, 0.f};
-    vt4 b[kColGroup];
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (cf < ncf) b[cf] = *(const vt4*)(vbase + (int64_t)cf * 16 * D + d0);
+  };
+  auto mma = [&](const f4 (&a)[RF], const vt4 (&b)[kColGroup]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -87,6 +91,13 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
 #pragma unroll
           for (int rf = 0; rf < RF; ++rf)
             acc[rf][cf] = Mfma<VT>::mma((VT)a[rf][s], b[cf][s], acc[rf][cf]);
+  };
+  load(a0, b0, 0);
+  for (int d0 = 0; d0 < D; d0 += 32) {
+    if (d0 + 16 < D) load(a1, b1, d0 + 16);
+    mma(a0, b0);
+    if (d0 + 32 < D) load(a0, b0, d0 + 32);
+    if (d0 + 16 < D) mma(a1, b1);
   }
 
   VT* Wt = W + w_off[t];
@@ -141,18 +152,21 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
 
-  for (int nb = 0; nb < np; nb += 16) {
-    frf a[4];
+  // Software pipeline as in k_phi_v: loads of chunk c+1 overlap the MFMAs of chunk c.
+  frf a0[4], a1[4];
+  vt4 b0[kColGroup], b1[kColGroup];
+  auto load = [&](frf (&a)[4], vt4 (&b)[kColGroup], int nb) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int n = nb + 4 * g4 + s;
       if (dval && n < nt) a[s] = *(const frf*)(pbase + (int64_t)n * D);
       else a[s] = frf{};
     }
-    vt4 b[kColGroup];
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (cf < ncf) b[cf] = *(const vt4*)(wbase + (int64_t)cf * 16 * np + nb);
+  };
+  auto mma = [&](const frf (&a)[4], const vt4 (&b)[kColGroup]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -164,6 +178,13 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
             if constexpr (RF == 1) av = a[s]; else av = a[s][f];
             acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], acc[f][cf]);
           }
+  };
+  if (np > 0) load(a0, b0, 0);
+  for (int nb = 0; nb < np; nb += 32) {
+    if (nb + 16 < np) load(a1, b1, nb + 16);
+    mma(a0, b0);
+    if (nb + 32 < np) load(a0, b0, nb + 32);
+    if (nb + 16 < np) mma(a1, b1);
   }
 
 #pragma unroll
