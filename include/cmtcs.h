@@ -162,10 +162,10 @@ cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, co
                            const cmtcs_opts_t* opts, float* alpha_inout);
 
 /* Batched CG (Alg. 1) on caller-supplied right-hand sides: for task t and column j solves
- * (beta Phi_t^T Phi_t + diag(alpha_{col_cluster[j]})) X[t][j] = B[t][j] from x = 0.
+ * (beta Phi_t^T Phi_t + diag(alpha_{col_cluster[t][j]})) X[t][j] = B[t][j] from x = 0.
  *   alpha        [C][D] float
  *   R_per_task   columns per task, 1..problem.max_rhs
- *   col_cluster  HOST [R_per_task] int32, each in 0..C-1
+ *   col_cluster  HOST [T][R_per_task] int32, each in 0..C-1
  *   B, X         [T][R_per_task][D], double for MATH_F64, float otherwise
  *   gamma, xi    optional [T][R_per_task][opts->max_iters or fixed_iters] double outputs: the
  *                step sizes gamma_u and xi_u of Alg. 1, zero past the steps taken
@@ -175,11 +175,32 @@ cmtcs_status_t cmtcs_solve(cmtcs_handle_t h, const float* alpha, int32_t R_per_t
                            const int32_t* col_cluster, const void* B, void* X, double* gamma,
                            double* xi, const cmtcs_opts_t* opts, cmtcs_cg_stats_t* stats);
 
+/* The right-hand side of the posterior-mean system, b_t = beta Phi_t^T y_t (Eq. (lin-sys)),
+ * as computed at create.  b: [T][D], double for MATH_F64, float otherwise. */
+cmtcs_status_t cmtcs_rhs(cmtcs_handle_t h, void* b);
+
+/* Gradients of a scalar loss through X = A^-1 B (the differentiation form; derived from the
+ * operator A of Eq. (lin-sys)).  Given the solutions X and the adjoint solutions
+ * Lam = A^-1 (dLoss/dX) -- A is symmetric, so cmtcs_solve computes both -- of the same
+ * columns (same col_cluster):
+ *   dalpha[c][d] = - sum over (t, j) with col_cluster[t][j] = c of Lam[t][j][d] X[t][j][d]
+ *   dphi rows of task t = - beta sum_j [ (Phi_t Lam_tj) X_tj^T + (Phi_t X_tj) Lam_tj^T ]
+ *                         + y_coef * beta * y_t (sum_j Lam_tj)^T
+ * y_coef = 1 when B = beta Phi^T y (so B itself depends on Phi), 0 for a fixed B (whose own
+ * gradient is Lam).  Products with Phi run on the matrix cores; sums are FP64.
+ *   R_per_task   1..problem.max_rhs/2 (the 2R columns X, Lam share the workspace slots)
+ *   col_cluster  HOST [T][R_per_task] int32 in 0..C-1
+ *   X, Lam       [T][R_per_task][D], double for MATH_F64, float otherwise
+ *   dalpha       [C][D] float out (may be NULL);  dphi [row_off[T]][D] float out (may be NULL) */
+cmtcs_status_t cmtcs_grad(cmtcs_handle_t h, int32_t R_per_task, const int32_t* col_cluster,
+                          const void* X, const void* Lam, double y_coef, float* dalpha,
+                          float* dphi);
+
 /* The operator alone (Eq. (lin-sys), applied matrix-free as in Sec. 3.3):
  *   AV[t][j] = beta Phi_t^T (Phi_t V[t][j]) + alpha_{col_cluster[j]} (.) V[t][j]
  * with the same matrix-core products a CG step uses.
  *   alpha        [C][D] float
- *   R_per_task   1..problem.max_rhs;  col_cluster HOST [R_per_task] int32 in 0..C-1
+ *   R_per_task   1..problem.max_rhs;  col_cluster HOST [T][R_per_task] int32 in 0..C-1
  *   V, AV        [T][R_per_task][D], double for MATH_F64, float otherwise */
 cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,
                            const int32_t* col_cluster, const void* V, void* AV);

@@ -6,7 +6,7 @@ package only loads it and marshals arguments.  Importing :mod:`.api` fails loudl
 library has not been built.
 """
 
-from .api import Cmtcs, fit, MATH  # noqa: F401
+from .api import Cmtcs, fit, MATH, CGSolve, PosteriorMean  # noqa: F401
 from ._lib import CmtcsError, load  # noqa: F401
 
-__all__ = ["Cmtcs", "fit", "MATH", "CmtcsError", "load"]
+__all__ = ["Cmtcs", "fit", "MATH", "CGSolve", "PosteriorMean", "CmtcsError", "load"]

@@ -68,6 +68,11 @@ def load():
     lib.cmtcs_solve.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp, vp,
                                 vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(CgStats)]
     lib.cmtcs_solve.restype = st
+    lib.cmtcs_rhs.argtypes = [vp, vp]
+    lib.cmtcs_rhs.restype = st
+    lib.cmtcs_grad.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp, vp,
+                               ctypes.c_double, vp, vp]
+    lib.cmtcs_grad.restype = st
     lib.cmtcs_apply.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp, vp]
     lib.cmtcs_apply.restype = st
     lib.cmtcs_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),

@@ -19,6 +19,16 @@ def _ptr(x):
     return ctypes.c_void_p(0 if x is None else x.data_ptr())
 
 
+def _cluster_map(col_cluster, T, R):
+    """[T][R] int32 host map from a per-column [R] or per-task [T][R] assignment."""
+    cc = np.asarray(col_cluster, dtype=np.int32)
+    if cc.shape == (R,):
+        cc = np.broadcast_to(cc, (T, R))
+    if cc.shape != (T, R):
+        raise ValueError("col_cluster must have shape (R,) or (T, R)")
+    return np.ascontiguousarray(cc)
+
+
 def _need(x, dtype, shape, name):
     if not isinstance(x, torch.Tensor) or not x.is_cuda:
         raise TypeError("%s must be a device tensor" % name)
@@ -140,9 +150,7 @@ class Cmtcs:
         R = int(B.shape[1])
         _need(alpha, torch.float32, (C, D), "alpha")
         _need(B, self.vdtype, (T, R, D), "B")
-        cc = np.ascontiguousarray(np.asarray(col_cluster, dtype=np.int32))
-        if cc.shape != (R,):
-            raise ValueError("col_cluster must have one entry per column")
+        cc = _cluster_map(col_cluster, T, R)
         X = torch.empty_like(B)
         steps = fixed_iters if fixed_iters > 0 else max_iters
         g = x = None
@@ -171,14 +179,36 @@ class Cmtcs:
         R = int(V.shape[1])
         _need(alpha, torch.float32, (C, D), "alpha")
         _need(V, self.vdtype, (T, R, D), "V")
-        cc = np.ascontiguousarray(np.asarray(col_cluster, dtype=np.int32))
-        if cc.shape != (R,):
-            raise ValueError("col_cluster must have one entry per column")
+        cc = _cluster_map(col_cluster, T, R)
         AV = torch.empty_like(V)
         _lib.check(_lib.load().cmtcs_apply(self._h, _ptr(alpha), R,
                                            cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                            _ptr(V), _ptr(AV)))
         return AV
+
+    def rhs(self):
+        """b_t = beta Phi_t^T y_t as computed by the library, [T][D]."""
+        self._check_stream()
+        b = torch.empty(self.T, self.D, dtype=self.vdtype, device=self.device)
+        _lib.check(_lib.load().cmtcs_rhs(self._h, _ptr(b)))
+        return b
+
+    def grad(self, X, Lam, col_cluster, y_coef):
+        """(dalpha [C][D], dphi [rows][D]) from solutions X and adjoint solutions Lam
+        (see cmtcs_grad in include/cmtcs.h)."""
+        self._check_stream()
+        T, C, D = self.T, self.C, self.D
+        R = int(X.shape[1])
+        _need(X, self.vdtype, (T, R, D), "X")
+        _need(Lam, self.vdtype, (T, R, D), "Lam")
+        cc = _cluster_map(col_cluster, T, R)
+        dalpha = torch.empty(C, D, dtype=torch.float32, device=self.device)
+        dphi = torch.empty_like(self.phi)
+        _lib.check(_lib.load().cmtcs_grad(self._h, R,
+                                          cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          _ptr(X), _ptr(Lam), float(y_coef), _ptr(dalpha),
+                                          _ptr(dphi)))
+        return dalpha, dphi
 
     def profile(self, enable=None):
         """Kernel timing: enable (True/False) and/or read {name: (total ms, launches)}."""
@@ -207,3 +237,58 @@ def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, 
     recon = torch.stack([out["mu"][t, int(assign[t])] for t in range(model.T)])
     return dict(alpha=alpha, q=out["q"], assign=assign, recon=recon, mu=out["mu"], s=out["s"],
                 ell=out["ell"], logdet=out["logdet"])
+
+
+class CGSolve(torch.autograd.Function):
+    """X = A(alpha, Phi)^-1 B column by column, A_tj = beta Phi_t^T Phi_t + diag(alpha_{c_tj})
+    (Eq. (lin-sys)), differentiable in B, alpha and Phi.
+
+    Backward (A is symmetric, so the adjoint system uses the same solver): Lam = A^-1 dL/dX,
+    dL/dB = Lam, dL/dalpha and dL/dPhi from cmtcs_grad.  ``phi`` must be the tensor the model
+    was built on (the library reads it in place); it is an argument only so that autograd
+    routes its gradient."""
+
+    @staticmethod
+    def forward(ctx, B, alpha, phi, model, col_cluster, tol, max_iters):
+        if phi.data_ptr() != model.phi.data_ptr():
+            raise ValueError("phi must be the tensor the model was built on")
+        X = model.solve(alpha.detach(), B.detach().contiguous(), col_cluster, tol=tol,
+                        max_iters=max_iters)["X"]
+        ctx.model, ctx.cc, ctx.tol, ctx.max_iters = model, col_cluster, tol, max_iters
+        ctx.save_for_backward(alpha, X)
+        return X
+
+    @staticmethod
+    def backward(ctx, gX):
+        alpha, X = ctx.saved_tensors
+        m = ctx.model
+        Lam = m.solve(alpha.detach(), gX.contiguous(), ctx.cc, tol=ctx.tol,
+                      max_iters=ctx.max_iters)["X"]
+        dalpha, dphi = m.grad(X, Lam, ctx.cc, y_coef=0.0)
+        return Lam, dalpha, dphi, None, None, None, None
+
+
+class PosteriorMean(torch.autograd.Function):
+    """mu_t = A_{t, c_t}(alpha, Phi_t)^-1 (beta Phi_t^T y_t): the posterior mean of task t under
+    cluster c_t (Eq. (estep)), differentiable in alpha and Phi (the right-hand side depends on
+    Phi too, hence y_coef = 1 in the gradient)."""
+
+    @staticmethod
+    def forward(ctx, alpha, phi, model, cluster, tol, max_iters):
+        if phi.data_ptr() != model.phi.data_ptr():
+            raise ValueError("phi must be the tensor the model was built on")
+        cc = np.asarray(cluster, dtype=np.int32).reshape(model.T, 1)
+        B = model.rhs().unsqueeze(1).contiguous()
+        X = model.solve(alpha.detach(), B, cc, tol=tol, max_iters=max_iters)["X"]
+        ctx.model, ctx.cc, ctx.tol, ctx.max_iters = model, cc, tol, max_iters
+        ctx.save_for_backward(alpha, X)
+        return X[:, 0, :]
+
+    @staticmethod
+    def backward(ctx, gmu):
+        alpha, X = ctx.saved_tensors
+        m = ctx.model
+        Lam = m.solve(alpha.detach(), gmu.unsqueeze(1).contiguous(), ctx.cc, tol=ctx.tol,
+                      max_iters=ctx.max_iters)["X"]
+        dalpha, dphi = m.grad(X, Lam, ctx.cc, y_coef=1.0)
+        return dalpha, dphi, None, None, None, None

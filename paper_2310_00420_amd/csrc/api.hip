@@ -196,7 +196,7 @@ struct cmtcs_handle_s {
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(R, Rp);
-    HIP_TRY(launch_fill_colc(colc, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
+    HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.key = 0; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, 0.0, 0, st), "launch(cg_init)");
@@ -212,6 +212,22 @@ struct cmtcs_handle_s {
   }
 
   template <typename VT>
+  cmtcs_status_t grad(int R, const int32_t* col_cluster, const void* Xs, const void* Lam,
+                      double y_coef, float* dalpha, float* dphi) {
+    const int Rp = round16(2 * R);
+    cmtcs_status_t rs = prepare(Rp);
+    if (rs != CMTCS_OK) return rs;
+    const Geometry g = geom(2 * R, Rp);
+    HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
+    HIP_TRY(launch_pack2<VT>(geom(R, Rp), Xs, Lam, Dv, st), "launch(pack2)");
+    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr, st),
+            "launch(phi_v)");
+    HIP_TRY(launch_grads<VT>(g, R, (const VT*)Dv, (const VT*)W, y, colc, beta, y_coef, dalpha,
+                             dphi, row_off[T], st), "launch(grads)");
+    return CMTCS_OK;
+  }
+
+  template <typename VT>
   cmtcs_status_t estep(const float* alpha, const double* log_pi, const cmtcs_opts_t& o,
                        float* mu, float* sd, double* logdet, double* ell, double* q,
                        cmtcs_cg_stats_t* stats) {
@@ -222,7 +238,7 @@ struct cmtcs_handle_s {
     const uint64_t key = probe_key(o.seed, o.em_iter);
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
-    HIP_TRY(launch_fill_colc(colc, R, Rp, K, nullptr, st), "launch(fill_colc)");
+    HIP_TRY(launch_fill_colc(colc, T, R, Rp, K, nullptr, st), "launch(fill_colc)");
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.key = key; src.probes = o.probes;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
@@ -258,7 +274,7 @@ struct cmtcs_handle_s {
     const Geometry g = geom(R, Rp);
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
-    HIP_TRY(launch_fill_colc(colc, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
+    HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.key = 0; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
@@ -368,7 +384,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->gam, sizeof(double) * it * T * Rpm);
   A(&h->xi, sizeof(double) * it * T * Rpm);
   A(&h->act, sizeof(int) * (it + 1) * T);
-  A(&h->colc, sizeof(int) * Rpm);
+  A(&h->colc, sizeof(int) * T * (Rpm + (size_t)h->max_rhs));   // [T][Rp] + map staging
   A(&h->fwd_tiles, sizeof(int4) * fwd_max);
   A(&h->adj_tiles, sizeof(int4) * adj_max);
   A(&h->dg, sizeof(double) * it * P);
@@ -444,12 +460,35 @@ cmtcs_status_t cmtcs_solve(cmtcs_handle_t h, const float* alpha, int32_t R_per_t
     return fail(CMTCS_E_INVALID, "R_per_task must be in 1..max_rhs");
   if (!alpha || !col_cluster || !B || !X)
     return fail(CMTCS_E_INVALID, "a required array argument is NULL");
-  for (int j = 0; j < R_per_task; ++j)
-    if (col_cluster[j] < 0 || col_cluster[j] >= h->C)
+  for (int64_t i = 0; i < (int64_t)h->T * R_per_task; ++i)
+    if (col_cluster[i] < 0 || col_cluster[i] >= h->C)
       return fail(CMTCS_E_INVALID, "col_cluster entries must be in 0..C-1");
   if (h->math == CMTCS_MATH_F64)
     return h->solve<double>(alpha, R_per_task, col_cluster, B, X, gamma, xi, *opts, stats);
   return h->solve<float>(alpha, R_per_task, col_cluster, B, X, gamma, xi, *opts, stats);
+}
+
+cmtcs_status_t cmtcs_rhs(cmtcs_handle_t h, void* b) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  if (b == nullptr) return fail(CMTCS_E_INVALID, "b is NULL");
+  HIP_TRY(hipMemcpyAsync(b, h->b, h->vbytes * h->T * h->D, hipMemcpyDeviceToDevice, h->st),
+          "hipMemcpyAsync(rhs)");
+  return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_grad(cmtcs_handle_t h, int32_t R_per_task, const int32_t* col_cluster,
+                          const void* X, const void* Lam, double y_coef, float* dalpha,
+                          float* dphi) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  if (R_per_task < 1 || 2 * (int64_t)R_per_task > h->max_rhs)
+    return fail(CMTCS_E_INVALID, "R_per_task must be in 1..max_rhs/2");
+  if (!col_cluster || !X || !Lam) return fail(CMTCS_E_INVALID, "a required argument is NULL");
+  for (int64_t i = 0; i < (int64_t)h->T * R_per_task; ++i)
+    if (col_cluster[i] < 0 || col_cluster[i] >= h->C)
+      return fail(CMTCS_E_INVALID, "col_cluster entries must be in 0..C-1");
+  if (h->math == CMTCS_MATH_F64)
+    return h->grad<double>(R_per_task, col_cluster, X, Lam, y_coef, dalpha, dphi);
+  return h->grad<float>(R_per_task, col_cluster, X, Lam, y_coef, dalpha, dphi);
 }
 
 cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,
@@ -459,8 +498,8 @@ cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_t
     return fail(CMTCS_E_INVALID, "R_per_task must be in 1..max_rhs");
   if (!alpha || !col_cluster || !V || !AV)
     return fail(CMTCS_E_INVALID, "a required array argument is NULL");
-  for (int j = 0; j < R_per_task; ++j)
-    if (col_cluster[j] < 0 || col_cluster[j] >= h->C)
+  for (int64_t i = 0; i < (int64_t)h->T * R_per_task; ++i)
+    if (col_cluster[i] < 0 || col_cluster[i] >= h->C)
       return fail(CMTCS_E_INVALID, "col_cluster entries must be in 0..C-1");
   if (h->math == CMTCS_MATH_F64) return h->apply<double>(alpha, R_per_task, col_cluster, V, AV);
   return h->apply<float>(alpha, R_per_task, col_cluster, V, AV);

@@ -150,8 +150,17 @@ template <typename VT>
 hipError_t launch_solve_output(const Geometry& g, const CgState& s, void* X, double* gam_out,
                                double* xi_out, int steps, int* iters_out, uint8_t* status_out,
                                hipStream_t st);
-hipError_t launch_fill_colc(int* colc, int R, int Rp, int K, const int32_t* host_map,
+// colc: [T][Rp] cluster of every column slot (-1 for padding).  host_map: [T][R] or null
+// (then slot j of every task belongs to cluster j / (K+1)).
+hipError_t launch_fill_colc(int* colc, int T, int R, int Rp, int K, const int32_t* host_map,
                             hipStream_t st);
+template <typename VT>
+hipError_t launch_pack2(const Geometry& g, const void* X, const void* Lam, void* Dv,
+                        hipStream_t st);
+template <typename VT>
+hipError_t launch_grads(const Geometry& g, int R, const VT* XL, const VT* W, const float* y,
+                        const int* colc, double beta, double y_coef, float* dalpha,
+                        float* dphi, int64_t rows, hipStream_t st);
 hipError_t launch_zero_i32(int* p, long n, hipStream_t st);
 hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iters_out,
                               uint8_t* status_out, hipStream_t st);

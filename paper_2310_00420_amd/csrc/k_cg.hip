@@ -214,12 +214,79 @@ __global__ __launch_bounds__(256) void k_stats_out(const int* __restrict__ iters
   if (sout != nullptr) sout[i] = state[idx];
 }
 
-__global__ __launch_bounds__(256) void k_fill_colc(int* __restrict__ colc, int R, int Rp, int K,
-                                                   int from_map) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= Rp) return;
-  if (j >= R) colc[j] = -1;
-  else if (!from_map) colc[j] = j / (K + 1);
+__global__ __launch_bounds__(256) void k_fill_colc(int* __restrict__ colc,
+                                                   const int* __restrict__ map, int T, int R,
+                                                   int Rp, int K) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long)T * Rp) return;
+  const int t = (int)(i / Rp), j = (int)(i % Rp);
+  if (j >= R) colc[i] = -1;
+  else if (map != nullptr) colc[i] = map[(long)t * R + j];
+  else colc[i] = j / (K + 1);
+}
+
+// Slots j < R of task t receive X[t][j], slots R <= j < 2R receive Lam[t][j-R], the rest 0.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_pack2(const VT* __restrict__ X,
+                                               const VT* __restrict__ Lam, VT* __restrict__ Dv,
+                                               int R, int Rp, int D) {
+  const int col = blockIdx.x;
+  const int t = col / Rp, j = col % Rp;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  VT v = 0;
+  if (j < R) v = X[((int64_t)t * R + j) * D + d];
+  else if (j < 2 * R) v = Lam[((int64_t)t * R + (j - R)) * D + d];
+  Dv[(int64_t)col * D + d] = v;
+}
+
+// dphi[n][d] for the rows n of task t, from W = Phi_t [X | Lam] (slots j and R + j).
+template <typename VT>
+__global__ __launch_bounds__(256) void k_dphi(const VT* __restrict__ XL, const VT* __restrict__ W,
+                                              const int64_t* __restrict__ row_off,
+                                              const int64_t* __restrict__ w_off,
+                                              const float* __restrict__ y, double beta,
+                                              double y_coef, float* __restrict__ dphi, int T,
+                                              int R, int Rp, int D) {
+  const int64_t n = blockIdx.x;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  int lo = 0, hi = T;             // task of row n: row_off[t] <= n < row_off[t+1]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (row_off[mid] <= n) lo = mid; else hi = mid;
+  }
+  const int t = lo;
+  const int64_t nl = n - row_off[t];
+  const int64_t np = (w_off[t + 1] - w_off[t]) / Rp;
+  const VT* Wt = W + w_off[t];
+  double acc = 0.0, ls = 0.0;
+  for (int j = 0; j < R; ++j) {
+    const double x = (double)XL[((int64_t)t * Rp + j) * D + d];
+    const double l = (double)XL[((int64_t)t * Rp + R + j) * D + d];
+    const double wx = (double)Wt[(int64_t)j * np + nl];
+    const double wl = (double)Wt[(int64_t)(R + j) * np + nl];
+    acc += wl * x + wx * l;
+    ls += l;
+  }
+  dphi[n * D + d] = (float)(-beta * acc + y_coef * beta * (double)y[n] * ls);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void k_dalpha(const VT* __restrict__ XL,
+                                                const int* __restrict__ colc,
+                                                float* __restrict__ dalpha, int T, int R, int Rp,
+                                                int D) {
+  const int c = blockIdx.y;
+  const int d = blockIdx.x * 256 + threadIdx.x;
+  if (d >= D) return;
+  double acc = 0.0;
+  for (int t = 0; t < T; ++t)
+    for (int j = 0; j < R; ++j)
+      if (colc[(int64_t)t * Rp + j] == c)
+        acc -= (double)XL[((int64_t)t * Rp + R + j) * D + d] *
+               (double)XL[((int64_t)t * Rp + j) * D + d];
+  dalpha[(int64_t)c * D + d] = (float)acc;
 }
 
 __global__ __launch_bounds__(256) void k_zero_i32(int* __restrict__ p, long n) {
@@ -317,15 +384,46 @@ hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iter
   return hipGetLastError();
 }
 
-hipError_t launch_fill_colc(int* colc, int R, int Rp, int K, const int32_t* host_map,
+hipError_t launch_fill_colc(int* colc, int T, int R, int Rp, int K, const int32_t* host_map,
                             hipStream_t st) {
+  int* map = nullptr;
   if (host_map != nullptr) {
-    hipError_t e = hipMemcpyAsync(colc, host_map, sizeof(int32_t) * R, hipMemcpyHostToDevice, st);
+    // the map is staged in the tail of colc ([T][Rp] slots hold at least [T][R] values)
+    map = colc + (int64_t)T * Rp;
+    hipError_t e = hipMemcpyAsync(map, host_map, sizeof(int32_t) * T * R, hipMemcpyHostToDevice,
+                                  st);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_fill_colc, dim3((Rp + 255) / 256), dim3(256), 0, st, colc, R, Rp, K,
-                     host_map != nullptr ? 1 : 0);
+  const long n = (long)T * Rp;
+  hipLaunchKernelGGL(k_fill_colc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, colc,
+                     map, T, R, Rp, K);
   return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_pack2(const Geometry& g, const void* X, const void* Lam, void* Dv,
+                        hipStream_t st) {
+  hipLaunchKernelGGL((k_pack2<VT>), dim3(g.T * g.Rp, (g.D + 255) / 256), dim3(256), 0, st,
+                     (const VT*)X, (const VT*)Lam, (VT*)Dv, g.R, g.Rp, g.D);
+  return hipGetLastError();
+}
+
+template <typename VT>
+hipError_t launch_grads(const Geometry& g, int R, const VT* XL, const VT* W, const float* y,
+                        const int* colc, double beta, double y_coef, float* dalpha,
+                        float* dphi, int64_t rows, hipStream_t st) {
+  if (dphi != nullptr && rows > 0) {
+    hipLaunchKernelGGL((k_dphi<VT>), dim3((unsigned)rows, (g.D + 255) / 256), dim3(256), 0, st,
+                       XL, W, g.row_off, g.w_off, y, beta, y_coef, dphi, g.T, R, g.Rp, g.D);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (dalpha != nullptr) {
+    hipLaunchKernelGGL((k_dalpha<VT>), dim3((g.D + 255) / 256, g.C), dim3(256), 0, st, XL, colc,
+                       dalpha, g.T, R, g.Rp, g.D);
+    return hipGetLastError();
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_zero_i32(int* p, long n, hipStream_t st) {
@@ -334,6 +432,16 @@ hipError_t launch_zero_i32(int* p, long n, hipStream_t st) {
   return hipGetLastError();
 }
 
+template hipError_t launch_pack2<double>(const Geometry&, const void*, const void*, void*,
+                                         hipStream_t);
+template hipError_t launch_pack2<float>(const Geometry&, const void*, const void*, void*,
+                                        hipStream_t);
+template hipError_t launch_grads<double>(const Geometry&, int, const double*, const double*,
+                                         const float*, const int*, double, double, float*,
+                                         float*, int64_t, hipStream_t);
+template hipError_t launch_grads<float>(const Geometry&, int, const float*, const float*,
+                                        const float*, const int*, double, double, float*,
+                                        float*, int64_t, hipStream_t);
 template hipError_t launch_cg_init<double>(const Geometry&, const CgState&, const RhsSource&,
                                            double, int, hipStream_t);
 template hipError_t launch_cg_init<float>(const Geometry&, const CgState&, const RhsSource&,

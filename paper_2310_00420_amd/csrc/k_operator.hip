@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
   for (int cf = 0; cf < kColGroup; ++cf) {
     if (cf >= ncf) continue;
     const int j = (cf0 + cf) * 16 + i16;
-    const int c = colc[j];
+    const int c = colc[(int64_t)t * Rp + j];
     const int64_t col = ((int64_t)t * Rp + j) * D;
     const float* al = alpha + (int64_t)(c >= 0 ? c : 0) * D;
 #pragma unroll
