@@ -113,12 +113,15 @@ def main():
     prof = m.profile(False)
     rhs_iters = int(sum(int(i.sum().item()) for i in iters))
     max_steps = int(max(int(i.max().item()) for i in iters))
+    # RHS-iterations weighted by the rows of their task (ragged N_t)
+    ns = np.diff(w.row_off).astype(np.float64)
+    row_iters = float(sum((i.double().sum(dim=1).cpu().numpy() * ns).sum() for i in iters))
 
-    # roofline of the dominant kernel: algorithmic flops = 2 N D per RHS-iteration per product
+    # roofline of the dominant kernel: algorithmic flops = 2 N_t D per RHS-iteration per product
     N = rows // cfg.T
     name = max(("phi_v", "phit_w"), key=lambda k: prof[k][0])
     tot_ms, launches = prof[name]
-    flops = 2.0 * N * cfg.D * rhs_iters
+    flops = 2.0 * cfg.D * row_iters
     achieved = flops / (tot_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[a.math]
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -133,10 +136,11 @@ def main():
         "data": "synthetic: Phi_t iid N(0,1/N) stored fp32, %d true clusters with %d-sparse "
                 "shared supports, sigma %g, seeds data %d / init %d / probes 1"
                 % (cfg.groups, cfg.sparsity, cfg.sigma, synth.DATA_SEED, synth.INIT_SEED),
-        "config": {"workload": "CoFEM EM iteration (E-step + M-step), T=%d C=%d D=%d N=%d K=%d, "
-                               "CG tol %g, <=%d steps" % (cfg.T, cfg.C, cfg.D, N, cfg.K, cfg.tol,
-                                                          cfg.max_iters),
-                   "T": cfg.T, "C": cfg.C, "D": cfg.D, "N": N, "K": cfg.K, "math": a.math},
+        "config": {"workload": "CoFEM EM iteration (E-step + M-step), T=%d C=%d D=%d N=%s K=%d, "
+                               "CG tol %g, <=%d steps" % (cfg.T, cfg.C, cfg.D, cfg.N, cfg.K,
+                                                          cfg.tol, cfg.max_iters),
+                   "T": cfg.T, "C": cfg.C, "D": cfg.D, "N": cfg.N, "rows": rows, "K": cfg.K,
+                   "math": a.math},
         "roofline": roof,
         "detail": {"rhs_iters_per_em_iter": rhs_iters / a.steps, "max_cg_steps": max_steps,
                    "kernel_ms_per_em_iter": {k: round(v[0] / a.steps, 3)

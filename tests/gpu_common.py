@@ -41,24 +41,34 @@ def rel_max(a, b):
     return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), 1e-300)))
 
 
+def estep_errors(got, ref):
+    """Per-(t, c) errors of one E-step result against another (both as numpy dicts with the
+    oracle's keys mu, s, nu, ell, q): relative vector norms for mu and s, relative values for
+    nu, and for ell relative to max(|ell|, |nu|) (ell itself can be ~0, e.g. for a task without
+    measurements, where nu = -sum log alpha exactly)."""
+    def cols(a, b):
+        a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+        return np.linalg.norm(a - b, axis=-1) / np.maximum(np.linalg.norm(b, axis=-1), 1e-300)
+    ell_scale = np.maximum(np.abs(ref["ell"]), np.abs(ref["nu"]))
+    return dict(mu=cols(got["mu"], ref["mu"]), s=cols(got["s"], ref["s"]),
+                logdet=np.abs(got["nu"] - ref["nu"]) / np.abs(ref["nu"]),
+                ell=np.abs(got["ell"] - ref["ell"]) / ell_scale)
+
+
 def compare_estep(gpu, ref, tasks):
-    """Error metrics of a device E-step against the oracle's on the same tasks."""
+    """Error metrics of a device E-step against the oracle's on the same tasks: per-(t, c)
+    arrays under "per", their maxima, and the argmax agreement of q."""
     g = {k: v.cpu().numpy() for k, v in gpu.items()}
     t = np.asarray(tasks)
-    # ell is a sum of terms of size |nu|; relative to that scale (ell itself can be ~0, e.g.
-    # for a task without measurements, where nu = -sum log alpha exactly)
-    ell_scale = np.maximum(np.abs(ref["ell"]), np.abs(ref["nu"]))
+    got = dict(mu=g["mu"][t], s=g["s"][t], nu=g["logdet"][t], ell=g["ell"][t])
+    per = estep_errors(got, ref)
     # argmax of q is unique only where the top two z = ell/2 + log pi are apart
     z = 0.5 * ref["ell"]
     zs = np.sort(z, axis=1)
     gap = zs[:, -1] - zs[:, -2] if z.shape[1] > 1 else np.full(len(z), np.inf)
     decided = gap > 1e-6 * np.max(np.abs(ref["nu"]), axis=1)
-    return dict(
-        mu=rel_cols(g["mu"][t], ref["mu"]),
-        s=rel_cols(g["s"][t], ref["s"]),
-        logdet=rel_max(g["logdet"][t], ref["nu"]),
-        ell=float(np.max(np.abs(g["ell"][t] - ref["ell"]) / ell_scale)),
-        q_abs=float(np.max(np.abs(g["q"][t] - ref["q"]))),
-        argmax_equal=bool(np.all((g["q"][t].argmax(1) == ref["q"].argmax(1))[decided])),
-        undecided_tasks=int((~decided).sum()),
-    )
+    out = {k: float(np.max(v)) for k, v in per.items()}
+    out.update(q_abs=float(np.max(np.abs(g["q"][t] - ref["q"]))),
+               argmax_equal=bool(np.all((g["q"][t].argmax(1) == ref["q"].argmax(1))[decided])),
+               undecided_tasks=int((~decided).sum()), per=per)
+    return out
