@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="prec")
-    ap.add_argument("--math", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--math", default="f64", choices=["f64", "f32", "mixed"])
+    ap.add_argument("--phi16", default="bf16", choices=["bf16", "f16"])
+    ap.add_argument("--refine-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tasks", type=int, default=4)
     return ap.parse_args()
@@ -89,10 +91,11 @@ def main():
     phi = torch.from_numpy(w.Phi).to(dev)
     y = torch.from_numpy(w.y).to(dev)
     m = Cmtcs(phi, w.row_off, y, w.beta, cfg.C, math=a.math, max_iters=cfg.max_iters,
-              max_K=cfg.K)
+              max_K=cfg.K, phi16=a.phi16)
     alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
     log_pi = torch.tensor(w.log_pi, device=dev)
-    kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1)
+    kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1,
+              refine_every=a.refine_every if a.math == "mixed" else 0)
 
     def em_iteration(it):
         out = m.estep(alpha, log_pi, cfg.K, em_iter=it, stats=True, **kw)
@@ -117,22 +120,40 @@ def main():
     ns = np.diff(w.row_off).astype(np.float64)
     row_iters = float(sum((i.double().sum(dim=1).cpu().numpy() * ns).sum() for i in iters))
 
-    # roofline of the dominant kernel: algorithmic flops = 2 N_t D per RHS-iteration per product
+    # roofline of the dominant kernel
     N = rows // cfg.T
     name = max(("phi_v", "phit_w"), key=lambda k: prof[k][0])
     tot_ms, launches = prof[name]
-    flops = 2.0 * cfg.D * row_iters
-    achieved = flops / (tot_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[a.math]
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None, "kernel": name,
-            "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
-            "flop_per_launch": flops / max(launches, 1)}
+    if a.math == "mixed":
+        # HBM-bound: algorithmic bytes = the 16-bit Phi stream plus one pass over the vectors,
+        # for every step each task is still active (task-steps = its longest column)
+        R = cfg.C * (cfg.K + 1)
+        task_steps = sum(i.max(dim=1).values.double().cpu().numpy() for i in iters)
+        if name == "phi_v":    # Phi16 N D, V16 R D, W16 R N (2-byte elements)
+            per_task = 2.0 * (ns * cfg.D + R * cfg.D + R * ns)
+        else:                  # PhiT16 D N, W16 R N, V and A V in FP32: 8 R D
+            per_task = 2.0 * (ns * cfg.D + R * ns) + 8.0 * R * cfg.D
+        nbytes = float((task_steps * per_task).sum())
+        achieved = nbytes / (tot_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_GBPS, 4), "traffic": None,
+                "kernel": name + "16", "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
+                "bytes_per_launch": nbytes / max(launches, 1)}
+    else:
+        # algorithmic flops = 2 N_t D per RHS-iteration per product
+        flops = 2.0 * cfg.D * row_iters
+        achieved = flops / (tot_ms * 1e-3) / 1e12
+        peak = PEAK_TFLOPS[a.math]
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": name, "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
+                "flop_per_launch": flops / max(launches, 1)}
     res = {
         "metric": "CG RHS-iters/sec + EM iter time, D=4096 T=64 C=4 K=32; MFMA/HBM roofline %",
         "value": rhs_iters / dt, "unit": "RHS-iters/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": a.math,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": a.math if a.math != "mixed" else a.phi16 + "+f32",
         "data": "synthetic: Phi_t iid N(0,1/N) stored fp32, %d true clusters with %d-sparse "
                 "shared supports, sigma %g, seeds data %d / init %d / probes 1"
                 % (cfg.groups, cfg.sparsity, cfg.sigma, synth.DATA_SEED, synth.INIT_SEED),
@@ -140,7 +161,8 @@ def main():
                                "CG tol %g, <=%d steps" % (cfg.T, cfg.C, cfg.D, cfg.N, cfg.K,
                                                           cfg.tol, cfg.max_iters),
                    "T": cfg.T, "C": cfg.C, "D": cfg.D, "N": cfg.N, "rows": rows, "K": cfg.K,
-                   "math": a.math},
+                   "math": a.math if a.math != "mixed" else
+                   "mixed(%s, true residual every %d)" % (a.phi16, a.refine_every)},
         "roofline": roof,
         "detail": {"rhs_iters_per_em_iter": rhs_iters / a.steps, "max_cg_steps": max_steps,
                    "kernel_ms_per_em_iter": {k: round(v[0] / a.steps, 3)

@@ -55,11 +55,12 @@ typedef enum { CMTCS_F32 = 0, CMTCS_BF16 = 1, CMTCS_F16 = 2 } cmtcs_dtype_t;
 /* Arithmetic of the operator products and of the CG vectors.
  *  CMTCS_MATH_F64: Phi products on FP64 matrix cores, CG vectors x, r, d, A d in FP64.
  *  CMTCS_MATH_F32: Phi products on FP32 matrix cores, CG vectors in FP32.
- *  CMTCS_MATH_MIXED: Phi stored in 16 bits (phi_dtype BF16/F16), the CG direction rounded to
- *                    the same 16-bit type, products on 16-bit matrix cores with FP32
- *                    accumulation; CG vectors in FP32; the recursive residual is replaced by
- *                    the true residual b - A x, computed with FP64 products from the FP32
- *                    copy of Phi, every refine_every steps and when a solve stops.
+ *  CMTCS_MATH_MIXED: the library keeps Phi in 16 bits (phi_dtype BF16 or F16: a rounded copy
+ *                    and a transposed rounded copy, built at create from the FP32 phi), rounds
+ *                    the CG direction to the same type, and runs both products on 16-bit matrix
+ *                    cores with FP32 accumulation; CG vectors are FP32.  Every refine_every
+ *                    steps the recursive residual is replaced by the true residual b - A x,
+ *                    computed with FP32 products from the FP32 phi.
  *  In every mode the CG scalars (r.r, d.Ad, gamma, xi), the tridiagonal eigenproblems, the
  *  log-determinants and the responsibilities are FP64. */
 typedef enum { CMTCS_MATH_F64 = 0, CMTCS_MATH_F32 = 1, CMTCS_MATH_MIXED = 2 } cmtcs_math_t;
@@ -71,18 +72,19 @@ enum {
   CMTCS_CG_BREAKDOWN = 2    /* d.Ad <= 0 or a non-finite scalar; the solve stopped before it */
 };
 
-/* Problem data: fixed for the lifetime of a handle.  The library reads phi, phi_f32 and y
- * in place (it does not copy them), so they must stay valid and unchanged until destroy. */
+/* Problem data: fixed for the lifetime of a handle.  The library reads phi and y in place (it
+ * does not copy them), so they must stay valid and unchanged until destroy. */
 typedef struct {
   int32_t T;                /* tasks, >= 1                                                  */
   int32_t C;                /* clusters, >= 1                                               */
-  int32_t D;                /* signal length, a positive multiple of 16, <= 16384           */
+  int32_t D;                /* signal length, a positive multiple of 16 (of 32 for
+                               MATH_MIXED), <= 16384                                        */
   const int64_t* row_off;   /* HOST, T+1 non-decreasing prefix sums of N_t, row_off[0] = 0;
                                N_t = 0 is allowed (then A_tc = diag(alpha_c))               */
-  const void* phi;          /* device [row_off[T]][D] in phi_dtype: the stacked Phi_t       */
-  cmtcs_dtype_t phi_dtype;  /* F32 for MATH_F64 / MATH_F32; BF16 or F16 for MATH_MIXED      */
-  const float* phi_f32;     /* device [row_off[T]][D] FP32 Phi; required by MATH_MIXED for
-                               the true residual, ignored otherwise                         */
+  const void* phi;          /* device [row_off[T]][D] float: the stacked Phi_t              */
+  cmtcs_dtype_t phi_dtype;  /* F32 for MATH_F64 / MATH_F32; for MATH_MIXED the 16-bit type
+                               (BF16 or F16) the library stores Phi in                      */
+  const float* phi_f32;     /* reserved, must be NULL                                       */
   const float* y;           /* device [row_off[T]] measurements, stacked like Phi           */
   double beta;              /* noise precision, > 0                                         */
   cmtcs_math_t math;        /* arithmetic, see cmtcs_math_t                                 */

@@ -44,11 +44,12 @@ class Cmtcs:
     """One problem {(Phi_t, y_t)}, beta, C on the current device (see include/cmtcs.h).
 
     phi: [sum N_t][D] float32 device tensor (stacked Phi_t); row_off: T+1 prefix sums of N_t
-    (host sequence); y: [sum N_t] float32 device tensor.
+    (host sequence); y: [sum N_t] float32 device tensor.  math: "f64", "f32" or "mixed"; with
+    "mixed" the library stores Phi in ``phi16`` ("bf16" or "f16").
     """
 
     def __init__(self, phi, row_off, y, beta, C, math="f64", max_rhs=None, max_iters=200,
-                 max_K=32):
+                 max_K=32, phi16="bf16"):
         lib = _lib.load()
         self.row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
         self.T = len(self.row_off) - 1
@@ -59,6 +60,9 @@ class Cmtcs:
         _need(y, torch.float32, (rows,), "y")
         self.math = math
         self.vdtype = torch.float64 if math == "f64" else torch.float32
+        dtype = _lib.CMTCS_F32
+        if math == "mixed":
+            dtype = {"bf16": _lib.CMTCS_BF16, "f16": _lib.CMTCS_F16}[phi16]
         self.phi, self.y = phi, y
         self.max_K = int(max_K)
         self.max_iters = int(max_iters)
@@ -67,7 +71,7 @@ class Cmtcs:
         self.device = phi.device
         self._roff = self.row_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         p = _lib.Problem(T=self.T, C=self.C, D=self.D, row_off=self._roff, phi=phi.data_ptr(),
-                         phi_dtype=_lib.CMTCS_F32, phi_f32=None, y=y.data_ptr(), beta=self.beta,
+                         phi_dtype=dtype, phi_f32=None, y=y.data_ptr(), beta=self.beta,
                          math=MATH[math], max_rhs=self.max_rhs, max_iters=self.max_iters,
                          max_K=self.max_K)
         h = ctypes.c_void_p()
@@ -100,7 +104,7 @@ class Cmtcs:
                          alpha_max=alpha_max)
 
     def estep(self, alpha, log_pi, K, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
-              em_iter=0, probes=None, stats=False):
+              em_iter=0, probes=None, stats=False, refine_every=0):
         """One E-step (Alg. 2 inner loop).  Returns a dict of device tensors."""
         self._check_stream()
         T, C, D, dev = self.T, self.C, self.D, self.device
@@ -122,7 +126,7 @@ class Cmtcs:
             st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(),
                               out["ritz_min"].data_ptr(), out["ritz_max"].data_ptr())
         o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
-                       em_iter=em_iter, probes=probes)
+                       em_iter=em_iter, probes=probes, refine_every=refine_every)
         _lib.check(_lib.load().cmtcs_estep(
             self._h, _ptr(alpha), _ptr(log_pi), ctypes.byref(o), _ptr(out["mu"]), _ptr(out["s"]),
             _ptr(out["logdet"]), _ptr(out["ell"]), _ptr(out["q"]),

@@ -67,6 +67,17 @@ struct cmtcs_handle_s {
   uint8_t* ok = nullptr;
   int* act_host = nullptr;   // pinned
 
+  // mixed precision (CMTCS_MATH_MIXED)
+  void* phi16 = nullptr;                 // 16-bit copy of Phi, [rows][D]
+  cmtcs_dtype_t phi_dtype = CMTCS_F32;
+  void* phiT16 = nullptr;                // [D][np32_t] per task
+  void* D16 = nullptr;                   // 16-bit copy of the CG direction
+  void* W16 = nullptr;                   // [Rp][np32_t] per task
+  int64_t* w16_off_d = nullptr;
+  int4* fwd16_tiles = nullptr;
+  int4* adj16_tiles = nullptr;
+  int nfwd16 = 0, nadj16 = 0, max_np32 = 0;
+
   // kernel timing (cmtcs_profile)
   bool prof_on = false;
   hipEvent_t ev[kCheckEvery][4] = {};
@@ -117,6 +128,14 @@ struct cmtcs_handle_s {
     return g;
   }
 
+  Geometry geom16(int R, int Rp) const {
+    Geometry g = geom(R, Rp);
+    g.w_off = w16_off_d;
+    return g;
+  }
+
+  bool mixed() const { return math == CMTCS_MATH_MIXED; }
+
   CgState cg() const {
     CgState s;
     s.X = X; s.Rv = Rv; s.Dv = Dv; s.AD = AD;
@@ -150,6 +169,28 @@ struct cmtcs_handle_s {
                              hipMemcpyHostToDevice, st), "hipMemcpyAsync(fwd tiles)");
     HIP_TRY(hipMemcpyAsync(adj_tiles, at.data(), sizeof(int4) * at.size(),
                            hipMemcpyHostToDevice, st), "hipMemcpyAsync(adj tiles)");
+    if (mixed()) {
+      std::vector<int64_t> w16(T + 1, 0);
+      std::vector<int4> f16, a16;
+      for (int t = 0; t < T; ++t) {
+        const int np = (int)((row_off[t + 1] - row_off[t] + 31) / 32 * 32);
+        w16[t + 1] = w16[t] + (int64_t)Rp * np;
+        for (int n0 = 0; n0 < np; n0 += kRows16)
+          for (int cg = 0; cg < ng; ++cg) f16.push_back(make_int4(t, n0, cg, 0));
+        for (int d0 = 0; d0 < D; d0 += kRows16)
+          for (int cg = 0; cg < ng; ++cg) a16.push_back(make_int4(t, d0, cg, 0));
+      }
+      HIP_TRY(hipMemcpyAsync(w16_off_d, w16.data(), sizeof(int64_t) * (T + 1),
+                             hipMemcpyHostToDevice, st), "hipMemcpyAsync(w16_off)");
+      if (!f16.empty())
+        HIP_TRY(hipMemcpyAsync(fwd16_tiles, f16.data(), sizeof(int4) * f16.size(),
+                               hipMemcpyHostToDevice, st), "hipMemcpyAsync(fwd16 tiles)");
+      HIP_TRY(hipMemcpyAsync(adj16_tiles, a16.data(), sizeof(int4) * a16.size(),
+                             hipMemcpyHostToDevice, st), "hipMemcpyAsync(adj16 tiles)");
+      HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(prepare16)");
+      nfwd16 = (int)f16.size();
+      nadj16 = (int)a16.size();
+    }
     HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(prepare)");
     nfwd = (int)ft.size();
     nadj = (int)at.size();
@@ -158,24 +199,65 @@ struct cmtcs_handle_s {
   }
 
   // Runs CG steps until every right-hand side has stopped or `steps` steps are done.
+  // 16-bit products of one step (MATH_MIXED); which = 1: Phi V16, 2: Phi^T W16 + alpha V.
+  hipError_t mixed_product(const Geometry& g16, const float* alpha, const int* act_u,
+                           int which) {
+    if (phi_dtype == CMTCS_BF16)
+      return launch_mixed_products<__bf16>(g16, phi16, phiT16, fwd16_tiles, nfwd16, adj16_tiles,
+                                           nadj16, D16, W16, (const float*)Dv, (float*)AD,
+                                           alpha, colc, beta, act_u, which, st);
+    return launch_mixed_products<_Float16>(g16, phi16, phiT16, fwd16_tiles, nfwd16, adj16_tiles,
+                                           nadj16, D16, W16, (const float*)Dv, (float*)AD,
+                                           alpha, colc, beta, act_u, which, st);
+  }
+
+  hipError_t round_direction(const Geometry& g) {
+    const int64_t n = (int64_t)T * g.Rp * D;
+    if (phi_dtype == CMTCS_BF16) return launch_round16<__bf16>((const float*)Dv, D16, n, st);
+    return launch_round16<_Float16>((const float*)Dv, D16, n, st);
+  }
+
   template <typename VT>
-  cmtcs_status_t run_cg(const Geometry& g, const float* alpha, int steps, int fixed) {
+  cmtcs_status_t run_cg(const Geometry& g, const float* alpha, int steps, int fixed,
+                        const RhsSource& src, int refine_every) {
     const CgState s = cg();
+    const Geometry g16 = geom16(g.R, g.Rp);
+    if (mixed()) HIP_TRY(round_direction(g), "launch(round16)");
     for (int u = 0; u < steps; ++u) {
       const int* act_u = act + (size_t)u * T;
       hipEvent_t* e4 = prof_on ? ev[ev_pending] : nullptr;
       if (e4) HIP_TRY(hipEventRecord(e4[0], st), "hipEventRecord");
-      HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, st),
-              "launch(phi_v)");
+      if (mixed())
+        HIP_TRY(mixed_product(g16, alpha, act_u, 1), "launch(phi_v16)");
+      else
+        HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, st),
+                "launch(phi_v)");
       if (e4) HIP_TRY(hipEventRecord(e4[1], st), "hipEventRecord");
-      HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
-                                alpha, colc, beta, act_u, st), "launch(phit_w)");
+      if (mixed())
+        HIP_TRY(mixed_product(g16, alpha, act_u, 2), "launch(phit_w16)");
+      else
+        HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
+                                  (VT*)AD, alpha, colc, beta, act_u, st), "launch(phit_w)");
       if (e4) HIP_TRY(hipEventRecord(e4[2], st), "hipEventRecord");
-      HIP_TRY(launch_cg_update<VT>(g, s, u, steps, fixed, st), "launch(cg_update)");
+      const bool replace = mixed() && refine_every > 0 && (u + 1) % refine_every == 0;
+      HIP_TRY(launch_cg_update<VT>(g, s, u, steps, fixed, replace ? 1 : 0, st),
+              "launch(cg_update)");
+      if (replace) {
+        // true-residual replacement: r = b - A x with FP32 products from the FP32 Phi, then
+        // xi, d and the stop decision from the replaced residual
+        HIP_TRY(launch_phi_v<float>(g, phi, fwd_tiles, nfwd, (const float*)X, (float*)W, act_u,
+                                    st), "launch(phi_v residual)");
+        HIP_TRY(launch_phit_w<float>(g, phi, adj_tiles, nadj, (const float*)W, (const float*)X,
+                                     (float*)AD, alpha, colc, beta, act_u, st),
+                "launch(phit_w residual)");
+        HIP_TRY(launch_replace(g, s, (const float*)AD, src, u, steps, fixed, st),
+                "launch(replace)");
+      }
       if (e4) {
         HIP_TRY(hipEventRecord(e4[3], st), "hipEventRecord");
         if (++ev_pending == kCheckEvery) HIP_TRY(harvest(), "profile events");
       }
+      if (mixed()) HIP_TRY(round_direction(g), "launch(round16)");
       if ((u + 1) % kCheckEvery == 0 && u + 1 < steps) {
         HIP_TRY(hipMemcpyAsync(act_host, act + (size_t)(u + 1) * T, sizeof(int) * T,
                                hipMemcpyDeviceToHost, st), "hipMemcpyAsync(active counts)");
@@ -242,7 +324,7 @@ struct cmtcs_handle_s {
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.key = key; src.probes = o.probes;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
-    rs = run_cg<VT>(g, alpha, steps, fixed);
+    rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key, o.probes, mu, sd, st),
             "launch(estep_finalize)");
@@ -278,7 +360,7 @@ struct cmtcs_handle_s {
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.key = 0; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
-    rs = run_cg<VT>(g, alpha, steps, fixed);
+    rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_solve_output<VT>(g, cg(), Xout, gout, xout, steps,
                                     stats ? stats->iters : nullptr,
@@ -335,12 +417,15 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   if (p->max_K < 0) return fail(CMTCS_E_INVALID, "max_K must be >= 0");
   if ((int64_t)p->C * (p->max_K + 1) > p->max_rhs && p->max_K > 0)
     return fail(CMTCS_E_INVALID, "max_rhs must be >= C*(max_K+1)");
-  if (p->math == CMTCS_MATH_MIXED)
-    return fail(CMTCS_E_UNSUPPORTED, "CMTCS_MATH_MIXED is not available in this build");
-  if (p->math != CMTCS_MATH_F64 && p->math != CMTCS_MATH_F32)
+  if (p->math != CMTCS_MATH_F64 && p->math != CMTCS_MATH_F32 && p->math != CMTCS_MATH_MIXED)
     return fail(CMTCS_E_INVALID, "unknown math mode");
-  if (p->phi_dtype != CMTCS_F32)
-    return fail(CMTCS_E_INVALID, "MATH_F64 and MATH_F32 take an F32 phi");
+  if (p->math == CMTCS_MATH_MIXED) {
+    if (p->phi_dtype != CMTCS_BF16 && p->phi_dtype != CMTCS_F16)
+      return fail(CMTCS_E_INVALID, "MATH_MIXED needs phi_dtype BF16 or F16");
+    if (p->D % 32 != 0) return fail(CMTCS_E_INVALID, "MATH_MIXED needs D a multiple of 32");
+  } else if (p->phi_dtype != CMTCS_F32) {
+    return fail(CMTCS_E_INVALID, "MATH_F64 and MATH_F32 take phi_dtype F32");
+  }
   for (int t = 0; t < p->T; ++t)
     if (p->row_off[t + 1] - p->row_off[t] > (1 << 30))
       return fail(CMTCS_E_INVALID, "N_t too large");
@@ -352,6 +437,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   h->Rp_max = round16(p->max_rhs);
   h->vbytes = p->math == CMTCS_MATH_F64 ? 8 : 4;
   h->row_off.assign(p->row_off, p->row_off + p->T + 1);
+  h->phi_dtype = p->phi_dtype;
   h->phi = (const float*)p->phi;
   h->y = p->y;
   h->st = (hipStream_t)stream;
@@ -395,6 +481,22 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->rmax, sizeof(double) * P);
   A(&h->ok, P);
   A(&h->slog, sizeof(double) * C);
+  if (h->math == CMTCS_MATH_MIXED) {
+    size_t np32_sum = 0, f16_max = 0;
+    for (size_t t = 0; t < T; ++t) {
+      const size_t np = (size_t)((h->row_off[t + 1] - h->row_off[t] + 31) / 32 * 32);
+      np32_sum += np;
+      h->max_np32 = std::max(h->max_np32, (int)np);
+      f16_max += (np + kRows16 - 1) / kRows16 * ngm;
+    }
+    A(&h->phi16, 2 * D * (size_t)rows);
+    A(&h->phiT16, 2 * D * np32_sum);
+    A(&h->D16, 2 * T * Rpm * D);
+    A(&h->W16, 2 * Rpm * np32_sum);
+    A(&h->w16_off_d, sizeof(int64_t) * (T + 1));
+    A(&h->fwd16_tiles, sizeof(int4) * f16_max);
+    A(&h->adj16_tiles, sizeof(int4) * T * ((D + kRows16 - 1) / kRows16) * ngm);
+  }
   if (e == hipSuccess) e = hipHostMalloc((void**)&h->act_host, sizeof(int) * T);
   if (e != hipSuccess) {
     delete h;
@@ -412,6 +514,30 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   if (e != hipSuccess) {
     delete h;
     return hip_fail(e, "cmtcs_create");
+  }
+  if (h->math == CMTCS_MATH_MIXED) {
+    // 16-bit tables and offsets, then the transposed 16-bit copy of Phi
+    cmtcs_status_t rs = h->prepare(h->Rp_max);
+    if (rs != CMTCS_OK) {
+      delete h;
+      return rs;
+    }
+    const Geometry g16 = h->geom16(1, h->Rp_max);
+    const int64_t n = (int64_t)rows * h->D;
+    if (h->phi_dtype == CMTCS_BF16) {
+      e = launch_round16<__bf16>(h->phi, h->phi16, n, h->st);
+      if (e == hipSuccess)
+        e = launch_transpose16<__bf16>(g16, h->phi16, h->phiT16, h->max_np32, h->st);
+    } else {
+      e = launch_round16<_Float16>(h->phi, h->phi16, n, h->st);
+      if (e == hipSuccess)
+        e = launch_transpose16<_Float16>(g16, h->phi16, h->phiT16, h->max_np32, h->st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+    if (e != hipSuccess) {
+      delete h;
+      return hip_fail(e, "cmtcs_create (transpose)");
+    }
   }
   *out = h;
   return CMTCS_OK;

@@ -140,9 +140,11 @@ struct RhsSource {
 template <typename VT>
 hipError_t launch_cg_init(const Geometry& g, const CgState& s, const RhsSource& src,
                           double tol, int max_steps, hipStream_t st);
+// split = 1: first half of a residual-replacement step (x and recursive r, gamma recorded);
+// launch_replace completes it.
 template <typename VT>
 hipError_t launch_cg_update(const Geometry& g, const CgState& s, int u, int steps, int fixed,
-                            hipStream_t st);
+                            int split, hipStream_t st);
 template <typename VT>
 hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, uint64_t key,
                                  const int8_t* probes, float* mu, float* sdiag, hipStream_t st);
@@ -169,6 +171,25 @@ hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iter
 hipError_t launch_slq(const Geometry& g, const CgState& s, int K, double pnorm2, double* dg,
                       double* of, double* zz, double* tau, uint8_t* ok, double* rmin,
                       double* rmax, hipStream_t st);
+
+// Launchers (k_mixed.hip).  g16.w_off holds the offsets of the 16-bit W (rows padded to 32).
+// which: 1 = the Phi V16 product only, 2 = the Phi^T W16 product only.
+template <typename T16>
+hipError_t launch_mixed_products(const Geometry& g16, const void* phi16, const void* phiT16,
+                                 const int4* fwd, int nfwd, const int4* adj, int nadj,
+                                 const void* V16, void* W16, const float* V, float* AV,
+                                 const float* alpha, const int* colc, double beta,
+                                 const int* act, int which, hipStream_t st);
+template <typename T16>
+hipError_t launch_transpose16(const Geometry& g16, const void* phi16, void* phiT16, int max_np,
+                              hipStream_t st);
+template <typename T16>
+hipError_t launch_round16(const float* x, void* y, int64_t n, hipStream_t st);
+// Second half of a residual-replacement step u: r = src - A x (A x in AX), then r.r, xi,
+// d = r + xi d and the stop decision of the step, as in the unsplit update.
+hipError_t launch_replace(const Geometry& g, const CgState& s, const float* AX,
+                          const RhsSource& src, int u, int steps, int fixed, hipStream_t st);
+constexpr int kRows16 = 64;   // output rows per wave tile of the 16-bit products
 
 // Launchers (k_em.hip).
 template <typename VT>

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
                                                   double* __restrict__ gam,
                                                   double* __restrict__ xi, int* __restrict__ act,
                                                   int u, int steps, int fixed, int T, int R,
-                                                  int Rp, int D) {
+                                                  int Rp, int D, int split) {
   __shared__ double sh[BS / 64];
   const int t = blockIdx.x / R, j = blockIdx.x % R;
   const int64_t idx = (int64_t)t * Rp + j;
@@ -121,6 +121,17 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
     } else {
       rv[e] = 0;
     }
+  }
+  if (split) {
+    // first half of a residual-replacement step: x and the recursive r only; the true
+    // residual, xi, d and the stop decision follow in k_replace
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int d = threadIdx.x + e * BS;
+      if (d < D) Rv[base + d] = rv[e];
+    }
+    if (threadIdx.x == 0) gam[(int64_t)u * T * Rp + idx] = g;
+    return;
   }
   const double rrn = block_sum<BS>(pr, sh);
   const double x_ = rrn / rr_old;
@@ -309,10 +320,10 @@ static hipError_t init_one(const Geometry& g, const CgState& s, const RhsSource&
 
 template <typename VT, int BS, int EPT>
 static hipError_t update_one(const Geometry& g, const CgState& s, int u, int steps, int fixed,
-                             hipStream_t st) {
+                             int split, hipStream_t st) {
   hipLaunchKernelGGL((k_cg_update<VT, BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, (VT*)s.X,
                      (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state, s.iters,
-                     s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D);
+                     s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split);
   return hipGetLastError();
 }
 
@@ -339,8 +350,8 @@ hipError_t launch_cg_init(const Geometry& g, const CgState& s, const RhsSource& 
 
 template <typename VT>
 hipError_t launch_cg_update(const Geometry& g, const CgState& s, int u, int steps, int fixed,
-                            hipStream_t st) {
-  CMTCS_DISPATCH_D(update_one, g, s, u, steps, fixed, st);
+                            int split, hipStream_t st) {
+  CMTCS_DISPATCH_D(update_one, g, s, u, steps, fixed, split, st);
 }
 
 template <typename VT>
@@ -447,8 +458,8 @@ template hipError_t launch_cg_init<double>(const Geometry&, const CgState&, cons
 template hipError_t launch_cg_init<float>(const Geometry&, const CgState&, const RhsSource&,
                                           double, int, hipStream_t);
 template hipError_t launch_cg_update<double>(const Geometry&, const CgState&, int, int, int,
-                                             hipStream_t);
-template hipError_t launch_cg_update<float>(const Geometry&, const CgState&, int, int, int,
+                                             int, hipStream_t);
+template hipError_t launch_cg_update<float>(const Geometry&, const CgState&, int, int, int, int,
                                             hipStream_t);
 template hipError_t launch_estep_finalize<double>(const Geometry&, const CgState&, int, uint64_t,
                                                   const int8_t*, float*, float*, hipStream_t);

@@ -1,0 +1,359 @@
+// Mixed-precision operator (CMTCS_MATH_MIXED): Phi stored in 16 bits (bf16 or fp16), the CG
+// direction rounded to the same type, products on the 16x16x32 matrix cores with FP32
+// accumulation (the brief's precision form; the method itself is Alg. 1 on the operator of
+// Eq. (lin-sys)).
+//
+// Both products are laid out so that the contraction index is contiguous in memory for both
+// operands (one 16-byte load gives a lane its 8 consecutive k values):
+//   fwd:  W16_t = round16(Phi16_t V16_t)       M = Phi16_t   [N_t][D]   (caller layout), K = D
+//   adj:  AV_t  = beta PhiT16_t W16_t + alpha (.) V_t
+//                                              M = PhiT16_t  [D][np_t] (built once at create,
+//                                              a transposed copy: HBM is plentiful, and the
+//                                              16-bit path is bound by streaming Phi)
+// np_t = N_t rounded up to 32; W16_t is [Rp][np_t] with zero rows beyond N_t.
+// The true residual b - A x that replaces the recursive residual every m steps is computed by
+// the FP32 kernels of k_operator.hip from the FP32 copy of Phi.
+#include "internal.h"
+#include "../../include/cmtcs.h"
+
+namespace cmtcs {
+
+template <typename T16> struct Mfma16;
+template <> struct Mfma16<__bf16> {
+  typedef __bf16 v8 __attribute__((ext_vector_type(8)));
+  __device__ static inline f4 mma(v8 a, v8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<_Float16> {
+  typedef _Float16 v8 __attribute__((ext_vector_type(8)));
+  __device__ static inline f4 mma(v8 a, v8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ inline int xcd_block16(int b, int nb) {
+  const int q = nb >> 3, rem = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, rem) + i;
+}
+
+constexpr int kRF16 = kRows16 / 16;   // 64 output rows per wave tile
+
+// Shared main loop: acc[rf][cf] += M[rows of rf][k] * V[cols of cf][k] over k in [0, K), K a
+// multiple of 32.  mrow[rf] points at row (tile row rf*16 + i16) + 8*g4 (null: zero row);
+// vcol points at column (cf0*16 + i16) + 8*g4, columns vld elements apart.
+template <typename T16>
+__device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* const (&mrow)[kRF16],
+                                     const T16* vcol, int64_t vld, int ncf, int K) {
+  typedef typename Mfma16<T16>::v8 v8;
+  v8 a0[kRF16], a1[kRF16], b0[kColGroup], b1[kColGroup];
+  auto load = [&](v8 (&a)[kRF16], v8 (&b)[kColGroup], int k0) {
+#pragma unroll
+    for (int rf = 0; rf < kRF16; ++rf)
+      a[rf] = mrow[rf] != nullptr ? *(const v8*)(mrow[rf] + k0) : v8{};
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (cf < ncf) b[cf] = *(const v8*)(vcol + (int64_t)cf * 16 * vld + k0);
+  };
+  auto mma = [&](const v8 (&a)[kRF16], const v8 (&b)[kColGroup]) {
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (cf < ncf)
+#pragma unroll
+        for (int rf = 0; rf < kRF16; ++rf) acc[rf][cf] = Mfma16<T16>::mma(a[rf], b[cf], acc[rf][cf]);
+  };
+  if (K > 0) load(a0, b0, 0);
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    if (k0 + 32 < K) load(a1, b1, k0 + 32);
+    mma(a0, b0);
+    if (k0 + 64 < K) load(a0, b0, k0 + 64);
+    if (k0 + 32 < K) mma(a1, b1);
+  }
+}
+
+// W16_t = round16(Phi16_t V16_t): tile {t, n0, column group}.
+template <typename T16>
+__global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
+                                                 const int64_t* __restrict__ row_off,
+                                                 const int64_t* __restrict__ w16_off,
+                                                 const int4* __restrict__ tiles, int ntiles,
+                                                 const T16* __restrict__ V16,
+                                                 T16* __restrict__ W16,
+                                                 const int* __restrict__ act, int D, int Rp) {
+  const int lane = threadIdx.x & 63, i16 = lane & 15, g4 = lane >> 4;
+  const int tile = xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int4 tl = tiles[tile];
+  const int t = tl.x, n0 = tl.y, cf0 = tl.z * kColGroup;
+  if (act != nullptr && act[t] == 0) return;
+  const int64_t r0 = row_off[t];
+  const int nt = (int)(row_off[t + 1] - r0);
+  const int np = (int)((w16_off[t + 1] - w16_off[t]) / Rp);
+  const int ncf = min(kColGroup, Rp / 16 - cf0);
+  const T16* mrow[kRF16];
+#pragma unroll
+  for (int rf = 0; rf < kRF16; ++rf) {
+    const int row = n0 + rf * 16 + i16;
+    mrow[rf] = row < nt ? phi16 + (r0 + row) * (int64_t)D + 8 * g4 : nullptr;
+  }
+  const T16* vcol = V16 + ((int64_t)t * Rp + cf0 * 16 + i16) * D + 8 * g4;
+  f4 acc[kRF16][kColGroup];
+#pragma unroll
+  for (int rf = 0; rf < kRF16; ++rf)
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = f4{0.f, 0.f, 0.f, 0.f};
+  nt16_mainloop<T16>(acc, mrow, vcol, D, ncf, D);
+  typedef T16 t4 __attribute__((ext_vector_type(4)));
+  T16* Wt = W16 + w16_off[t];
+#pragma unroll
+  for (int rf = 0; rf < kRF16; ++rf) {
+    const int rb = n0 + rf * 16;
+    if (rb >= np) continue;
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      if (cf >= ncf) continue;
+      const int j = (cf0 + cf) * 16 + i16;
+      t4 o;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = (T16)acc[rf][cf][r];
+      *(t4*)(Wt + (int64_t)j * np + rb + 4 * g4) = o;
+    }
+  }
+}
+
+// AV_t = beta PhiT16_t W16_t + alpha_{c(j)} (.) V_t: tile {t, d0, column group}.
+template <typename T16>
+__global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16,
+                                                  const int64_t* __restrict__ w16_off,
+                                                  const int4* __restrict__ tiles, int ntiles,
+                                                  const T16* __restrict__ W16,
+                                                  const float* __restrict__ V,
+                                                  float* __restrict__ AV,
+                                                  const float* __restrict__ alpha,
+                                                  const int* __restrict__ colc, double beta,
+                                                  const int* __restrict__ act, int D, int Rp) {
+  const int lane = threadIdx.x & 63, i16 = lane & 15, g4 = lane >> 4;
+  const int tile = xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  if (tile >= ntiles) return;
+  const int4 tl = tiles[tile];
+  const int t = tl.x, d0 = tl.y, cf0 = tl.z * kColGroup;
+  if (act != nullptr && act[t] == 0) return;
+  const int64_t wo = w16_off[t];
+  const int np = (int)((w16_off[t + 1] - wo) / Rp);
+  const int ncf = min(kColGroup, Rp / 16 - cf0);
+  const T16* M = phiT16 + (wo / Rp) * (int64_t)D;
+  const T16* mrow[kRF16];
+#pragma unroll
+  for (int rf = 0; rf < kRF16; ++rf) {
+    const int row = d0 + rf * 16 + i16;
+    mrow[rf] = row < D ? M + (int64_t)row * np + 8 * g4 : nullptr;
+  }
+  const T16* vcol = W16 + wo + (int64_t)(cf0 * 16 + i16) * np + 8 * g4;
+  f4 acc[kRF16][kColGroup];
+#pragma unroll
+  for (int rf = 0; rf < kRF16; ++rf)
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = f4{0.f, 0.f, 0.f, 0.f};
+  nt16_mainloop<T16>(acc, mrow, vcol, np, ncf, np);
+#pragma unroll
+  for (int cf = 0; cf < kColGroup; ++cf) {
+    if (cf >= ncf) continue;
+    const int j = (cf0 + cf) * 16 + i16;
+    const int c = colc[(int64_t)t * Rp + j];
+    const int64_t col = ((int64_t)t * Rp + j) * D;
+    const float* al = alpha + (int64_t)(c >= 0 ? c : 0) * D;
+#pragma unroll
+    for (int rf = 0; rf < kRF16; ++rf) {
+      const int d = d0 + rf * 16 + 4 * g4;
+      if (d >= D) continue;
+      const f4 v = *(const f4*)(V + col + d);
+      f4 o;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        o[r] = (float)beta * acc[rf][cf][r] + (c >= 0 ? al[d + r] : 0.f) * v[r];
+      *(f4*)(AV + col + d) = o;
+    }
+  }
+}
+
+// PhiT16 of every task: [D][np_t] with zero columns n >= N_t.  32x32 tiles through LDS.
+template <typename T16>
+__global__ __launch_bounds__(256) void k_transpose16(const T16* __restrict__ phi16,
+                                                     const int64_t* __restrict__ row_off,
+                                                     const int64_t* __restrict__ w16_off,
+                                                     T16* __restrict__ phiT16, int D, int Rp) {
+  __shared__ T16 tileb[32][33];
+  const int t = blockIdx.z;
+  const int64_t wo = w16_off[t];
+  const int np = (int)((w16_off[t + 1] - wo) / Rp);
+  const int n0 = blockIdx.y * 32, d0 = blockIdx.x * 32;
+  if (n0 >= np) return;
+  const int64_t r0 = row_off[t];
+  const int nt = (int)(row_off[t + 1] - r0);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int i = ty; i < 32; i += 8) {
+    const int n = n0 + i, d = d0 + tx;
+    tileb[i][tx] = (n < nt && d < D) ? phi16[(r0 + n) * (int64_t)D + d] : (T16)0.f;
+  }
+  __syncthreads();
+  T16* out = phiT16 + (wo / Rp) * (int64_t)D;
+  for (int i = ty; i < 32; i += 8) {
+    const int d = d0 + i, n = n0 + tx;
+    if (d < D) out[(int64_t)d * np + n] = tileb[tx][i];
+  }
+}
+
+template <typename T16>
+__global__ __launch_bounds__(256) void k_round16(const float* __restrict__ x,
+                                                 T16* __restrict__ y, int64_t n) {
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i + 3 < n) {
+    const f4 v = *(const f4*)(x + i);
+    typedef T16 t4 __attribute__((ext_vector_type(4)));
+    t4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = (T16)v[r];
+    *(t4*)(y + i) = o;
+  } else {
+    for (int64_t k = i; k < n; ++k) y[k] = (T16)x[k];
+  }
+}
+
+// Second half of a residual-replacement step u for every active column:
+//   r = src - A x;  xi = r.r / r_old.r_old;  d = r + xi d;  stop decision as in k_cg_update.
+template <int BS, int EPT>
+__global__ __launch_bounds__(BS) void k_replace(const float* __restrict__ AX,
+                                                float* __restrict__ Rv, float* __restrict__ Dv,
+                                                double* __restrict__ rr,
+                                                const double* __restrict__ thr,
+                                                uint8_t* __restrict__ state,
+                                                int* __restrict__ iters,
+                                                double* __restrict__ xi, int* __restrict__ act,
+                                                int kind, const float* __restrict__ b,
+                                                const float* __restrict__ B, int K, uint64_t key,
+                                                const int8_t* __restrict__ probes, int u,
+                                                int steps, int fixed, int T, int C, int R,
+                                                int Rp, int D) {
+  __shared__ double sh[BS / 64];
+  const int t = blockIdx.x / R, j = blockIdx.x % R;
+  const int64_t idx = (int64_t)t * Rp + j;
+  if (state[idx] != kActive) return;
+  const double rr_old = rr[idx];
+  int c = 0, k = 0;
+  if (kind == 0) { c = j / (K + 1); k = j % (K + 1); }
+  const int64_t base = idx * D;
+  float rv[EPT];
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int d = threadIdx.x + e * BS;
+    rv[e] = 0.f;
+    if (d >= D) continue;
+    float v;
+    if (kind == 0) {
+      if (k == 0) v = b[(int64_t)t * D + d];
+      else if (probes != nullptr) v = (float)probes[(((int64_t)t * C + c) * K + (k - 1)) * D + d];
+      else v = (float)probe_entry(key, t, c, k - 1, d, C, K, D);
+    } else {
+      v = B[((int64_t)t * R + j) * D + d];
+    }
+    rv[e] = v - AX[base + d];
+    acc += (double)rv[e] * (double)rv[e];
+  }
+  const double rrn = block_sum<BS>(acc, sh);
+  const double x_ = rrn / rr_old;
+  const float xf = (float)x_;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int d = threadIdx.x + e * BS;
+    if (d < D) {
+      Rv[base + d] = rv[e];
+      Dv[base + d] = rv[e] + xf * Dv[base + d];
+    }
+  }
+  if (threadIdx.x == 0) {
+    xi[(int64_t)u * T * Rp + idx] = x_;
+    rr[idx] = rrn;
+    iters[idx] = u + 1;
+    uint8_t st = kActive;
+    if (!isfinite(rrn)) st = CMTCS_CG_BREAKDOWN;
+    else if (rrn == 0.0 || (fixed == 0 && rrn <= thr[idx])) st = CMTCS_CG_CONVERGED;
+    else if (u + 1 >= steps) st = fixed ? CMTCS_CG_CONVERGED : CMTCS_CG_MAX_ITER;
+    state[idx] = st;
+    if (st == kActive) atomicAdd(&act[(int64_t)(u + 1) * T + t], 1);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+
+template <typename T16>
+hipError_t launch_mixed_products(const Geometry& g16, const void* phi16, const void* phiT16,
+                                 const int4* fwd, int nfwd, const int4* adj, int nadj,
+                                 const void* V16, void* W16, const float* V, float* AV,
+                                 const float* alpha, const int* colc, double beta,
+                                 const int* act, int which, hipStream_t st) {
+  if (which == 1) {
+    if (nfwd == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_phi_v16<T16>), dim3((nfwd + 3) / 4), dim3(256), 0, st,
+                       (const T16*)phi16, g16.row_off, g16.w_off, fwd, nfwd, (const T16*)V16,
+                       (T16*)W16, act, g16.D, g16.Rp);
+    return hipGetLastError();
+  }
+  if (nadj == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_phit_w16<T16>), dim3((nadj + 3) / 4), dim3(256), 0, st,
+                     (const T16*)phiT16, g16.w_off, adj, nadj, (const T16*)W16, V, AV, alpha,
+                     colc, beta, act, g16.D, g16.Rp);
+  return hipGetLastError();
+}
+
+template <typename T16>
+hipError_t launch_transpose16(const Geometry& g16, const void* phi16, void* phiT16,
+                              int max_np, hipStream_t st) {
+  if (max_np == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_transpose16<T16>), dim3((g16.D + 31) / 32, (max_np + 31) / 32, g16.T),
+                     dim3(256), 0, st, (const T16*)phi16, g16.row_off, g16.w_off,
+                     (T16*)phiT16, g16.D, g16.Rp);
+  return hipGetLastError();
+}
+
+template <typename T16>
+hipError_t launch_round16(const float* x, void* y, int64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const int64_t blocks = (n / 4 + 255) / 256 + 1;
+  hipLaunchKernelGGL((k_round16<T16>), dim3((unsigned)blocks), dim3(256), 0, st, x, (T16*)y, n);
+  return hipGetLastError();
+}
+
+template <int BS, int EPT>
+static hipError_t replace_one(const Geometry& g, const CgState& s, const float* AX,
+                              const RhsSource& src, int u, int steps, int fixed, hipStream_t st) {
+  hipLaunchKernelGGL((k_replace<BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, AX, (float*)s.Rv,
+                     (float*)s.Dv, s.rr, s.thr, s.state, s.iters, s.xi, s.act, src.kind,
+                     (const float*)src.b, (const float*)src.B, src.K, src.key, src.probes, u,
+                     steps, fixed, g.T, g.C, g.R, g.Rp, g.D);
+  return hipGetLastError();
+}
+
+hipError_t launch_replace(const Geometry& g, const CgState& s, const float* AX,
+                          const RhsSource& src, int u, int steps, int fixed, hipStream_t st) {
+  if (g.D <= 256) return replace_one<256, 1>(g, s, AX, src, u, steps, fixed, st);
+  if (g.D <= 512) return replace_one<256, 2>(g, s, AX, src, u, steps, fixed, st);
+  if (g.D <= 1024) return replace_one<256, 4>(g, s, AX, src, u, steps, fixed, st);
+  if (g.D <= 2048) return replace_one<256, 8>(g, s, AX, src, u, steps, fixed, st);
+  if (g.D <= 4096) return replace_one<256, 16>(g, s, AX, src, u, steps, fixed, st);
+  if (g.D <= 8192) return replace_one<1024, 8>(g, s, AX, src, u, steps, fixed, st);
+  return replace_one<1024, 16>(g, s, AX, src, u, steps, fixed, st);
+}
+
+#define CMTCS_INST16(T16)                                                                      \
+  template hipError_t launch_mixed_products<T16>(                                              \
+      const Geometry&, const void*, const void*, const int4*, int, const int4*, int,            \
+      const void*, void*, const float*, float*, const float*, const int*, double, const int*,  \
+      int, hipStream_t);                                                                       \
+  template hipError_t launch_transpose16<T16>(const Geometry&, const void*, void*, int,       \
+                                              hipStream_t);                                    \
+  template hipError_t launch_round16<T16>(const float*, void*, int64_t, hipStream_t);
+CMTCS_INST16(__bf16)
+CMTCS_INST16(_Float16)
+
+}  // namespace cmtcs

@@ -61,7 +61,8 @@ def _problem(**over):
     (dict(row_off=np.array([0, 5, 3], np.int64)), "non-decreasing"),
     (dict(row_off=np.array([1, 5, 8], np.int64)), "row_off[0]"),
     (dict(math=_lib.CMTCS_MATH_MIXED), "MATH_MIXED"),
-    (dict(phi_dtype=_lib.CMTCS_BF16), "F32 phi"),
+    (dict(math=_lib.CMTCS_MATH_MIXED, phi_dtype=_lib.CMTCS_BF16, D=48), "multiple of 32"),
+    (dict(phi_dtype=_lib.CMTCS_BF16), "phi_dtype F32"),
 ])
 def test_create_rejects_bad_problems(over, frag):
     lib = _lib.load()
