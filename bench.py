@@ -13,6 +13,7 @@ sample on the host CPU.
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,7 +40,26 @@ def parse():
     ap.add_argument("--refine-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tasks", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after timing, copy 1 GiB device-to-device three times (a plain copy "
+                         "kernel of known size, for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+def measured_traffic(kernel, workload, math):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter record
+    (profiles/traffic.json), or None if there is none for this workload or the kernel's source
+    has changed since the counters were taken."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec["workload"] != workload or rec["math"] != math:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_read_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
 
 
 def cpu_baseline(w, ntasks):
@@ -144,9 +164,13 @@ def main():
         flops = 2.0 * cfg.D * row_iters
         achieved = flops / (tot_ms * 1e-3) / 1e12
         peak = PEAK_TFLOPS[a.math]
+        rows = m.tiles()[0 if name == "phi_v" else 1]
+        vt = "double" if a.math == "f64" else "float"
+        kname = "k_%s<%s, %d>" % (name, vt, rows // 16)
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": name, "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(kname, a.config, a.math),
+                "kernel": kname, "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
                 "flop_per_launch": flops / max(launches, 1)}
     res = {
         "metric": "CG RHS-iters/sec + EM iter time, D=4096 T=64 C=4 K=32; MFMA/HBM roofline %",
@@ -165,10 +189,19 @@ def main():
                    "mixed(%s, true residual every %d)" % (a.phi16, a.refine_every)},
         "roofline": roof,
         "detail": {"rhs_iters_per_em_iter": rhs_iters / a.steps, "max_cg_steps": max_steps,
+                   "tile_rows": m.tiles(),
                    "kernel_ms_per_em_iter": {k: round(v[0] / a.steps, 3)
                                              for k, v in prof.items()},
                    "launches_per_em_iter": {k: v[1] / a.steps for k, v in prof.items()}},
     }
+    if a.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["detail"]["copy_calibration_bytes"] = 4 << 28
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, a.cpu_tasks)
     m.close()

@@ -216,6 +216,12 @@ cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_t
 cmtcs_status_t cmtcs_profile(cmtcs_handle_t h, int32_t enable, double* totals_ms,
                              int64_t* counts);
 
+/* Tile shapes in use: rows[0] and rows[1] (HOST) receive the output rows per wave tile of the
+ * Phi V and the Phi^T W products.  Unless the environment variable CMTCS_AUTOTUNE is "0" when
+ * the handle is created, the first call with a new number of column slots per task times every
+ * supported height of each product on the handle's own buffers and keeps the fastest. */
+cmtcs_status_t cmtcs_tiles(cmtcs_handle_t h, int32_t* rows);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* cmtcs_last_error(void);
 

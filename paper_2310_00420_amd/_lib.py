@@ -78,6 +78,8 @@ def load():
     lib.cmtcs_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
     lib.cmtcs_profile.restype = st
+    lib.cmtcs_tiles.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    lib.cmtcs_tiles.restype = st
     lib.cmtcs_last_error.argtypes = []
     lib.cmtcs_last_error.restype = ctypes.c_char_p
     lib.cmtcs_version.argtypes = []

@@ -214,6 +214,12 @@ class Cmtcs:
                                           _ptr(dphi)))
         return dalpha, dphi
 
+    def tiles(self):
+        """Output rows per wave tile of the (Phi V, Phi^T W) products in use."""
+        rows = (ctypes.c_int32 * 2)()
+        _lib.check(_lib.load().cmtcs_tiles(self._h, rows))
+        return int(rows[0]), int(rows[1])
+
     def profile(self, enable=None):
         """Kernel timing: enable (True/False) and/or read {name: (total ms, launches)}."""
         flag = -1 if enable is None else int(bool(enable))

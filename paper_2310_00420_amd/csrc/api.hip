@@ -3,6 +3,7 @@
 // tasks, Sec. 3.3) per E-step of Alg. 2.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -62,6 +63,9 @@ struct cmtcs_handle_s {
   int4* fwd_tiles = nullptr;
   int4* adj_tiles = nullptr;
   int nfwd = 0, nadj = 0, cur_Rp = -1;
+  // output rows per wave tile of the two products (autotuned per column count)
+  int fwd_rows = 0, adj_rows = 0, cur_fwd_rows = -1, cur_adj_rows = -1, tuned_Rp = -1;
+  bool autotune = true;
   double *dg = nullptr, *of = nullptr, *zz = nullptr, *tau = nullptr, *rmin = nullptr,
          *rmax = nullptr, *slog = nullptr;
   uint8_t* ok = nullptr;
@@ -148,9 +152,8 @@ struct cmtcs_handle_s {
 
   // Tile tables and W offsets for Rp column slots per task (rebuilt only when Rp changes).
   cmtcs_status_t prepare(int Rp) {
-    if (Rp == cur_Rp) return CMTCS_OK;
-    const bool f64 = math == CMTCS_MATH_F64;
-    const int fr = fwd_rows_per_tile(f64), ar = adj_rows_per_tile(f64), ng = ngroups(Rp);
+    if (Rp == cur_Rp && fwd_rows == cur_fwd_rows && adj_rows == cur_adj_rows) return CMTCS_OK;
+    const int fr = fwd_rows, ar = adj_rows, ng = ngroups(Rp);
     std::vector<int64_t> woff(T + 1, 0);
     std::vector<int4> ft, at;
     for (int t = 0; t < T; ++t) {
@@ -195,7 +198,56 @@ struct cmtcs_handle_s {
     nfwd = (int)ft.size();
     nadj = (int)at.size();
     cur_Rp = Rp;
+    cur_fwd_rows = fwd_rows;
+    cur_adj_rows = adj_rows;
     return CMTCS_OK;
+  }
+
+  // Autotuner: for a new column count, times every supported tile height of each product on
+  // the handle's own buffers (one warm-up and three timed launches, HIP events on the
+  // handle's stream) and keeps the fastest.  Runs before the solve initialises its vectors;
+  // the products only read the workspace and write W and AD.
+  template <typename VT>
+  cmtcs_status_t tune(const Geometry& g, const float* alpha) {
+    if (!autotune || mixed() || tuned_Rp == g.Rp) return prepare(g.Rp);
+    int cand[4];
+    const int nc = op_row_candidates(math == CMTCS_MATH_F64, cand);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    cmtcs_status_t rs = CMTCS_OK;
+    for (int kind = 0; kind < 2 && rs == CMTCS_OK; ++kind) {
+      float best = 1e30f;
+      int best_rows = kind == 0 ? fwd_rows : adj_rows;
+      for (int i = 0; i < nc && rs == CMTCS_OK; ++i) {
+        (kind == 0 ? fwd_rows : adj_rows) = cand[i];
+        rs = prepare(g.Rp);
+        if (rs != CMTCS_OK) break;
+        float ms = 0.f;
+        hipError_t e = hipSuccess;
+        for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+          if (rep == 1) e = hipEventRecord(e0, st);
+          if (e != hipSuccess) break;
+          if (kind == 0)
+            e = launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
+                                 fwd_rows, st);
+          else
+            e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
+                                  (VT*)AD, alpha, colc, beta, nullptr, adj_rows, st);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { rs = hip_fail(e, "autotune"); break; }
+        if (ms < best) { best = ms; best_rows = cand[i]; }
+      }
+      (kind == 0 ? fwd_rows : adj_rows) = best_rows;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs != CMTCS_OK) return rs;
+    tuned_Rp = g.Rp;
+    return prepare(g.Rp);
   }
 
   // Runs CG steps until every right-hand side has stopped or `steps` steps are done.
@@ -230,14 +282,16 @@ struct cmtcs_handle_s {
       if (mixed())
         HIP_TRY(mixed_product(g16, alpha, act_u, 1), "launch(phi_v16)");
       else
-        HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, st),
+        HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u,
+                                  fwd_rows, st),
                 "launch(phi_v)");
       if (e4) HIP_TRY(hipEventRecord(e4[1], st), "hipEventRecord");
       if (mixed())
         HIP_TRY(mixed_product(g16, alpha, act_u, 2), "launch(phit_w16)");
       else
         HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
-                                  (VT*)AD, alpha, colc, beta, act_u, st), "launch(phit_w)");
+                                  (VT*)AD, alpha, colc, beta, act_u, adj_rows, st),
+                "launch(phit_w)");
       if (e4) HIP_TRY(hipEventRecord(e4[2], st), "hipEventRecord");
       const bool replace = mixed() && refine_every > 0 && (u + 1) % refine_every == 0;
       HIP_TRY(launch_cg_update<VT>(g, s, u, steps, fixed, replace ? 1 : 0, st),
@@ -246,9 +300,9 @@ struct cmtcs_handle_s {
         // true-residual replacement: r = b - A x with FP32 products from the FP32 Phi, then
         // xi, d and the stop decision from the replaced residual
         HIP_TRY(launch_phi_v<float>(g, phi, fwd_tiles, nfwd, (const float*)X, (float*)W, act_u,
-                                    st), "launch(phi_v residual)");
+                                    fwd_rows, st), "launch(phi_v residual)");
         HIP_TRY(launch_phit_w<float>(g, phi, adj_tiles, nadj, (const float*)W, (const float*)X,
-                                     (float*)AD, alpha, colc, beta, act_u, st),
+                                     (float*)AD, alpha, colc, beta, act_u, adj_rows, st),
                 "launch(phit_w residual)");
         HIP_TRY(launch_replace(g, s, (const float*)AD, src, u, steps, fixed, st),
                 "launch(replace)");
@@ -282,10 +336,10 @@ struct cmtcs_handle_s {
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.key = 0; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, 0.0, 0, st), "launch(cg_init)");
-    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr, st),
-            "launch(phi_v)");
+    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
+                             fwd_rows, st), "launch(phi_v)");
     HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
-                              alpha, colc, beta, nullptr, st), "launch(phit_w)");
+                              alpha, colc, beta, nullptr, adj_rows, st), "launch(phit_w)");
     CgState s = cg();
     s.X = AD;   // copy A V out through the solution-copy kernel
     HIP_TRY(launch_solve_output<VT>(g, s, AV, nullptr, nullptr, 0, nullptr, nullptr, st),
@@ -302,8 +356,8 @@ struct cmtcs_handle_s {
     const Geometry g = geom(2 * R, Rp);
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
     HIP_TRY(launch_pack2<VT>(geom(R, Rp), Xs, Lam, Dv, st), "launch(pack2)");
-    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr, st),
-            "launch(phi_v)");
+    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
+                             fwd_rows, st), "launch(phi_v)");
     HIP_TRY(launch_grads<VT>(g, R, (const VT*)Dv, (const VT*)W, y, colc, beta, y_coef, dalpha,
                              dphi, row_off[T], st), "launch(grads)");
     return CMTCS_OK;
@@ -321,6 +375,8 @@ struct cmtcs_handle_s {
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, K, nullptr, st), "launch(fill_colc)");
+    rs = tune<VT>(g, alpha);
+    if (rs != CMTCS_OK) return rs;
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.key = key; src.probes = o.probes;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
@@ -357,6 +413,8 @@ struct cmtcs_handle_s {
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
+    rs = tune<VT>(g, alpha);
+    if (rs != CMTCS_OK) return rs;
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.key = 0; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
@@ -446,12 +504,19 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   size_t np_sum = 0, fwd_max = 0;
   const bool f64 = h->math == CMTCS_MATH_F64;
   const size_t ngm = (size_t)h->ngroups(h->Rp_max);
+  int cand[4];
+  const int nc = op_row_candidates(f64, cand);
+  int min_rows = cand[0];
+  for (int i = 1; i < nc; ++i) min_rows = std::min(min_rows, cand[i]);
+  h->fwd_rows = h->adj_rows = cand[0];
+  const char* at = std::getenv("CMTCS_AUTOTUNE");
+  h->autotune = !(at != nullptr && at[0] == '0');
   for (size_t t = 0; t < T; ++t) {
     const size_t np = (size_t)round16((int)(h->row_off[t + 1] - h->row_off[t]));
     np_sum += np;
-    fwd_max += (np + fwd_rows_per_tile(f64) - 1) / fwd_rows_per_tile(f64) * ngm;
+    fwd_max += (np + min_rows - 1) / min_rows * ngm;
   }
-  const size_t adj_max = T * ((D + adj_rows_per_tile(f64) - 1) / adj_rows_per_tile(f64)) * ngm;
+  const size_t adj_max = T * ((D + min_rows - 1) / min_rows) * ngm;
   const size_t vec = T * Rpm * D * h->vbytes;
   const size_t P = T * C * (size_t)h->max_K;
   hipError_t e = hipSuccess;
@@ -655,6 +720,13 @@ cmtcs_status_t cmtcs_profile(cmtcs_handle_t h, int32_t enable, double* totals_ms
       if (counts) counts[k] = h->prof_n[k];
     }
   }
+  return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_tiles(cmtcs_handle_t h, int32_t* rows) {
+  if (h == nullptr || rows == nullptr) return fail(CMTCS_E_INVALID, "NULL argument");
+  rows[0] = h->fwd_rows;
+  rows[1] = h->adj_rows;
   return CMTCS_OK;
 }
 

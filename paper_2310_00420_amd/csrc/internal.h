@@ -106,16 +106,17 @@ struct Geometry {
 constexpr int kColGroup = 9;   // 16-column fragments per wave tile (144 columns)
 
 // Launchers (k_operator.hip).  `act` is the [T] count of active right-hand sides for the
-// current step (tasks with a zero count are skipped) or null.
+// current step (tasks with a zero count are skipped) or null.  `rows` is the output rows per
+// wave tile the tile table was built for (one of op_row_candidates).
 template <typename VT>
 hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
-                        const VT* V, VT* W, const int* act, hipStream_t st);
+                        const VT* V, VT* W, const int* act, int rows, hipStream_t st);
 template <typename VT>
 hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
-                         double beta, const int* act, hipStream_t st);
-int fwd_rows_per_tile(bool f64);
-int adj_rows_per_tile(bool f64);
+                         double beta, const int* act, int rows, hipStream_t st);
+// Writes the supported rows-per-tile values (default first) and returns their count.
+int op_row_candidates(bool f64, int* rows);
 
 // Launchers (k_cg.hip).
 struct CgState {

@@ -24,12 +24,13 @@ __device__ inline int xcd_block(int b, int nb) {
   return x * q + min(x, rem) + i;
 }
 
-template <typename VT> struct OpCfg;
-template <> struct OpCfg<double> { static constexpr int kFwdRF = 2, kAdjRF = 2; };
-template <> struct OpCfg<float> { static constexpr int kFwdRF = 4, kAdjRF = 4; };
-
-int fwd_rows_per_tile(bool f64) { return 16 * (f64 ? OpCfg<double>::kFwdRF : OpCfg<float>::kFwdRF); }
-int adj_rows_per_tile(bool f64) { return 16 * (f64 ? OpCfg<double>::kAdjRF : OpCfg<float>::kAdjRF); }
+// Output rows per wave tile (16 * RF) that the instantiations below support; the autotuner of
+// the host layer picks one per product.  FP64 tiles keep RF * 9 accumulators of 8 registers.
+int op_row_candidates(bool f64, int* rows) {
+  if (f64) { rows[0] = 32; rows[1] = 16; }
+  else { rows[0] = 64; rows[1] = 32; }
+  return 2;   // the first entry is the default
+}
 
 template <typename VT, int RF>
 __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
@@ -198,49 +199,87 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
     for (int r = 0; r < 4; ++r) {
       const int d = d0 + RF * Mfma<VT>::out_row(g4, r);
       if (d >= D) continue;
-      const vrf v = *(const vrf*)(V + col + d);
-      vrf o;
+      // one explicit fused multiply-add per element, so that every tile shape rounds the
+      // epilogue identically (results do not depend on the autotuner's choice)
+      if constexpr (RF == 1) {
+        const VT a = c >= 0 ? (VT)al[d] : (VT)0;
+        const VT av = a * V[col + d];
+        AV[col + d] = __builtin_fma((VT)beta, acc[0][cf][r], av);
+      } else {
+        const vrf v = *(const vrf*)(V + col + d);
+        vrf o;
 #pragma unroll
-      for (int f = 0; f < RF; ++f) {
-        const VT a = c >= 0 ? (VT)al[d + f] : (VT)0;
-        o[f] = (VT)beta * acc[f][cf][r] + a * v[f];
+        for (int f = 0; f < RF; ++f) {
+          const VT a = c >= 0 ? (VT)al[d + f] : (VT)0;
+          const VT av = a * v[f];
+          o[f] = __builtin_fma((VT)beta, acc[f][cf][r], av);
+        }
+        *(vrf*)(AV + col + d) = o;
       }
-      *(vrf*)(AV + col + d) = o;
     }
   }
 }
 
-template <typename VT>
-hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
-                        const VT* V, VT* W, const int* act, hipStream_t st) {
-  if (ntiles == 0) return hipSuccess;
-  const int blocks = (ntiles + 3) / 4;
-  hipLaunchKernelGGL((k_phi_v<VT, OpCfg<VT>::kFwdRF>), dim3(blocks), dim3(256), 0, st, phi,
+template <typename VT, int RF>
+static hipError_t phi_v_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                           const VT* V, VT* W, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL((k_phi_v<VT, RF>), dim3((ntiles + 3) / 4), dim3(256), 0, st, phi,
                      g.row_off, g.w_off, tiles, ntiles, V, W, act, g.D, g.Rp);
   return hipGetLastError();
 }
 
-template <typename VT>
-hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
-                         const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
-                         double beta, const int* act, hipStream_t st) {
-  if (ntiles == 0) return hipSuccess;
-  const int blocks = (ntiles + 3) / 4;
-  hipLaunchKernelGGL((k_phit_w<VT, OpCfg<VT>::kAdjRF>), dim3(blocks), dim3(256), 0, st, phi,
+template <typename VT, int RF>
+static hipError_t phit_w_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                            const VT* W, const VT* V, VT* AV, const float* alpha,
+                            const int* colc, double beta, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL((k_phit_w<VT, RF>), dim3((ntiles + 3) / 4), dim3(256), 0, st, phi,
                      g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
                      g.Rp);
   return hipGetLastError();
 }
 
+template <typename VT>
+hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                        const VT* V, VT* W, const int* act, int rows, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  if constexpr (sizeof(VT) == 8) {
+    if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
+    if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, st);
+  } else {
+    if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, st);
+    if (rows == 64) return phi_v_rf<VT, 4>(g, phi, tiles, ntiles, V, W, act, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename VT>
+hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
+                         const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
+                         double beta, const int* act, int rows, hipStream_t st) {
+  if (ntiles == 0) return hipSuccess;
+  if constexpr (sizeof(VT) == 8) {
+    if (rows == 16)
+      return phit_w_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+    if (rows == 32)
+      return phit_w_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+  } else {
+    if (rows == 32)
+      return phit_w_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+    if (rows == 64)
+      return phit_w_rf<VT, 4>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template hipError_t launch_phi_v<double>(const Geometry&, const float*, const int4*, int,
-                                         const double*, double*, const int*, hipStream_t);
+                                         const double*, double*, const int*, int, hipStream_t);
 template hipError_t launch_phi_v<float>(const Geometry&, const float*, const int4*, int,
-                                        const float*, float*, const int*, hipStream_t);
+                                        const float*, float*, const int*, int, hipStream_t);
 template hipError_t launch_phit_w<double>(const Geometry&, const float*, const int4*, int,
                                           const double*, const double*, double*, const float*,
-                                          const int*, double, const int*, hipStream_t);
+                                          const int*, double, const int*, int, hipStream_t);
 template hipError_t launch_phit_w<float>(const Geometry&, const float*, const int4*, int,
                                          const float*, const float*, float*, const float*,
-                                         const int*, double, const int*, hipStream_t);
+                                         const int*, double, const int*, int, hipStream_t);
 
 }  // namespace cmtcs

@@ -23,7 +23,7 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("cmtcs_create", "cmtcs_destroy", "cmtcs_estep", "cmtcs_mstep", "cmtcs_solve",
-              "cmtcs_apply", "cmtcs_profile", "cmtcs_rhs", "cmtcs_grad", "cmtcs_last_error",
+              "cmtcs_apply", "cmtcs_profile", "cmtcs_rhs", "cmtcs_grad", "cmtcs_tiles", "cmtcs_last_error",
               "cmtcs_version"):
         assert n in names
 
@@ -88,6 +88,7 @@ def test_null_arguments():
     assert lib.cmtcs_apply(None, None, 1, None, None, None) == _lib.CMTCS_E_INVALID
     assert lib.cmtcs_profile(None, 1, None, None) == _lib.CMTCS_E_INVALID
     assert lib.cmtcs_rhs(None, None) == _lib.CMTCS_E_INVALID
+    assert lib.cmtcs_tiles(None, None) == _lib.CMTCS_E_INVALID
     assert lib.cmtcs_grad(None, 1, None, None, None, 0.0, None, None) == _lib.CMTCS_E_INVALID
     assert lib.cmtcs_destroy(None) == _lib.CMTCS_OK
 

@@ -68,9 +68,12 @@ def test_posterior_mean_grads_diff_config():
 
 def test_posterior_mean_grads_central_differences():
     """Central differences of the device forward itself (FP64 CG) at D=64, N=32, for entries
-    of alpha.  The step is h = alpha * 2^-8 and the quotient uses the FP32 values actually
-    applied, so the only errors are the O((h/alpha)^2) truncation and the CG residual."""
-    w = synth.make(synth.Config("diff-small", T=3, C=2, D=64, N=32, sparsity=5, groups=2, K=0))
+    of alpha, with beta = 50 as in the oracle's own central-difference pin (condition ~1e4, so
+    the CG residual at tol 1e-13 is far below the difference signal).  The step is
+    h = alpha * 2^-8 and the quotient uses the FP32 values actually applied, so what is left is
+    the O((h/alpha)^2) truncation."""
+    w = synth.make(synth.Config("diff-small", T=3, C=2, D=64, N=32, sparsity=5, groups=2, K=0,
+                                sigma=50 ** -0.5))
     _, da, _ = _posterior_mean_grads(w, w.alpha0)
     m = device_model(w, K=0, max_rhs=2, max_iters=CG["max_iters"])
     z = torch.tensor(w.z, device=DEV)
@@ -88,7 +91,8 @@ def test_posterior_mean_grads_central_differences():
         am[c, d] = np.float32(a0 - a0 * 2.0 ** -8)
         fd = (loss(ap) - loss(am)) / (float(ap[c, d]) - float(am[c, d]))
         worst = max(worst, abs(fd - da[c, d]) / max(abs(fd), 1e-12))
-    print("\ncentral differences: worst rel %.2e" % worst)
+        print("\nalpha[%d,%d]=%.4g: fd %.8e adjoint %.8e" % (c, d, a0, fd, da[c, d]))
+    print("central differences: worst rel %.2e (tiles %s)" % (worst, m.tiles()))
     assert worst <= 1e-4   # truncation ~ (2^-8)^2 = 1.5e-5 times a modest constant
 
 

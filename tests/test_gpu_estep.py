@@ -71,6 +71,9 @@ def _run(w, tasks, math="f64", probes=None, seed=1, it=0, alpha=None, K=None, sp
     if spread:
         alt = _oracle_columnwise(w, b, alpha, K, _policy(cfg), seed, it, probes, tasks)
         sp = estep_errors(alt, ref)
+        # CG step counts: a column may stop where either FP64 order of the oracle stops (+-1)
+        it_a = alt["iters"].reshape(len(tasks), -1)
+        err["iters_excess"] = int(np.max(np.abs(it_g - it_o) - np.maximum(1, np.abs(it_a - it_o))))
         print("\noracle self-spread (summation order):",
               {k: float(np.max(v)) for k, v in sp.items()})
     else:
@@ -96,7 +99,7 @@ def test_estep_tiny_f64():
     w = synth.make("tiny")
     err, g, ref, sp = _run(w, range(w.T))
     _assert(err, sp)
-    assert err["iters_maxdiff"] == 0
+    assert err["iters_maxdiff"] == 0           # fixed mode: every column takes 64 steps
 
 
 def test_estep_tiny_converged_f64():
@@ -116,7 +119,7 @@ def test_estep_fp32_config_f64_sampled_tasks():
     w = synth.make("fp32")
     err, g, ref, sp = _run(w, [0, 9, 18, 31])
     _assert(err, sp)
-    assert err["iters_maxdiff"] <= 1
+    assert err["iters_excess"] <= 0
 
 
 def test_estep_batch_config_f64_sampled_tasks():
@@ -129,7 +132,7 @@ def test_estep_batch_config_f64_sampled_tasks():
     tasks = sorted([int(order[0]), int(order[1]), int(order[len(order) // 2])])
     err, g, ref, sp = _run(w, tasks)
     _assert(err, sp)
-    assert err["iters_maxdiff"] <= 1
+    assert err["iters_excess"] <= 0
 
 
 def test_estep_ragged_edge_f64():
