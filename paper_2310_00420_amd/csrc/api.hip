@@ -385,7 +385,7 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key, o.probes, mu, sd, st),
             "launch(estep_finalize)");
     HIP_TRY(launch_sum_log_alpha(C, D, alpha, slog, st), "launch(sum_log_alpha)");
-    HIP_TRY(launch_slq(g, cg(), K, (double)D, dg, of, zz, tau, ok, rmin, rmax, st),
+    HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, dg, of, zz, tau, ok, rmin, rmax, st),
             "launch(slq)");
     HIP_TRY(launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, st),
             "launch(resp)");

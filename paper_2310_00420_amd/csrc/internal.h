@@ -87,6 +87,9 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;
 }
 
+// A value every lane of the wave holds equally, moved to a scalar register.
+__device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // Internal state of a right-hand side during CG.
 constexpr uint8_t kActive = 255;
 
@@ -169,8 +172,9 @@ hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iter
                               uint8_t* status_out, hipStream_t st);
 
 // Launchers (k_slq.hip).
-hipError_t launch_slq(const Geometry& g, const CgState& s, int K, double pnorm2, double* dg,
-                      double* of, double* zz, double* tau, uint8_t* ok, double* rmin,
+// steps: the largest number of CG steps any probe took (bounds the tridiagonal size).
+hipError_t launch_slq(const Geometry& g, const CgState& s, int K, int steps, double pnorm2,
+                      double* dg, double* of, double* zz, double* tau, uint8_t* ok, double* rmin,
                       double* rmax, hipStream_t st);
 
 // Launchers (k_mixed.hip).  g16.w_off holds the offsets of the 16-bit W (rows padded to 32).

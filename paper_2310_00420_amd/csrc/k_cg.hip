@@ -88,7 +88,9 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
   if (state[idx] != kActive) return;
   const double rr_old = rr[idx];   // read by every thread before thread 0 rewrites it
   const int64_t base = idx * D;
-  VT dv[EPT], av[EPT];
+  // all four vectors are loaded before the first reduction so that the r and x loads are in
+  // flight while d.Ad is summed
+  VT dv[EPT], av[EPT], rv[EPT], xv[EPT];
   double pd = 0.0;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -96,9 +98,11 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
     if (d < D) {
       dv[e] = Dv[base + d];
       av[e] = AD[base + d];
+      rv[e] = Rv[base + d];
+      xv[e] = X[base + d];
       pd += (double)dv[e] * (double)av[e];
     } else {
-      dv[e] = 0; av[e] = 0;
+      dv[e] = 0; av[e] = 0; rv[e] = 0; xv[e] = 0;
     }
   }
   const double dAd = block_sum<BS>(pd, sh);
@@ -108,18 +112,14 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
   }
   const double g = rr_old / dAd;
   const VT gv = (VT)g;
-  VT rv[EPT];
   double pr = 0.0;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int d = threadIdx.x + e * BS;
     if (d < D) {
-      const VT xv = X[base + d] + gv * dv[e];
-      rv[e] = Rv[base + d] - gv * av[e];
-      X[base + d] = xv;
+      X[base + d] = xv[e] + gv * dv[e];
+      rv[e] = rv[e] - gv * av[e];
       pr += (double)rv[e] * (double)rv[e];
-    } else {
-      rv[e] = 0;
     }
   }
   if (split) {

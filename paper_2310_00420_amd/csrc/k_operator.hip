@@ -13,6 +13,8 @@
 // share, so the sum is unchanged).  Phi is streamed once per tile from HBM; the shared
 // right-hand-side block (V_t or W_t) is re-read by all tiles of a task and stays in L2, which is
 // why the block index is remapped so that the tiles of one task run on the same XCD.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace cmtcs {
@@ -43,15 +45,17 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
   typedef typename VecOf<VT, 4>::type vt4;
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
-  const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  // tile fields are wave-uniform: keep them in scalar registers so that every branch on them
+  // is a scalar branch, not an exec-mask branch around matrix-core instructions
+  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int4 tl = tiles[tile];
-  const int t = tl.x, n0 = tl.y, cf0 = tl.z * kColGroup;
+  const int t = uniform(tl.x), n0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
   if (act != nullptr && act[t] == 0) return;
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
-  const int ncf = min(kColGroup, Rp / 16 - cf0);
+  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
 
   const float* prow[RF];
   bool pval[RF];
@@ -77,29 +81,36 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
   vt4 b0[kColGroup], b1[kColGroup];
   auto load = [&](f4 (&a)[RF], vt4 (&b)[kColGroup], int d0) {
 #pragma unroll
-    for (int rf = 0; rf < RF; ++rf)
-      a[rf] = pval[rf] ? *(const f4*)(prow[rf] + d0) : f4{0.f, 0.f, 0.f, 0.f};
+    for (int rf = 0; rf < RF; ++rf) {
+      // branch-free: rows past N_t read row 0 of the task (prow) and are dropped
+      const f4 v = *(const f4*)(prow[rf] + d0);
+      a[rf] = pval[rf] ? v : f4{0.f, 0.f, 0.f, 0.f};
+    }
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (cf < ncf) b[cf] = *(const vt4*)(vbase + (int64_t)cf * 16 * D + d0);
   };
-  auto mma = [&](const f4 (&a)[RF], const vt4 (&b)[kColGroup]) {
+  auto mma = [&](const f4 (&a)[RF], const vt4 (&b)[kColGroup], auto full) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
-        if (cf < ncf)
+        if (decltype(full)::value || cf < ncf)
 #pragma unroll
           for (int rf = 0; rf < RF; ++rf)
             acc[rf][cf] = Mfma<VT>::mma((VT)a[rf][s], b[cf][s], acc[rf][cf]);
   };
-  load(a0, b0, 0);
-  for (int d0 = 0; d0 < D; d0 += 32) {
-    if (d0 + 16 < D) load(a1, b1, d0 + 16);
-    mma(a0, b0);
-    if (d0 + 32 < D) load(a0, b0, d0 + 32);
-    if (d0 + 16 < D) mma(a1, b1);
-  }
+  auto run = [&](auto full) {
+    load(a0, b0, 0);
+    for (int d0 = 0; d0 < D; d0 += 32) {
+      if (d0 + 16 < D) load(a1, b1, d0 + 16);
+      mma(a0, b0, full);
+      if (d0 + 32 < D) load(a0, b0, d0 + 32);
+      if (d0 + 16 < D) mma(a1, b1, full);
+    }
+  };
+  if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
+  else run(std::false_type{});
 
   VT* Wt = W + w_off[t];
 #pragma unroll
@@ -133,15 +144,15 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
   typedef typename VecOf<VT, RF>::type vrf;
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
-  const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int4 tl = tiles[tile];
-  const int t = tl.x, d0 = tl.y, cf0 = tl.z * kColGroup;
+  const int t = uniform(tl.x), d0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
   if (act != nullptr && act[t] == 0) return;
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
-  const int ncf = min(kColGroup, Rp / 16 - cf0);
+  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
   const int dl = d0 + RF * i16;          // first of the RF output rows this lane loads
   const bool dval = dl < D;
   const float* pbase = phi + r0 * (int64_t)D + (dval ? dl : 0);
@@ -159,20 +170,22 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
   auto load = [&](frf (&a)[4], vt4 (&b)[kColGroup], int nb) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      // branch-free: rows past N_t (or lanes past D) read row 0 of the task and drop it
       const int n = nb + 4 * g4 + s;
-      if (dval && n < nt) a[s] = *(const frf*)(pbase + (int64_t)n * D);
-      else a[s] = frf{};
+      const bool ok = dval && n < nt;
+      const frf v = *(const frf*)(pbase + (ok ? (int64_t)n * D : 0));
+      a[s] = ok ? v : frf{};
     }
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (cf < ncf) b[cf] = *(const vt4*)(wbase + (int64_t)cf * 16 * np + nb);
   };
-  auto mma = [&](const frf (&a)[4], const vt4 (&b)[kColGroup]) {
+  auto mma = [&](const frf (&a)[4], const vt4 (&b)[kColGroup], auto full) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
-        if (cf < ncf)
+        if (decltype(full)::value || cf < ncf)
 #pragma unroll
           for (int f = 0; f < RF; ++f) {
             float av;
@@ -180,13 +193,17 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
             acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], acc[f][cf]);
           }
   };
-  if (np > 0) load(a0, b0, 0);
-  for (int nb = 0; nb < np; nb += 32) {
-    if (nb + 16 < np) load(a1, b1, nb + 16);
-    mma(a0, b0);
-    if (nb + 32 < np) load(a0, b0, nb + 32);
-    if (nb + 16 < np) mma(a1, b1);
-  }
+  auto run = [&](auto full) {
+    if (np > 0) load(a0, b0, 0);
+    for (int nb = 0; nb < np; nb += 32) {
+      if (nb + 16 < np) load(a1, b1, nb + 16);
+      mma(a0, b0, full);
+      if (nb + 32 < np) load(a0, b0, nb + 32);
+      if (nb + 16 < np) mma(a1, b1, full);
+    }
+  };
+  if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
+  else run(std::false_type{});
 
 #pragma unroll
   for (int cf = 0; cf < kColGroup; ++cf) {
