@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--refine-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tasks", type=int, default=4)
+    ap.add_argument("--graph", action="store_true",
+                    help="also time the same EM iterations with the CG loop replayed as a HIP "
+                         "graph (reported under detail)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 1 GiB device-to-device three times (a plain copy "
                          "kernel of known size, for scaling HBM byte counters)")
@@ -194,6 +197,21 @@ def main():
                                              for k, v in prof.items()},
                    "launches_per_em_iter": {k: v[1] / a.steps for k, v in prof.items()}},
     }
+    if a.graph and a.math != "mixed":
+        alpha.copy_(torch.tensor(w.alpha0, dtype=torch.float32, device=dev))
+        kw["graph"] = True
+        for it in range(a.warmup):
+            em_iteration(it)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        giters = []
+        for it in range(a.warmup, a.warmup + a.steps):
+            giters.append(em_iteration(it)["iters"])
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        res["detail"]["graph"] = {
+            "ms_per_step": 1e3 * gdt / a.steps,
+            "value": sum(int(i.sum().item()) for i in giters) / gdt}
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

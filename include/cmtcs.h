@@ -112,6 +112,12 @@ typedef struct {
   const int8_t* probes;     /* optional device [T][C][K][D] of +1/-1 replacing the
                                generated probes; NULL = generated                           */
   double alpha_max;         /* M-step cap on alpha, > 0 (see cmtcs_mstep)                   */
+  int32_t graph;            /* cmtcs_estep / cmtcs_solve, MATH_F64 and MATH_F32: 1 = run the
+                               CG steps as one HIP graph, recorded on the first call with a
+                               given shape, alpha pointer and step policy and replayed after
+                               that (all steps are launched; work for right-hand sides that
+                               have stopped is skipped inside the kernels, and kernel timing by
+                               cmtcs_profile is not available); 0 = launch step by step     */
 } cmtcs_opts_t;
 
 /* Optional per-right-hand-side outputs, device pointers, each may be NULL.  For cmtcs_estep

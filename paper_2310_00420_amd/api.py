@@ -97,14 +97,14 @@ class Cmtcs:
 
     @staticmethod
     def _opts(K=0, fixed_iters=0, tol=1e-6, max_iters=200, seed=1, em_iter=0, probes=None,
-              alpha_max=1e10, refine_every=0):
+              alpha_max=1e10, refine_every=0, graph=False):
         return _lib.Opts(K=K, max_iters=max_iters, fixed_iters=fixed_iters, tol=tol,
                          refine_every=refine_every, seed=seed, em_iter=em_iter,
                          probes=None if probes is None else probes.data_ptr(),
-                         alpha_max=alpha_max)
+                         alpha_max=alpha_max, graph=int(bool(graph)))
 
     def estep(self, alpha, log_pi, K, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
-              em_iter=0, probes=None, stats=False, refine_every=0):
+              em_iter=0, probes=None, stats=False, refine_every=0, graph=False):
         """One E-step (Alg. 2 inner loop).  Returns a dict of device tensors."""
         self._check_stream()
         T, C, D, dev = self.T, self.C, self.D, self.device
@@ -126,7 +126,7 @@ class Cmtcs:
             st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(),
                               out["ritz_min"].data_ptr(), out["ritz_max"].data_ptr())
         o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
-                       em_iter=em_iter, probes=probes, refine_every=refine_every)
+                       em_iter=em_iter, probes=probes, refine_every=refine_every, graph=graph)
         _lib.check(_lib.load().cmtcs_estep(
             self._h, _ptr(alpha), _ptr(log_pi), ctypes.byref(o), _ptr(out["mu"]), _ptr(out["s"]),
             _ptr(out["logdet"]), _ptr(out["ell"]), _ptr(out["q"]),
@@ -147,7 +147,7 @@ class Cmtcs:
         return alpha
 
     def solve(self, alpha, B, col_cluster, fixed_iters=0, tol=1e-6, max_iters=200,
-              coefs=False, stats=False):
+              coefs=False, stats=False, graph=False):
         """X[t][j] = A_{t, col_cluster[j]}^-1 B[t][j] by CG (Alg. 1)."""
         self._check_stream()
         T, C, D = self.T, self.C, self.D
@@ -167,7 +167,7 @@ class Cmtcs:
             out["iters"] = torch.empty(T, R, dtype=torch.int32, device=self.device)
             out["status"] = torch.empty(T, R, dtype=torch.uint8, device=self.device)
             st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(), None, None)
-        o = self._opts(fixed_iters=fixed_iters, tol=tol, max_iters=max_iters)
+        o = self._opts(fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, graph=graph)
         _lib.check(_lib.load().cmtcs_solve(
             self._h, _ptr(alpha), R, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(B),
             _ptr(X), _ptr(g), _ptr(x), ctypes.byref(o),
@@ -231,7 +231,7 @@ class Cmtcs:
 
 
 def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
-        alpha_max=1e10, probes_fn=None, callback=None):
+        alpha_max=1e10, probes_fn=None, callback=None, graph=False):
     """CoFEM (Alg. 2): n_em iterations of E-step + M-step from alpha0, then a_t = argmax_c q_tc
     (lowest c on ties) and mu_{t, a_t} from the last E-step."""
     alpha = alpha0.clone()
@@ -239,7 +239,7 @@ def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, 
     for it in range(n_em):
         pr = None if probes_fn is None else probes_fn(it)
         out = model.estep(alpha, log_pi, K, fixed_iters=fixed_iters, tol=tol,
-                          max_iters=max_iters, seed=seed, em_iter=it, probes=pr)
+                          max_iters=max_iters, seed=seed, em_iter=it, probes=pr, graph=graph)
         if callback is not None:
             callback(it, alpha, out)
         model.mstep(out["mu"], out["s"], out["q"], alpha, alpha_max=alpha_max)

@@ -82,6 +82,18 @@ struct cmtcs_handle_s {
   int4* adj16_tiles = nullptr;
   int nfwd16 = 0, nadj16 = 0, max_np32 = 0;
 
+  // recorded CG loop (opts.graph)
+  hipStream_t cap_st = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  struct GraphKey {
+    const float* alpha; int R, Rp, steps, fixed, fwd_rows, adj_rows;
+    bool operator==(const GraphKey& o) const {
+      return alpha == o.alpha && R == o.R && Rp == o.Rp && steps == o.steps && fixed == o.fixed &&
+             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows;
+    }
+  } graph_key{};
+
   // kernel timing (cmtcs_profile)
   bool prof_on = false;
   hipEvent_t ev[kCheckEvery][4] = {};
@@ -106,6 +118,49 @@ struct cmtcs_handle_s {
     if (ev_made)
       for (auto& row : ev)
         for (auto& e : row) (void)hipEventDestroy(e);
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+  }
+
+  // Records the `steps` CG steps of run_cg as one graph (on a private stream: the caller's
+  // stream may be the null stream, which cannot be captured) and launches it on the handle's
+  // stream; the recording is reused while its key matches.
+  template <typename VT>
+  cmtcs_status_t run_cg_graph(const Geometry& g, const float* alpha, int steps, int fixed) {
+    const GraphKey key{alpha, g.R, g.Rp, steps, fixed, fwd_rows, adj_rows};
+    if (graph_exec == nullptr || !(key == graph_key)) {
+      if (graph_exec) { (void)hipGraphExecDestroy(graph_exec); graph_exec = nullptr; }
+      if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+      if (cap_st == nullptr)
+        HIP_TRY(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking), "hipStreamCreate");
+      HIP_TRY(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed),
+              "hipStreamBeginCapture");
+      const CgState s = cg();
+      hipError_t e = hipSuccess;
+      for (int u = 0; u < steps && e == hipSuccess; ++u) {
+        const int* act_u = act + (size_t)u * T;
+        e = launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, fwd_rows,
+                             cap_st);
+        if (e == hipSuccess)
+          e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
+                                alpha, colc, beta, act_u, adj_rows, cap_st);
+        if (e == hipSuccess) e = launch_cg_update<VT>(g, s, u, steps, fixed, 0, cap_st);
+      }
+      hipGraph_t gr = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cap_st, &gr);
+      if (e != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(e, "graph recording");
+      }
+      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+      graph = gr;
+      HIP_TRY(hipGraphInstantiate(&graph_exec, graph, nullptr, nullptr, 0),
+              "hipGraphInstantiate");
+      graph_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(graph_exec, st), "hipGraphLaunch");
+    return CMTCS_OK;
   }
 
   // Adds the durations of the `ev_pending` timed steps recorded so far.
@@ -148,7 +203,7 @@ struct cmtcs_handle_s {
     return s;
   }
 
-  int ngroups(int Rp) const { return (Rp / 16 + kColGroup - 1) / kColGroup; }
+  int ngroups(int Rp) const { return Rp / 16 / group_width(Rp); }
 
   // Tile tables and W offsets for Rp column slots per task (rebuilt only when Rp changes).
   cmtcs_status_t prepare(int Rp) {
@@ -328,7 +383,7 @@ struct cmtcs_handle_s {
   template <typename VT>
   cmtcs_status_t apply(const float* alpha, int R, const int32_t* col_cluster, const void* V,
                        void* AV) {
-    const int Rp = round16(R);
+    const int Rp = col_slots(R);
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(R, Rp);
@@ -350,7 +405,7 @@ struct cmtcs_handle_s {
   template <typename VT>
   cmtcs_status_t grad(int R, const int32_t* col_cluster, const void* Xs, const void* Lam,
                       double y_coef, float* dalpha, float* dphi) {
-    const int Rp = round16(2 * R);
+    const int Rp = col_slots(2 * R);
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(2 * R, Rp);
@@ -367,7 +422,7 @@ struct cmtcs_handle_s {
   cmtcs_status_t estep(const float* alpha, const double* log_pi, const cmtcs_opts_t& o,
                        float* mu, float* sd, double* logdet, double* ell, double* q,
                        cmtcs_cg_stats_t* stats) {
-    const int K = o.K, R = C * (K + 1), Rp = round16(R);
+    const int K = o.K, R = C * (K + 1), Rp = col_slots(R);
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(R, Rp);
@@ -380,7 +435,8 @@ struct cmtcs_handle_s {
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.key = key; src.probes = o.probes;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
-    rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
+    if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
+    else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key, o.probes, mu, sd, st),
             "launch(estep_finalize)");
@@ -406,7 +462,7 @@ struct cmtcs_handle_s {
   cmtcs_status_t solve(const float* alpha, int R, const int32_t* col_cluster, const void* B,
                        void* Xout, double* gout, double* xout, const cmtcs_opts_t& o,
                        cmtcs_cg_stats_t* stats) {
-    const int Rp = round16(R);
+    const int Rp = col_slots(R);
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(R, Rp);
@@ -418,7 +474,8 @@ struct cmtcs_handle_s {
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.key = 0; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
-    rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
+    if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
+    else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_solve_output<VT>(g, cg(), Xout, gout, xout, steps,
                                     stats ? stats->iters : nullptr,
@@ -492,7 +549,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   if (h == nullptr) return fail(CMTCS_E_NOMEM, "host allocation failed");
   h->T = p->T; h->C = p->C; h->D = p->D; h->beta = p->beta; h->math = p->math;
   h->max_rhs = p->max_rhs; h->max_iters = p->max_iters; h->max_K = p->max_K;
-  h->Rp_max = round16(p->max_rhs);
+  h->Rp_max = col_slots(p->max_rhs);
   h->vbytes = p->math == CMTCS_MATH_F64 ? 8 : 4;
   h->row_off.assign(p->row_off, p->row_off + p->T + 1);
   h->phi_dtype = p->phi_dtype;

@@ -106,7 +106,22 @@ struct Geometry {
 // Wave tiles of the two operator products, one int4 per tile:
 //   fwd  (W = Phi V):             {t, n0, column group, 0}
 //   adj  (A V = beta Phi^T W + alpha V): {t, d0, column group, 0}
-constexpr int kColGroup = 9;   // 16-column fragments per wave tile (144 columns)
+// A column group is up to kColGroup 16-column fragments (144 columns) held by one wave.  All
+// groups of a launch have the same width: with at most kColGroup fragments there is one group
+// of all of them; beyond that the column slots are padded to a multiple of kColGroup
+// fragments (zero columns), so that the products run one guard-free instantiation.
+constexpr int kColGroup = 9;
+// Column slots per task (a multiple of 16) for R right-hand sides.
+inline int col_slots(int R) {
+  const int frags = (R + 15) / 16;
+  if (frags <= kColGroup) return 16 * frags;
+  return 16 * kColGroup * ((frags + kColGroup - 1) / kColGroup);
+}
+// 16-column fragments per column group for Rp column slots.
+__host__ __device__ inline int group_width(int Rp) {
+  const int frags = Rp / 16;
+  return frags <= kColGroup ? frags : kColGroup;
+}
 
 // Launchers (k_operator.hip).  `act` is the [T] count of active right-hand sides for the
 // current step (tasks with a zero count are skipped) or null.  `rows` is the output rows per

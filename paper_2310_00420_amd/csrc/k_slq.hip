@@ -232,10 +232,14 @@ hipError_t launch_slq(const Geometry& g, const CgState& s, int K, int steps, dou
   if (P == 0) return hipSuccess;
   // 16 KB of LDS per block: a few probes per block and many blocks per CU, so that every SIMD
   // has several waves whose sequential QR chains hide each other's latency
+  // With few probes, LDS-resident tridiagonals in small blocks spread the probes over every
+  // SIMD; with many (more than fit on chip in one round), one probe per lane in full waves keeps
+  // more probes in flight at once and the global-memory layout wins.
   constexpr long kLdsBytes = 16 * 1024;
+  constexpr long kLdsMaxProbes = 16384;
   const long Um = steps > 0 ? steps : 1;
   const long PB = std::min<long>(64, kLdsBytes / (24 * Um));
-  if (PB >= 1) {
+  if (PB >= 1 && P <= kLdsMaxProbes) {
     hipLaunchKernelGGL(k_slq_lds, dim3((unsigned)((P + PB - 1) / PB)), dim3(64),
                        (size_t)(24 * PB * Um), st, s.gam, s.xi, s.iters, g.T, g.C, K, g.Rp,
                        pnorm2, tau, ok, rmin, rmax, (int)PB, (int)Um);
