@@ -136,7 +136,7 @@ struct cmtcs_handle_s {
         HIP_TRY(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking), "hipStreamCreate");
       HIP_TRY(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed),
               "hipStreamBeginCapture");
-      const CgState s = cg();
+      const CgState s = cg_loop(alpha);
       hipError_t e = hipSuccess;
       for (int u = 0; u < steps && e == hipSuccess; ++u) {
         const int* act_u = act + (size_t)u * T;
@@ -144,7 +144,7 @@ struct cmtcs_handle_s {
                              cap_st);
         if (e == hipSuccess)
           e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
-                                alpha, colc, beta, act_u, adj_rows, cap_st);
+                                nullptr, colc, beta, act_u, adj_rows, cap_st);
         if (e == hipSuccess) e = launch_cg_update<VT>(g, s, u, steps, fixed, 0, cap_st);
       }
       hipGraph_t gr = nullptr;
@@ -200,6 +200,16 @@ struct cmtcs_handle_s {
     s.X = X; s.Rv = Rv; s.Dv = Dv; s.AD = AD;
     s.rr = rr; s.thr = thr; s.state = state; s.iters = iters;
     s.gam = gam; s.xi = xi; s.act = act;
+    s.alpha = nullptr; s.colc = colc; s.beta = beta;
+    return s;
+  }
+
+  // State for the CG loop: with the FP64/FP32 products, the adjoint product stores the bare
+  // Phi^T Phi d and the update adds beta and the diagonal term; the 16-bit adjoint product
+  // forms the whole A d itself.
+  CgState cg_loop(const float* alpha) const {
+    CgState s = cg();
+    if (!mixed()) s.alpha = alpha;
     return s;
   }
 
@@ -288,7 +298,7 @@ struct cmtcs_handle_s {
                                  fwd_rows, st);
           else
             e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
-                                  (VT*)AD, alpha, colc, beta, nullptr, adj_rows, st);
+                                  (VT*)AD, nullptr, colc, beta, nullptr, adj_rows, st);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -327,7 +337,7 @@ struct cmtcs_handle_s {
   template <typename VT>
   cmtcs_status_t run_cg(const Geometry& g, const float* alpha, int steps, int fixed,
                         const RhsSource& src, int refine_every) {
-    const CgState s = cg();
+    const CgState s = cg_loop(alpha);
     const Geometry g16 = geom16(g.R, g.Rp);
     if (mixed()) HIP_TRY(round_direction(g), "launch(round16)");
     for (int u = 0; u < steps; ++u) {
@@ -345,7 +355,7 @@ struct cmtcs_handle_s {
         HIP_TRY(mixed_product(g16, alpha, act_u, 2), "launch(phit_w16)");
       else
         HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
-                                  (VT*)AD, alpha, colc, beta, act_u, adj_rows, st),
+                                  (VT*)AD, nullptr, colc, beta, act_u, adj_rows, st),
                 "launch(phit_w)");
       if (e4) HIP_TRY(hipEventRecord(e4[2], st), "hipEventRecord");
       const bool replace = mixed() && refine_every > 0 && (u + 1) % refine_every == 0;

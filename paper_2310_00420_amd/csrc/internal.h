@@ -129,6 +129,7 @@ __host__ __device__ inline int group_width(int Rp) {
 template <typename VT>
 hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                         const VT* V, VT* W, const int* act, int rows, hipStream_t st);
+// alpha == nullptr: AV = Phi^T W alone (beta and the diagonal term are left to the caller).
 template <typename VT>
 hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
@@ -146,6 +147,12 @@ struct CgState {
   double* gam;       // [max_iters][T*Rp]
   double* xi;        // [max_iters][T*Rp]
   int* act;          // [(max_iters+1)][T] active counts per step
+  // Diagonal term of the operator, applied by the CG update when alpha != nullptr: AD then
+  // holds the bare product Phi^T Phi d, and the update forms beta AD + alpha_{c(j)} (.) d
+  // itself (it reads d anyway).  nullptr: AD already holds A d.
+  const float* alpha;   // [C][D]
+  const int* colc;      // [T*Rp] cluster of each column
+  double beta;
 };
 // Source of the right-hand sides for cg_init.
 struct RhsSource {

@@ -81,13 +81,19 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
                                                   double* __restrict__ gam,
                                                   double* __restrict__ xi, int* __restrict__ act,
                                                   int u, int steps, int fixed, int T, int R,
-                                                  int Rp, int D, int split) {
+                                                  int Rp, int D, int split,
+                                                  const float* __restrict__ alpha,
+                                                  const int* __restrict__ colc, double beta) {
   __shared__ double sh[BS / 64];
   const int t = blockIdx.x / R, j = blockIdx.x % R;
   const int64_t idx = (int64_t)t * Rp + j;
   if (state[idx] != kActive) return;
   const double rr_old = rr[idx];   // read by every thread before thread 0 rewrites it
   const int64_t base = idx * D;
+  // with alpha given, AD holds Phi^T Phi d and A d = beta AD + alpha_c (.) d is formed here,
+  // with the same fused multiply-add as the product's own epilogue
+  const int c = alpha != nullptr ? colc[idx] : -1;
+  const float* al = alpha + (int64_t)(c >= 0 ? c : 0) * D;
   // all four vectors are loaded before the first reduction so that the r and x loads are in
   // flight while d.Ad is summed
   VT dv[EPT], av[EPT], rv[EPT], xv[EPT];
@@ -100,6 +106,10 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
       av[e] = AD[base + d];
       rv[e] = Rv[base + d];
       xv[e] = X[base + d];
+      if (alpha != nullptr) {
+        const VT a = c >= 0 ? (VT)al[d] : (VT)0;
+        av[e] = __builtin_fma((VT)beta, av[e], a * dv[e]);
+      }
       pd += (double)dv[e] * (double)av[e];
     } else {
       dv[e] = 0; av[e] = 0; rv[e] = 0; xv[e] = 0;
@@ -323,7 +333,8 @@ static hipError_t update_one(const Geometry& g, const CgState& s, int u, int ste
                              int split, hipStream_t st) {
   hipLaunchKernelGGL((k_cg_update<VT, BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, (VT*)s.X,
                      (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state, s.iters,
-                     s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split);
+                     s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split, s.alpha,
+                     s.colc, s.beta);
   return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 //   fwd:  W_t  = Phi_t V_t          W_t [Rp][np_t], contraction over d (both operands
 //                                    d-contiguous: Phi_t rows and V_t columns)
 //   adj:  AV_t = beta Phi_t^T W_t + alpha_{c(j)} (.) V_t     contraction over n
+//         (or the bare Phi_t^T W_t when no alpha is given: the CG update then adds beta and
+//         the diagonal term while it reads V_t anyway)
 //
 // Each wave owns one output tile (16*RF rows x up to 144 columns) and keeps the whole
 // contraction in accumulator registers.  Loads are 16-byte or wider: lane l of the wave reads
@@ -28,6 +30,10 @@ __device__ inline int xcd_block(int b, int nb) {
 
 // Output rows per wave tile (16 * RF) that the instantiations below support; the autotuner of
 // the host layer picks one per product.  FP64 tiles keep RF * 9 accumulators of 8 registers.
+// Waves (tiles) per workgroup.  Four measured faster than one on the FP64 tiles, although a
+// SIMD then starts its next tile only when all four waves of its group have ended.
+constexpr int kOpWaves = 4;
+
 int op_row_candidates(bool f64, int* rows) {
   if (f64) { rows[0] = 32; rows[1] = 16; }
   else { rows[0] = 64; rows[1] = 32; }
@@ -35,7 +41,7 @@ int op_row_candidates(bool f64, int* rows) {
 }
 
 template <typename VT, int RF>
-__global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
+__global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict__ phi,
                                                const int64_t* __restrict__ row_off,
                                                const int64_t* __restrict__ w_off,
                                                const int4* __restrict__ tiles, int ntiles,
@@ -47,7 +53,7 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
   const int i16 = lane & 15, g4 = lane >> 4;
   // tile fields are wave-uniform: keep them in scalar registers so that every branch on them
   // is a scalar branch, not an exec-mask branch around matrix-core instructions
-  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
+  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * kOpWaves + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int4 tl = tiles[tile];
   const int t = uniform(tl.x), n0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
@@ -58,14 +64,14 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
 
   const float* prow[RF];
-  bool pval[RF];
 #pragma unroll
   for (int rf = 0; rf < RF; ++rf) {
     // matrix row i16 of fragment rf is Phi row n0 + rf*16 + a_row(i16), so that the
-    // accumulator of lane (g4, r) holds the consecutive rows n0 + rf*16 + 4 g4 + r
+    // accumulator of lane (g4, r) holds the consecutive rows n0 + rf*16 + 4 g4 + r.  Rows past
+    // N_t read row 0 of the task instead; they only reach output rows past N_t, which the
+    // epilogue writes as zeros.
     const int row = n0 + rf * 16 + Mfma<VT>::a_row(i16);
-    pval[rf] = row < nt;
-    prow[rf] = phi + (r0 + (pval[rf] ? row : 0)) * (int64_t)D + 4 * g4;
+    prow[rf] = phi + (r0 + (row < nt ? row : 0)) * (int64_t)D + 4 * g4;
   }
   const VT* vbase = V + ((int64_t)t * Rp + cf0 * 16 + i16) * D + 4 * g4;
 
@@ -75,22 +81,27 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
 
-  // Software pipeline: the loads of chunk c+1 are issued before the matrix-core work of
-  // chunk c, so global-memory latency overlaps the MFMA chain (two register buffers).
+  // Software pipeline over chunks of 16 along d: the loads of chunk c+1 are issued before the
+  // matrix-core work of chunk c (two register buffers).  Every load is unconditional and no
+  // loaded value is touched before its MFMA, so the only wait per chunk is for the chunk about
+  // to be multiplied; a load past the last chunk re-reads the last chunk (in bounds, unused),
+  // and a missing column fragment re-reads the last present one.
+  const int nch = D / 16;
   f4 a0[RF], a1[RF];
   vt4 b0[kColGroup], b1[kColGroup];
-  auto load = [&](f4 (&a)[RF], vt4 (&b)[kColGroup], int d0) {
+  auto load = [&](f4 (&a)[RF], vt4 (&b)[kColGroup], int c, auto full)
+      __attribute__((always_inline)) {
+    const int d0 = min(c, nch - 1) * 16;
 #pragma unroll
-    for (int rf = 0; rf < RF; ++rf) {
-      // branch-free: rows past N_t read row 0 of the task (prow) and are dropped
-      const f4 v = *(const f4*)(prow[rf] + d0);
-      a[rf] = pval[rf] ? v : f4{0.f, 0.f, 0.f, 0.f};
+    for (int rf = 0; rf < RF; ++rf) a[rf] = *(const f4*)(prow[rf] + d0);
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
+      b[cf] = *(const vt4*)(vbase + (int64_t)f * 16 * D + d0);
     }
-#pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf)
-      if (cf < ncf) b[cf] = *(const vt4*)(vbase + (int64_t)cf * 16 * D + d0);
   };
-  auto mma = [&](const f4 (&a)[RF], const vt4 (&b)[kColGroup], auto full) {
+  auto mma = [&](const f4 (&a)[RF], const vt4 (&b)[kColGroup], auto full)
+      __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -100,14 +111,21 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
           for (int rf = 0; rf < RF; ++rf)
             acc[rf][cf] = Mfma<VT>::mma((VT)a[rf][s], b[cf][s], acc[rf][cf]);
   };
-  auto run = [&](auto full) {
-    load(a0, b0, 0);
-    for (int d0 = 0; d0 < D; d0 += 32) {
-      if (d0 + 16 < D) load(a1, b1, d0 + 16);
+  auto run = [&](auto full) __attribute__((always_inline)) {
+    load(a0, b0, 0, full);
+    for (int c = 0; c + 1 < nch; c += 2) {
+      // scheduling barriers between the stages: the compiler may neither sink a buffer's loads
+      // below the MFMAs they should overlap nor hoist its conversions up to its loads
+      load(a1, b1, c + 1, full);
+      __builtin_amdgcn_sched_barrier(0);
       mma(a0, b0, full);
-      if (d0 + 32 < D) load(a0, b0, d0 + 32);
-      if (d0 + 16 < D) mma(a1, b1, full);
+      __builtin_amdgcn_sched_barrier(0);
+      load(a0, b0, c + 2, full);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a1, b1, full);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (nch & 1) mma(a0, b0, full);   // odd chunk count: the last chunk is in buffer 0
   };
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
   else run(std::false_type{});
@@ -121,15 +139,17 @@ __global__ __launch_bounds__(256) void k_phi_v(const float* __restrict__ phi,
     for (int cf = 0; cf < kColGroup; ++cf) {
       if (cf >= ncf) continue;
       const int j = (cf0 + cf) * 16 + i16;
+      // rows N_t..np-1 of W are zero: the adjoint product contracts over them
       vt4 o;
-      o[0] = acc[rf][cf][0]; o[1] = acc[rf][cf][1]; o[2] = acc[rf][cf][2]; o[3] = acc[rf][cf][3];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = rb + 4 * g4 + r < nt ? (VT)acc[rf][cf][r] : (VT)0;
       *(vt4*)(Wt + (int64_t)j * np + rb + 4 * g4) = o;
     }
   }
 }
 
 template <typename VT, int RF>
-__global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
+__global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restrict__ phi,
                                                 const int64_t* __restrict__ row_off,
                                                 const int64_t* __restrict__ w_off,
                                                 const int4* __restrict__ tiles, int ntiles,
@@ -144,7 +164,7 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
   typedef typename VecOf<VT, RF>::type vrf;
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
-  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
+  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * kOpWaves + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int4 tl = tiles[tile];
   const int t = uniform(tl.x), d0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
@@ -164,23 +184,28 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
 
-  // Software pipeline as in k_phi_v: loads of chunk c+1 overlap the MFMAs of chunk c.
+  // Software pipeline as in k_phi_v, over chunks of 16 along n.  Rows past N_t read row 0 of
+  // the task: they meet rows of W that the forward product wrote as zeros.  Lanes past D read
+  // column 0 and feed only output rows that are not stored.
+  const int nch = np / 16;
   frf a0[4], a1[4];
   vt4 b0[kColGroup], b1[kColGroup];
-  auto load = [&](frf (&a)[4], vt4 (&b)[kColGroup], int nb) {
+  auto load = [&](frf (&a)[4], vt4 (&b)[kColGroup], int c, auto full)
+      __attribute__((always_inline)) {
+    const int nb = min(c, nch - 1) * 16;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      // branch-free: rows past N_t (or lanes past D) read row 0 of the task and drop it
       const int n = nb + 4 * g4 + s;
-      const bool ok = dval && n < nt;
-      const frf v = *(const frf*)(pbase + (ok ? (int64_t)n * D : 0));
-      a[s] = ok ? v : frf{};
+      a[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
     }
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf)
-      if (cf < ncf) b[cf] = *(const vt4*)(wbase + (int64_t)cf * 16 * np + nb);
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
+      b[cf] = *(const vt4*)(wbase + (int64_t)f * 16 * np + nb);
+    }
   };
-  auto mma = [&](const frf (&a)[4], const vt4 (&b)[kColGroup], auto full) {
+  auto mma = [&](const frf (&a)[4], const vt4 (&b)[kColGroup], auto full)
+      __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -193,18 +218,49 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
             acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], acc[f][cf]);
           }
   };
-  auto run = [&](auto full) {
-    if (np > 0) load(a0, b0, 0);
-    for (int nb = 0; nb < np; nb += 32) {
-      if (nb + 16 < np) load(a1, b1, nb + 16);
+  auto run = [&](auto full) __attribute__((always_inline)) {
+    if (nch == 0) return;   // empty task: A V = alpha (.) V
+    load(a0, b0, 0, full);
+    for (int c = 0; c + 1 < nch; c += 2) {
+      // scheduling barriers between the stages: the compiler may neither sink a buffer's loads
+      // below the MFMAs they should overlap nor hoist its conversions up to its loads
+      load(a1, b1, c + 1, full);
+      __builtin_amdgcn_sched_barrier(0);
       mma(a0, b0, full);
-      if (nb + 32 < np) load(a0, b0, nb + 32);
-      if (nb + 16 < np) mma(a1, b1, full);
+      __builtin_amdgcn_sched_barrier(0);
+      load(a0, b0, c + 2, full);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a1, b1, full);
+      __builtin_amdgcn_sched_barrier(0);
     }
+    if (nch & 1) mma(a0, b0, full);   // odd chunk count: the last chunk is in buffer 0
   };
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
   else run(std::false_type{});
 
+  if (alpha == nullptr) {
+    // bare product Phi^T W (the CG update adds beta and the diagonal term): stores only, so
+    // the epilogue issues no load and never waits on memory
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      if (cf >= ncf) continue;
+      const int64_t col = ((int64_t)t * Rp + (cf0 + cf) * 16 + i16) * D;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int d = d0 + RF * Mfma<VT>::out_row(g4, r);
+        if (d >= D) continue;
+        if constexpr (RF == 1) {
+          AV[col + d] = acc[0][cf][r];
+        } else {
+          vrf o;
+#pragma unroll
+          for (int f = 0; f < RF; ++f) o[f] = acc[f][cf][r];
+          *(vrf*)(AV + col + d) = o;
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int cf = 0; cf < kColGroup; ++cf) {
     if (cf >= ncf) continue;
@@ -240,7 +296,7 @@ __global__ __launch_bounds__(256) void k_phit_w(const float* __restrict__ phi,
 template <typename VT, int RF>
 static hipError_t phi_v_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                            const VT* V, VT* W, const int* act, hipStream_t st) {
-  hipLaunchKernelGGL((k_phi_v<VT, RF>), dim3((ntiles + 3) / 4), dim3(256), 0, st, phi,
+  hipLaunchKernelGGL((k_phi_v<VT, RF>), dim3((ntiles + kOpWaves - 1) / kOpWaves), dim3(64 * kOpWaves), 0, st, phi,
                      g.row_off, g.w_off, tiles, ntiles, V, W, act, g.D, g.Rp);
   return hipGetLastError();
 }
@@ -249,7 +305,7 @@ template <typename VT, int RF>
 static hipError_t phit_w_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                             const VT* W, const VT* V, VT* AV, const float* alpha,
                             const int* colc, double beta, const int* act, hipStream_t st) {
-  hipLaunchKernelGGL((k_phit_w<VT, RF>), dim3((ntiles + 3) / 4), dim3(256), 0, st, phi,
+  hipLaunchKernelGGL((k_phit_w<VT, RF>), dim3((ntiles + kOpWaves - 1) / kOpWaves), dim3(64 * kOpWaves), 0, st, phi,
                      g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
                      g.Rp);
   return hipGetLastError();

@@ -33,6 +33,7 @@ def _ref_apply(w, alpha, V, cc):
     dict(T=3, C=2, D=64, N=32, R=5),                       # one tile, padded columns
     dict(T=4, C=3, D=208, N=[0, 17, 70, 129], R=37),      # ragged rows, partial tiles
     dict(T=2, C=4, D=512, N=256, R=150),                   # two column groups
+    dict(T=4, C=1, D=48, N=[5, 16, 33, 1], R=9),           # one-chunk tasks, odd chunk count
 ])
 def test_apply(math, tol, shape):
     shape = dict(shape)
