@@ -605,9 +605,10 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->colc, sizeof(int) * T * (Rpm + (size_t)h->max_rhs));   // [T][Rp] + map staging
   A(&h->fwd_tiles, sizeof(int4) * fwd_max);
   A(&h->adj_tiles, sizeof(int4) * adj_max);
-  A(&h->dg, sizeof(double) * it * P);
-  A(&h->of, sizeof(double) * it * P);
-  A(&h->zz, sizeof(double) * it * P);
+  // SLQ tridiagonals [u][probe], u = 0..max_iters (the last row is the eigensolver's scratch)
+  A(&h->dg, sizeof(double) * (it + 1) * P);
+  A(&h->of, sizeof(double) * (it + 1) * P);
+  A(&h->zz, sizeof(double) * (it + 1) * P);
   A(&h->tau, sizeof(double) * P);
   A(&h->rmin, sizeof(double) * P);
   A(&h->rmax, sizeof(double) * P);

@@ -16,57 +16,66 @@
 // [u][probe] so that the 64 lanes of a wave touch consecutive addresses.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
 namespace cmtcs {
 
-// Eigenvalues (left in dg) and first eigenvector components (left in zz, which must enter as
-// e_1) of the symmetric tridiagonal with diagonal dg[0..n-1] and off-diagonal of[0..n-2];
-// element i of each array is at index i * stride (index type I: int for on-chip arrays).
-// Returns 0 on success, 1 if the sweep limit was reached.
-// Within a sweep, the entries a rotation has just updated at position k+1 are exactly the ones
-// the next rotation reads, so they are carried in registers: each rotation loads only the
-// untouched entries at k+1 (and k+2 for the bulge) and stores its finished entries at k.
 // Reciprocal square root of r2 > 0 for the Givens rotations.  On the device: the hardware
-// estimate refined by two Newton steps (y <- y (3 - r2 y^2) / 2, each roughly squaring the
-// relative error), accurate to a few ulp, which is all a rotation needs (cs^2 + sn^2 = 1).
+// estimate y0 refined by one third-order step, y = y0 (1 + e/2 + 3 e^2/8) with
+// e = 1 - r2 y0^2 (the series of (1 - e)^(-1/2)), which cubes the relative error of the
+// estimate; four dependent operations where two Newton steps take six, and the rotation's
+// dependent chain is what bounds this kernel.
 struct RsqDevice {
   __device__ double operator()(double r2) const {
-    double y = __builtin_amdgcn_rsq(r2);
-    y = y * (1.5 - 0.5 * r2 * y * y);
-    y = y * (1.5 - 0.5 * r2 * y * y);
-    return y;
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = __builtin_fma(-r2, y0 * y0, 1.0);
+    const double p = __builtin_fma(0.375, e, 0.5);
+    return __builtin_fma(y0 * e, p, y0);
   }
 };
-// The same on the host (used by host-side checks of this routine).
+// The same on the host (for host builds of this routine, which the tests compile).
 struct RsqHost {
   __host__ double operator()(double r2) const { return 1.0 / std::sqrt(r2); }
 };
 
+// Eigenvalues (left in dg) and first eigenvector components (left in zz, which must enter as
+// e_1) of the symmetric tridiagonal with diagonal dg[0..n-1] and off-diagonal of[0..n-2];
+// element i of each array is at index i * stride (index type I: int for on-chip arrays).
+// Each array must provide n + 1 entries: entry n (and of[n-1]) is scratch that a sweep may read
+// ahead or write and never uses.  Returns 0 on success, 1 if the sweep limit was reached.
+//
+// The routine runs one probe per thread, and a wave executes the union of its lanes' control
+// paths, so every branch is kept short: the bottom deflations run in their own small loop (so
+// that each round of the outer loop is one sweep for every lane that is not done), the scan for
+// the block start tests four off-diagonals per round, and the rotation loop has no branch.
 template <typename I, typename Rsq>
 __host__ __device__ inline int tridiag_eig_first_row(double* dg, double* of, double* zz, int n,
                                                      I stride, int max_sweeps, Rsq rsq) {
   const double eps = 2.220446049250313e-16;
+  // off-diagonal j is negligible against its two diagonal neighbours
+  auto small = [&](int j) __attribute__((always_inline)) {
+    return fabs(of[(I)j * stride]) <=
+           eps * (fabs(dg[(I)j * stride]) + fabs(dg[(I)(j + 1) * stride]));
+  };
   int hi = n - 1;
   int sweeps = 0;
-  while (hi > 0) {
-    const double e_hi = of[(I)(hi - 1) * stride];
-    if (fabs(e_hi) <= eps * (fabs(dg[(I)(hi - 1) * stride]) + fabs(dg[(I)hi * stride]))) {
+  while (true) {
+    while (hi > 0 && small(hi - 1)) {
       of[(I)(hi - 1) * stride] = 0.0;
       --hi;
-      continue;
     }
+    if (hi <= 0) break;
     // start of the unreduced block that ends at hi
     int lo = hi - 1;
-    while (lo > 0) {
-      const double e = of[(I)(lo - 1) * stride];
-      if (fabs(e) <= eps * (fabs(dg[(I)(lo - 1) * stride]) + fabs(dg[(I)lo * stride]))) {
-        of[(I)(lo - 1) * stride] = 0.0;
-        break;
-      }
-      --lo;
+    while (lo >= 4) {
+      const bool s1 = small(lo - 1), s2 = small(lo - 2), s3 = small(lo - 3), s4 = small(lo - 4);
+      if (s1 || s2 || s3 || s4) break;
+      lo -= 4;
     }
+    while (lo > 0 && !small(lo - 1)) --lo;
+    if (lo > 0) of[(I)(lo - 1) * stride] = 0.0;
     if (++sweeps > max_sweeps) return 1;
     // Wilkinson shift: the eigenvalue of the trailing 2x2 block nearer its last diagonal entry
     const double a = dg[(I)(hi - 1) * stride], bq = of[(I)(hi - 1) * stride];
@@ -74,40 +83,47 @@ __host__ __device__ inline int tridiag_eig_first_row(double* dg, double* of, dou
     const double delta = 0.5 * (a - cq);
     const double den = delta + copysign(hypot(delta, bq), delta);
     const double mu = cq - bq * bq / den;
-    // bulge chase: rotations in planes (k, k+1), k = lo..hi-1
+    // Bulge chase: rotations in planes (k, k+1), k = lo..hi-1.  Rotation k writes positions
+    // k-1 and k only, so the untouched entries at k+2 that the next rotation needs are loaded
+    // one rotation ahead (up to position hi+1 <= n, the scratch entry at the end); the
+    // off-diagonal read past the block end only feeds values the last rotation discards.  The
+    // first rotation is peeled: it has no finished off-diagonal to store.
     double a0 = dg[(I)lo * stride], b0 = of[(I)lo * stride], z0 = zz[(I)lo * stride];
+    double a1 = dg[(I)(lo + 1) * stride], z1 = zz[(I)(lo + 1) * stride];
+    double b1 = of[(I)(lo + 1) * stride];
     double x = a0 - mu;
     double y = b0;
-    for (int k = lo; k < hi; ++k) {
-      const double a1 = dg[(I)(k + 1) * stride];
-      const double z1 = zz[(I)(k + 1) * stride];
-      const double b1 = (k + 1 < hi) ? of[(I)(k + 1) * stride] : 0.0;
-      // Givens rotation zeroing y against x.  The entries are eigenvalue-sized (CG step
-      // sizes of a positive definite system), far from FP64 overflow, so r needs no scaling;
-      // one reciprocal square root keeps the dependent chain of a step short.
+    auto rotate = [&](int k, auto first) __attribute__((always_inline)) {
+      const double a2 = dg[(I)(k + 2) * stride], z2 = zz[(I)(k + 2) * stride];
+      const double b2 = of[(I)(k + 2) * stride];
+      // Givens rotation (cs, sn) = (x, y) / r zeroing y against x.  The entries are
+      // eigenvalue-sized (CG step sizes of a positive definite system), far from FP64
+      // overflow, so r needs no scaling.  The next x, the new off-diagonal
+      //   nb = cs sn (a1 - a0) + (cs^2 - sn^2) b0 = [x y (a1 - a0) + (x - y)(x + y) b0] / r^2,
+      // takes its bracket from values known before the rotation, so that the chain from one
+      // rotation's x to the next runs through r^2, one reciprocal square root and two
+      // products only.  r2 = 0 (x = y = 0) keeps the identity rotation.
       const double r2 = x * x + y * y;
-      double cs = 1.0, sn = 0.0, r = 0.0;
-      if (r2 > 0.0) {
-        const double inv = rsq(r2);
-        r = r2 * inv;
-        cs = x * inv;
-        sn = y * inv;
-      }
-      if (k > lo) of[(I)(k - 1) * stride] = r;
+      const double num = (x * y) * (a1 - a0) + ((x - y) * (x + y)) * b0;
+      const double inv = rsq(fmax(r2, 1e-300));
+      const double cs = r2 > 0.0 ? x * inv : 1.0;
+      const double sn = y * inv;   // y = 0 when r2 = 0
+      if constexpr (!decltype(first)::value) of[(I)(k - 1) * stride] = r2 * inv;
+      const double nb = (num * inv) * inv;
       const double na0 = cs * cs * a0 + 2.0 * cs * sn * b0 + sn * sn * a1;
       const double na1 = sn * sn * a0 - 2.0 * cs * sn * b0 + cs * cs * a1;
-      const double nb = cs * sn * (a1 - a0) + (cs * cs - sn * sn) * b0;
       dg[(I)k * stride] = na0;
       of[(I)k * stride] = nb;
       zz[(I)k * stride] = cs * z0 + sn * z1;
       z0 = -sn * z0 + cs * z1;
       a0 = na1;
-      if (k + 1 < hi) {
-        y = sn * b1;      // bulge at (k+2, k)
-        b0 = cs * b1;     // off-diagonal (k+1, k+2) after this rotation
-        x = nb;
-      }
-    }
+      y = (y * inv) * b1;   // bulge at (k+2, k): sn b1
+      b0 = cs * b1;         // off-diagonal (k+1, k+2) after this rotation
+      x = nb;
+      a1 = a2; z1 = z2; b1 = b2;
+    };
+    rotate(lo, std::true_type{});
+    for (int k = lo + 1; k < hi; ++k) rotate(k, std::false_type{});
     dg[(I)hi * stride] = a0;
     zz[(I)hi * stride] = z0;
   }
@@ -166,7 +182,8 @@ __global__ __launch_bounds__(64) void k_slq(const double* __restrict__ gam,
 }
 
 // The same computation with each probe's three arrays in LDS: PB probes per block (one
-// thread each), arrays laid out [u][probe] in dynamic shared memory of 3 * PB * Um doubles.
+// thread each), arrays laid out [u][probe] in dynamic shared memory of 3 * PB * (Um + 1)
+// doubles.
 // Keeping the O(U) working set of a probe on chip removes the global-memory round trips of
 // the QR sweeps, which otherwise dominate this kernel.
 __global__ __launch_bounds__(64) void k_slq_lds(const double* __restrict__ gam,
@@ -193,9 +210,10 @@ __global__ __launch_bounds__(64) void k_slq_lds(const double* __restrict__ gam,
     tau[p] = 0.0; ok[p] = 0; rmin[p] = NAN; rmax[p] = NAN;
     return;
   }
+  // Um + 1 positions per array: the eigensolver's scratch entry follows the last step
   double* dg = sm + lp;
-  double* of = sm + (long)PB * Um + lp;
-  double* zz = sm + 2L * PB * Um + lp;
+  double* of = sm + (long)PB * (Um + 1) + lp;
+  double* zz = sm + 2L * PB * (Um + 1) + lp;
   double gprev = 1.0, xprev = 0.0;
   for (int u = 0; u < n; ++u) {
     const double g = gam[(long)u * ncol + idx];
@@ -230,18 +248,18 @@ hipError_t launch_slq(const Geometry& g, const CgState& s, int K, int steps, dou
                       double* rmax, hipStream_t st) {
   const long P = (long)g.T * g.C * K;
   if (P == 0) return hipSuccess;
-  // 16 KB of LDS per block: a few probes per block and many blocks per CU, so that every SIMD
-  // has several waves whose sequential QR chains hide each other's latency
-  // With few probes, LDS-resident tridiagonals in small blocks spread the probes over every
-  // SIMD; with many (more than fit on chip in one round), one probe per lane in full waves keeps
-  // more probes in flight at once and the global-memory layout wins.
-  constexpr long kLdsBytes = 16 * 1024;
+  // The QR sweeps are bound by instruction issue: a wave pays for every instruction whatever
+  // number of its lanes hold a probe.  Up to 40 KB of LDS per one-wave block (four blocks per
+  // CU, one per SIMD) holds as many probes per wave as fit; with many probes (more than fit
+  // on chip in one round), one probe per lane in full waves with the global-memory layout
+  // needs fewer rounds and wins.
+  constexpr long kLdsBytes = 40 * 1024;
   constexpr long kLdsMaxProbes = 16384;
   const long Um = steps > 0 ? steps : 1;
-  const long PB = std::min<long>(64, kLdsBytes / (24 * Um));
+  const long PB = std::min<long>(64, kLdsBytes / (24 * (Um + 1)));
   if (PB >= 1 && P <= kLdsMaxProbes) {
     hipLaunchKernelGGL(k_slq_lds, dim3((unsigned)((P + PB - 1) / PB)), dim3(64),
-                       (size_t)(24 * PB * Um), st, s.gam, s.xi, s.iters, g.T, g.C, K, g.Rp,
+                       (size_t)(24 * PB * (Um + 1)), st, s.gam, s.xi, s.iters, g.T, g.C, K, g.Rp,
                        pnorm2, tau, ok, rmin, rmax, (int)PB, (int)Um);
     return hipGetLastError();
   }
