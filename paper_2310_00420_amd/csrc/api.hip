@@ -204,12 +204,11 @@ struct cmtcs_handle_s {
     return s;
   }
 
-  // State for the CG loop: with the FP64/FP32 products, the adjoint product stores the bare
-  // Phi^T Phi d and the update adds beta and the diagonal term; the 16-bit adjoint product
-  // forms the whole A d itself.
+  // State for the CG loop: the adjoint product (FP64, FP32 or 16-bit) stores the bare
+  // Phi^T Phi d and the update adds beta and the diagonal term.
   CgState cg_loop(const float* alpha) const {
     CgState s = cg();
-    if (!mixed()) s.alpha = alpha;
+    s.alpha = alpha;
     return s;
   }
 
@@ -316,7 +315,8 @@ struct cmtcs_handle_s {
   }
 
   // Runs CG steps until every right-hand side has stopped or `steps` steps are done.
-  // 16-bit products of one step (MATH_MIXED); which = 1: Phi V16, 2: Phi^T W16 + alpha V.
+  // 16-bit products of one step (MATH_MIXED); which = 1: Phi V16, 2: Phi^T W16 (+ beta and
+  // alpha V when alpha is given; the CG loop passes none and the update adds them).
   hipError_t mixed_product(const Geometry& g16, const float* alpha, const int* act_u,
                            int which) {
     if (phi_dtype == CMTCS_BF16)
@@ -352,7 +352,7 @@ struct cmtcs_handle_s {
                 "launch(phi_v)");
       if (e4) HIP_TRY(hipEventRecord(e4[1], st), "hipEventRecord");
       if (mixed())
-        HIP_TRY(mixed_product(g16, alpha, act_u, 2), "launch(phit_w16)");
+        HIP_TRY(mixed_product(g16, nullptr, act_u, 2), "launch(phit_w16)");
       else
         HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
                                   (VT*)AD, nullptr, colc, beta, act_u, adj_rows, st),

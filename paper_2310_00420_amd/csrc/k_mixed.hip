@@ -13,6 +13,8 @@
 // np_t = N_t rounded up to 32; W16_t is [Rp][np_t] with zero rows beyond N_t.
 // The true residual b - A x that replaces the recursive residual every m steps is computed by
 // the FP32 kernels of k_operator.hip from the FP32 copy of Phi.
+#include <type_traits>
+
 #include "internal.h"
 #include "../../include/cmtcs.h"
 
@@ -40,35 +42,54 @@ __device__ inline int xcd_block16(int b, int nb) {
 constexpr int kRF16 = kRows16 / 16;   // 64 output rows per wave tile
 
 // Shared main loop: acc[rf][cf] += M[rows of rf][k] * V[cols of cf][k] over k in [0, K), K a
-// multiple of 32.  mrow[rf] points at row (tile row rf*16 + i16) + 8*g4 (null: zero row);
-// vcol points at column (cf0*16 + i16) + 8*g4, columns vld elements apart.
+// multiple of 32.  mrow[rf] points at row (tile row rf*16 + i16) + 8*g4 (a row past the end of
+// M points at a valid row instead, and the caller drops its outputs); vcol points at column
+// (cf0*16 + i16) + 8*g4, columns vld elements apart.  As in the FP64/FP32 products, every load
+// is unconditional (chunk index clamped, a missing column fragment re-reads the last present
+// one) and no loaded value is touched before its MFMA, so each chunk waits only for the buffer
+// it multiplies.
 template <typename T16>
 __device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* const (&mrow)[kRF16],
                                      const T16* vcol, int64_t vld, int ncf, int K) {
   typedef typename Mfma16<T16>::v8 v8;
+  const int nch = K / 32;
+  if (nch == 0) return;
   v8 a0[kRF16], a1[kRF16], b0[kColGroup], b1[kColGroup];
-  auto load = [&](v8 (&a)[kRF16], v8 (&b)[kColGroup], int k0) {
+  auto load = [&](v8 (&a)[kRF16], v8 (&b)[kColGroup], int c, auto full)
+      __attribute__((always_inline)) {
+    const int k0 = min(c, nch - 1) * 32;
 #pragma unroll
-    for (int rf = 0; rf < kRF16; ++rf)
-      a[rf] = mrow[rf] != nullptr ? *(const v8*)(mrow[rf] + k0) : v8{};
+    for (int rf = 0; rf < kRF16; ++rf) a[rf] = *(const v8*)(mrow[rf] + k0);
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf)
-      if (cf < ncf) b[cf] = *(const v8*)(vcol + (int64_t)cf * 16 * vld + k0);
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
+      b[cf] = *(const v8*)(vcol + (int64_t)f * 16 * vld + k0);
+    }
   };
-  auto mma = [&](const v8 (&a)[kRF16], const v8 (&b)[kColGroup]) {
+  auto mma = [&](const v8 (&a)[kRF16], const v8 (&b)[kColGroup], auto full)
+      __attribute__((always_inline)) {
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
-      if (cf < ncf)
+      if (decltype(full)::value || cf < ncf)
 #pragma unroll
         for (int rf = 0; rf < kRF16; ++rf) acc[rf][cf] = Mfma16<T16>::mma(a[rf], b[cf], acc[rf][cf]);
   };
-  if (K > 0) load(a0, b0, 0);
-  for (int k0 = 0; k0 < K; k0 += 64) {
-    if (k0 + 32 < K) load(a1, b1, k0 + 32);
-    mma(a0, b0);
-    if (k0 + 64 < K) load(a0, b0, k0 + 64);
-    if (k0 + 32 < K) mma(a1, b1);
-  }
+  auto run = [&](auto full) __attribute__((always_inline)) {
+    load(a0, b0, 0, full);
+    for (int c = 0; c + 1 < nch; c += 2) {
+      load(a1, b1, c + 1, full);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a0, b0, full);
+      __builtin_amdgcn_sched_barrier(0);
+      load(a0, b0, c + 2, full);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a1, b1, full);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (nch & 1) mma(a0, b0, full);   // odd chunk count: the last chunk is in buffer 0
+  };
+  if (ncf == kColGroup) run(std::true_type{});
+  else run(std::false_type{});
 }
 
 // W16_t = round16(Phi16_t V16_t): tile {t, n0, column group}.
@@ -81,20 +102,21 @@ __global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
                                                  T16* __restrict__ W16,
                                                  const int* __restrict__ act, int D, int Rp) {
   const int lane = threadIdx.x & 63, i16 = lane & 15, g4 = lane >> 4;
-  const int tile = xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int tile = uniform(xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int4 tl = tiles[tile];
-  const int t = tl.x, n0 = tl.y, cf0 = tl.z * kColGroup;
+  const int t = uniform(tl.x), n0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
   if (act != nullptr && act[t] == 0) return;
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w16_off[t + 1] - w16_off[t]) / Rp);
-  const int ncf = min(kColGroup, Rp / 16 - cf0);
+  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  // rows past N_t read row 0 of the task; the epilogue writes their outputs as zeros
   const T16* mrow[kRF16];
 #pragma unroll
   for (int rf = 0; rf < kRF16; ++rf) {
     const int row = n0 + rf * 16 + i16;
-    mrow[rf] = row < nt ? phi16 + (r0 + row) * (int64_t)D + 8 * g4 : nullptr;
+    mrow[rf] = phi16 + (r0 + (row < nt ? row : 0)) * (int64_t)D + 8 * g4;
   }
   const T16* vcol = V16 + ((int64_t)t * Rp + cf0 * 16 + i16) * D + 8 * g4;
   f4 acc[kRF16][kColGroup];
@@ -115,13 +137,14 @@ __global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
       const int j = (cf0 + cf) * 16 + i16;
       t4 o;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) o[r] = (T16)acc[rf][cf][r];
+      for (int r = 0; r < 4; ++r) o[r] = rb + 4 * g4 + r < nt ? (T16)acc[rf][cf][r] : (T16)0.f;
       *(t4*)(Wt + (int64_t)j * np + rb + 4 * g4) = o;
     }
   }
 }
 
-// AV_t = beta PhiT16_t W16_t + alpha_{c(j)} (.) V_t: tile {t, d0, column group}.
+// AV_t = beta PhiT16_t W16_t + alpha_{c(j)} (.) V_t: tile {t, d0, column group}; with no alpha,
+// the bare PhiT16_t W16_t (the CG update then adds beta and the diagonal term).
 template <typename T16>
 __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16,
                                                   const int64_t* __restrict__ w16_off,
@@ -133,20 +156,21 @@ __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16
                                                   const int* __restrict__ colc, double beta,
                                                   const int* __restrict__ act, int D, int Rp) {
   const int lane = threadIdx.x & 63, i16 = lane & 15, g4 = lane >> 4;
-  const int tile = xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+  const int tile = uniform(xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int4 tl = tiles[tile];
-  const int t = tl.x, d0 = tl.y, cf0 = tl.z * kColGroup;
+  const int t = uniform(tl.x), d0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
   if (act != nullptr && act[t] == 0) return;
   const int64_t wo = w16_off[t];
   const int np = (int)((w16_off[t + 1] - wo) / Rp);
-  const int ncf = min(kColGroup, Rp / 16 - cf0);
+  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
   const T16* M = phiT16 + (wo / Rp) * (int64_t)D;
+  // rows past D read row 0; their outputs are not stored
   const T16* mrow[kRF16];
 #pragma unroll
   for (int rf = 0; rf < kRF16; ++rf) {
     const int row = d0 + rf * 16 + i16;
-    mrow[rf] = row < D ? M + (int64_t)row * np + 8 * g4 : nullptr;
+    mrow[rf] = M + (int64_t)(row < D ? row : 0) * np + 8 * g4;
   }
   const T16* vcol = W16 + wo + (int64_t)(cf0 * 16 + i16) * np + 8 * g4;
   f4 acc[kRF16][kColGroup];
@@ -155,6 +179,19 @@ __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = f4{0.f, 0.f, 0.f, 0.f};
   nt16_mainloop<T16>(acc, mrow, vcol, np, ncf, np);
+  if (alpha == nullptr) {   // bare product: stores only
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      if (cf >= ncf) continue;
+      const int64_t col = ((int64_t)t * Rp + (cf0 + cf) * 16 + i16) * D;
+#pragma unroll
+      for (int rf = 0; rf < kRF16; ++rf) {
+        const int d = d0 + rf * 16 + 4 * g4;
+        if (d < D) *(f4*)(AV + col + d) = acc[rf][cf];
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int cf = 0; cf < kColGroup; ++cf) {
     if (cf >= ncf) continue;
