@@ -81,26 +81,31 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
 
-  // Software pipeline over chunks of 16 along d: the loads of chunk c+1 are issued before the
-  // matrix-core work of chunk c (two register buffers).  Every load is unconditional and no
-  // loaded value is touched before its MFMA, so the only wait per chunk is for the chunk about
-  // to be multiplied; a load past the last chunk re-reads the last chunk (in bounds, unused),
-  // and a missing column fragment re-reads the last present one.
+  // Software pipeline over chunks of 16 along d.  The Phi operand streams from HBM (it misses
+  // L2 every time), so it is prefetched three chunks ahead in a ring of four register buffers;
+  // the right-hand-side block comes from L2 and is double-buffered one chunk ahead.  Every load
+  // is unconditional and no loaded value is touched before its MFMA; a load past the last chunk
+  // re-reads the last chunk (in bounds, unused) and a missing column fragment re-reads the last
+  // present one.  In each slot the right-hand-side loads are issued before the Phi loads: the
+  // memory counter completes in issue order, so waiting for a chunk's right-hand side then
+  // does not also wait for the Phi loads of later chunks.
   const int nch = D / 16;
-  f4 a0[RF], a1[RF];
+  f4 a[4][RF];
   vt4 b0[kColGroup], b1[kColGroup];
-  auto load = [&](f4 (&a)[RF], vt4 (&b)[kColGroup], int c, auto full)
-      __attribute__((always_inline)) {
+  auto load_a = [&](f4 (&x)[RF], int c) __attribute__((always_inline)) {
     const int d0 = min(c, nch - 1) * 16;
 #pragma unroll
-    for (int rf = 0; rf < RF; ++rf) a[rf] = *(const f4*)(prow[rf] + d0);
+    for (int rf = 0; rf < RF; ++rf) x[rf] = *(const f4*)(prow[rf] + d0);
+  };
+  auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
+    const int d0 = min(c, nch - 1) * 16;
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
       const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      b[cf] = *(const vt4*)(vbase + (int64_t)f * 16 * D + d0);
+      x[cf] = *(const vt4*)(vbase + (int64_t)f * 16 * D + d0);
     }
   };
-  auto mma = [&](const f4 (&a)[RF], const vt4 (&b)[kColGroup], auto full)
+  auto mma = [&](const f4 (&x)[RF], const vt4 (&y)[kColGroup], auto full)
       __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -109,23 +114,44 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
         if (decltype(full)::value || cf < ncf)
 #pragma unroll
           for (int rf = 0; rf < RF; ++rf)
-            acc[rf][cf] = Mfma<VT>::mma((VT)a[rf][s], b[cf][s], acc[rf][cf]);
+            acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], y[cf][s], acc[rf][cf]);
   };
   auto run = [&](auto full) __attribute__((always_inline)) {
-    load(a0, b0, 0, full);
-    for (int c = 0; c + 1 < nch; c += 2) {
-      // scheduling barriers between the stages: the compiler may neither sink a buffer's loads
-      // below the MFMAs they should overlap nor hoist its conversions up to its loads
-      load(a1, b1, c + 1, full);
+    load_b(b0, 0, full);
+    load_a(a[0], 0);
+    load_a(a[1], 1);
+    load_a(a[2], 2);
+    int c = 0;
+    for (; c + 4 <= nch; c += 4) {
+      // entering: a[0..2] hold chunks c..c+2, b0 holds chunk c.  The scheduling barriers keep
+      // the compiler from moving loads across the MFMAs they should overlap, or conversions up
+      // to their loads.
+      load_b(b1, c + 1, full);
+      load_a(a[3], c + 3);
       __builtin_amdgcn_sched_barrier(0);
-      mma(a0, b0, full);
+      mma(a[0], b0, full);
       __builtin_amdgcn_sched_barrier(0);
-      load(a0, b0, c + 2, full);
+      load_b(b0, c + 2, full);
+      load_a(a[0], c + 4);
       __builtin_amdgcn_sched_barrier(0);
-      mma(a1, b1, full);
+      mma(a[1], b1, full);
+      __builtin_amdgcn_sched_barrier(0);
+      load_b(b1, c + 3, full);
+      load_a(a[1], c + 5);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a[2], b0, full);
+      __builtin_amdgcn_sched_barrier(0);
+      load_b(b0, c + 4, full);
+      load_a(a[2], c + 6);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a[3], b1, full);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (nch & 1) mma(a0, b0, full);   // odd chunk count: the last chunk is in buffer 0
+    // at most three chunks left: c..c+2 in a[0..2], chunk c's right-hand side in b0
+    const int rem = nch - c;
+    if (rem > 0) mma(a[0], b0, full);
+    if (rem > 1) { load_b(b1, c + 1, full); mma(a[1], b1, full); }
+    if (rem > 2) { load_b(b0, c + 2, full); mma(a[2], b0, full); }
   };
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
   else run(std::false_type{});
@@ -184,27 +210,29 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
 
-  // Software pipeline as in k_phi_v, over chunks of 16 along n.  Rows past N_t read row 0 of
-  // the task: they meet rows of W that the forward product wrote as zeros.  Lanes past D read
-  // column 0 and feed only output rows that are not stored.
+  // Software pipeline as in k_phi_v, over chunks of 16 along n (Phi three chunks ahead, W one).
+  // Rows past N_t read row 0 of the task: they meet rows of W that the forward product wrote as
+  // zeros.  Lanes past D read column 0 and feed only output rows that are not stored.
   const int nch = np / 16;
-  frf a0[4], a1[4];
+  frf a[4][4];
   vt4 b0[kColGroup], b1[kColGroup];
-  auto load = [&](frf (&a)[4], vt4 (&b)[kColGroup], int c, auto full)
-      __attribute__((always_inline)) {
+  auto load_a = [&](frf (&x)[4], int c) __attribute__((always_inline)) {
     const int nb = min(c, nch - 1) * 16;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int n = nb + 4 * g4 + s;
-      a[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
+      x[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
     }
+  };
+  auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
+    const int nb = min(c, nch - 1) * 16;
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
       const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      b[cf] = *(const vt4*)(wbase + (int64_t)f * 16 * np + nb);
+      x[cf] = *(const vt4*)(wbase + (int64_t)f * 16 * np + nb);
     }
   };
-  auto mma = [&](const frf (&a)[4], const vt4 (&b)[kColGroup], auto full)
+  auto mma = [&](const frf (&x)[4], const vt4 (&y)[kColGroup], auto full)
       __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -214,26 +242,43 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
 #pragma unroll
           for (int f = 0; f < RF; ++f) {
             float av;
-            if constexpr (RF == 1) av = a[s]; else av = a[s][f];
-            acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], acc[f][cf]);
+            if constexpr (RF == 1) av = x[s]; else av = x[s][f];
+            acc[f][cf] = Mfma<VT>::mma((VT)av, y[cf][s], acc[f][cf]);
           }
   };
   auto run = [&](auto full) __attribute__((always_inline)) {
-    if (nch == 0) return;   // empty task: A V = alpha (.) V
-    load(a0, b0, 0, full);
-    for (int c = 0; c + 1 < nch; c += 2) {
-      // scheduling barriers between the stages: the compiler may neither sink a buffer's loads
-      // below the MFMAs they should overlap nor hoist its conversions up to its loads
-      load(a1, b1, c + 1, full);
+    if (nch == 0) return;   // empty task: the product is zero
+    load_b(b0, 0, full);
+    load_a(a[0], 0);
+    load_a(a[1], 1);
+    load_a(a[2], 2);
+    int c = 0;
+    for (; c + 4 <= nch; c += 4) {
+      load_b(b1, c + 1, full);
+      load_a(a[3], c + 3);
       __builtin_amdgcn_sched_barrier(0);
-      mma(a0, b0, full);
+      mma(a[0], b0, full);
       __builtin_amdgcn_sched_barrier(0);
-      load(a0, b0, c + 2, full);
+      load_b(b0, c + 2, full);
+      load_a(a[0], c + 4);
       __builtin_amdgcn_sched_barrier(0);
-      mma(a1, b1, full);
+      mma(a[1], b1, full);
+      __builtin_amdgcn_sched_barrier(0);
+      load_b(b1, c + 3, full);
+      load_a(a[1], c + 5);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a[2], b0, full);
+      __builtin_amdgcn_sched_barrier(0);
+      load_b(b0, c + 4, full);
+      load_a(a[2], c + 6);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(a[3], b1, full);
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (nch & 1) mma(a0, b0, full);   // odd chunk count: the last chunk is in buffer 0
+    const int rem = nch - c;
+    if (rem > 0) mma(a[0], b0, full);
+    if (rem > 1) { load_b(b1, c + 1, full); mma(a[1], b1, full); }
+    if (rem > 2) { load_b(b0, c + 2, full); mma(a[2], b0, full); }
   };
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
   else run(std::false_type{});
