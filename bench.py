@@ -169,7 +169,7 @@ def main():
         peak = PEAK_TFLOPS[a.math]
         rows = m.tiles()[0 if name == "phi_v" else 1]
         vt = "double" if a.math == "f64" else "float"
-        kname = "k_%s<%s, %d>" % (name, vt, rows // 16)
+        kname = "k_%s%s<%s, %d>" % (name, "_lds" if rows < 0 else "", vt, abs(rows) // 16)
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(kname, a.config, a.math),

@@ -223,9 +223,12 @@ cmtcs_status_t cmtcs_profile(cmtcs_handle_t h, int32_t enable, double* totals_ms
                              int64_t* counts);
 
 /* Tile shapes in use: rows[0] and rows[1] (HOST) receive the output rows per wave tile of the
- * Phi V and the Phi^T W products.  Unless the environment variable CMTCS_AUTOTUNE is "0" when
- * the handle is created, the first call with a new number of column slots per task times every
- * supported height of each product on the handle's own buffers and keeps the fastest. */
+ * Phi V and the Phi^T W products; a negative value -r means the LDS-staged kernel, whose tile is
+ * four waves of r rows sharing one right-hand-side chunk in LDS.  Unless the environment
+ * variable CMTCS_AUTOTUNE is "0" when the handle is created, the first call with a new number of
+ * column slots per task times every supported shape of each product on the handle's own buffers
+ * and keeps the fastest.  CMTCS_TILES="f,a" at create pins the two shapes (each must be one the
+ * library supports; otherwise the defaults stay) and turns the autotuner off. */
 cmtcs_status_t cmtcs_tiles(cmtcs_handle_t h, int32_t* rows);
 
 /* Message of the last failed call on this thread ("" if none). */

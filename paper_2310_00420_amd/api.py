@@ -215,7 +215,8 @@ class Cmtcs:
         return dalpha, dphi
 
     def tiles(self):
-        """Output rows per wave tile of the (Phi V, Phi^T W) products in use."""
+        """Output rows per wave tile of the (Phi V, Phi^T W) products in use (negative: the
+        LDS-staged kernel with four waves of that many rows per tile)."""
         rows = (ctypes.c_int32 * 2)()
         _lib.check(_lib.load().cmtcs_tiles(self._h, rows))
         return int(rows[0]), int(rows[1])

@@ -224,9 +224,9 @@ struct cmtcs_handle_s {
       const int nt = (int)(row_off[t + 1] - row_off[t]);
       const int np = round16(nt);
       woff[t + 1] = woff[t] + (int64_t)Rp * np;
-      for (int n0 = 0; n0 < np; n0 += fr)
+      for (int n0 = 0; n0 < np; n0 += tile_step(fr))
         for (int cg = 0; cg < ng; ++cg) ft.push_back(make_int4(t, n0, cg, 0));
-      for (int d0 = 0; d0 < D; d0 += ar)
+      for (int d0 = 0; d0 < D; d0 += tile_step(ar))
         for (int cg = 0; cg < ng; ++cg) at.push_back(make_int4(t, d0, cg, 0));
     }
     HIP_TRY(hipMemcpyAsync(w_off_d, woff.data(), sizeof(int64_t) * (T + 1),
@@ -267,41 +267,48 @@ struct cmtcs_handle_s {
     return CMTCS_OK;
   }
 
-  // Autotuner: for a new column count, times every supported tile height of each product on
+  // Autotuner: for a new column count, times every supported tile shape of each product on
   // the handle's own buffers (one warm-up and three timed launches, HIP events on the
-  // handle's stream) and keeps the fastest.  Runs before the solve initialises its vectors;
+  // handle's stream, each after a launch of the other product) and keeps the fastest.  Runs before the solve initialises its vectors;
   // the products only read the workspace and write W and AD.
   template <typename VT>
   cmtcs_status_t tune(const Geometry& g, const float* alpha) {
     if (!autotune || mixed() || tuned_Rp == g.Rp) return prepare(g.Rp);
-    int cand[4];
-    const int nc = op_row_candidates(math == CMTCS_MATH_F64, cand);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
     cmtcs_status_t rs = CMTCS_OK;
     for (int kind = 0; kind < 2 && rs == CMTCS_OK; ++kind) {
+      int cand[kMaxTileCands];
+      const int nc = op_row_candidates(math == CMTCS_MATH_F64, kind, cand);
       float best = 1e30f;
       int best_rows = kind == 0 ? fwd_rows : adj_rows;
       for (int i = 0; i < nc && rs == CMTCS_OK; ++i) {
         (kind == 0 ? fwd_rows : adj_rows) = cand[i];
         rs = prepare(g.Rp);
         if (rs != CMTCS_OK) break;
+        // each timed launch follows a launch of the other product, as in a CG step, so that
+        // the candidate meets the cache state the loop leaves (its own operands evicted)
         float ms = 0.f;
         hipError_t e = hipSuccess;
+        auto fwd = [&]() {
+          return launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
+                                  fwd_rows, st);
+        };
+        auto adj = [&]() {
+          return launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
+                                   (VT*)AD, nullptr, colc, beta, nullptr, adj_rows, st);
+        };
         for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-          if (rep == 1) e = hipEventRecord(e0, st);
-          if (e != hipSuccess) break;
-          if (kind == 0)
-            e = launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
-                                 fwd_rows, st);
-          else
-            e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
-                                  (VT*)AD, nullptr, colc, beta, nullptr, adj_rows, st);
+          e = kind == 0 ? adj() : fwd();
+          if (e == hipSuccess) e = hipEventRecord(e0, st);
+          if (e == hipSuccess) e = kind == 0 ? fwd() : adj();
+          if (e == hipSuccess) e = hipEventRecord(e1, st);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float one = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&one, e0, e1);
+          if (rep > 0) ms += one;   // the first round is a warm-up
         }
-        if (e == hipSuccess) e = hipEventRecord(e1, st);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         if (e != hipSuccess) { rs = hip_fail(e, "autotune"); break; }
         if (ms < best) { best = ms; best_rows = cand[i]; }
       }
@@ -571,13 +578,28 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   size_t np_sum = 0, fwd_max = 0;
   const bool f64 = h->math == CMTCS_MATH_F64;
   const size_t ngm = (size_t)h->ngroups(h->Rp_max);
-  int cand[4];
-  const int nc = op_row_candidates(f64, cand);
-  int min_rows = cand[0];
-  for (int i = 1; i < nc; ++i) min_rows = std::min(min_rows, cand[i]);
-  h->fwd_rows = h->adj_rows = cand[0];
+  // tile tables are sized for the smallest tile of either product
+  int min_rows = 1 << 30;
+  int cand[2][kMaxTileCands], ncand[2];
+  for (int kind = 0; kind < 2; ++kind) {
+    ncand[kind] = op_row_candidates(f64, kind, cand[kind]);
+    for (int i = 0; i < ncand[kind]; ++i) min_rows = std::min(min_rows, tile_step(cand[kind][i]));
+  }
+  h->fwd_rows = cand[0][0];
+  h->adj_rows = cand[1][0];
   const char* at = std::getenv("CMTCS_AUTOTUNE");
   h->autotune = !(at != nullptr && at[0] == '0');
+  // CMTCS_TILES="fwd,adj" pins both tile heights (each one of the supported candidates) and
+  // turns the autotuner off; unsupported values leave the defaults in place
+  if (const char* pin = std::getenv("CMTCS_TILES")) {
+    int f = 0, a = 0;
+    if (std::sscanf(pin, "%d,%d", &f, &a) == 2) {
+      bool okf = false, oka = false;
+      for (int i = 0; i < ncand[0]; ++i) okf = okf || cand[0][i] == f;
+      for (int i = 0; i < ncand[1]; ++i) oka = oka || cand[1][i] == a;
+      if (okf && oka) { h->fwd_rows = f; h->adj_rows = a; h->autotune = false; }
+    }
+  }
   for (size_t t = 0; t < T; ++t) {
     const size_t np = (size_t)round16((int)(h->row_off[t + 1] - h->row_off[t]));
     np_sum += np;

@@ -134,8 +134,14 @@ template <typename VT>
 hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
                          double beta, const int* act, int rows, hipStream_t st);
-// Writes the supported rows-per-tile values (default first) and returns their count.
-int op_row_candidates(bool f64, int* rows);
+// Writes the supported tile heights of product `kind` (0: Phi V, 1: Phi^T W) for FP64 (f64)
+// or FP32 right-hand sides, default first, and returns their count (at most kMaxTileCands).  A
+// positive height is the output rows of a one-wave tile of the register-pipelined kernels; a
+// negative one selects the LDS-staged kernels, whose tile is a block of four waves of -rows rows
+// each (tile_step gives the rows a tile covers).
+constexpr int kMaxTileCands = 4;
+int op_row_candidates(bool f64, int kind, int* rows);
+inline int tile_step(int rows) { return rows > 0 ? rows : -4 * rows; }
 
 // Launchers (k_cg.hip).
 struct CgState {

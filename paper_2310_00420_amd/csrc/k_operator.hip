@@ -34,10 +34,18 @@ __device__ inline int xcd_block(int b, int nb) {
 // SIMD then starts its next tile only when all four waves of its group have ended.
 constexpr int kOpWaves = 4;
 
-int op_row_candidates(bool f64, int* rows) {
-  if (f64) { rows[0] = 32; rows[1] = 16; }
-  else { rows[0] = 64; rows[1] = 32; }
-  return 2;   // the first entry is the default
+// Depth of the register ring that prefetches the Phi operand (depth - 1 chunks ahead), per
+// element type of the right-hand sides: measured best at 6 for FP64 (8 spills) and 4 for FP32.
+template <typename VT> constexpr int ring_depth() { return sizeof(VT) == 8 ? 6 : 4; }
+
+// The LDS-staged kernels are offered where they won in the CG loop: FP64 with 16 rows per wave
+// (two waves per SIMD).  With 32 FP64 rows they stay at one wave per SIMD and lose to the
+// register-pipelined kernel, and in FP32 the register-pipelined 64-row tile is faster.
+int op_row_candidates(bool f64, int kind, int* rows) {
+  (void)kind;   // both products offer the same shapes
+  if (!f64) { rows[0] = 64; rows[1] = 32; return 2; }   // the first entry is the default
+  rows[0] = 32; rows[1] = 16; rows[2] = -16;
+  return 3;
 }
 
 template <typename VT, int RF>
@@ -49,6 +57,7 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
                                                const int* __restrict__ act, int D, int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<VT, 4>::type vt4;
+  constexpr int kRingA = ring_depth<VT>();
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
   // tile fields are wave-uniform: keep them in scalar registers so that every branch on them
@@ -82,7 +91,7 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
     for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
 
   // Software pipeline over chunks of 16 along d.  The Phi operand streams from HBM (it misses
-  // L2 every time), so it is prefetched three chunks ahead in a ring of four register buffers;
+  // L2 every time), so it is prefetched kRingA - 1 chunks ahead in a ring of register buffers;
   // the right-hand-side block comes from L2 and is double-buffered one chunk ahead.  Every load
   // is unconditional and no loaded value is touched before its MFMA; a load past the last chunk
   // re-reads the last chunk (in bounds, unused) and a missing column fragment re-reads the last
@@ -90,8 +99,8 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   // memory counter completes in issue order, so waiting for a chunk's right-hand side then
   // does not also wait for the Phi loads of later chunks.
   const int nch = D / 16;
-  f4 a[4][RF];
-  vt4 b0[kColGroup], b1[kColGroup];
+  f4 a[kRingA][RF];
+  vt4 b[2][kColGroup];
   auto load_a = [&](f4 (&x)[RF], int c) __attribute__((always_inline)) {
     const int d0 = min(c, nch - 1) * 16;
 #pragma unroll
@@ -117,41 +126,30 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
             acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], y[cf][s], acc[rf][cf]);
   };
   auto run = [&](auto full) __attribute__((always_inline)) {
-    load_b(b0, 0, full);
-    load_a(a[0], 0);
-    load_a(a[1], 1);
-    load_a(a[2], 2);
+    load_b(b[0], 0, full);
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
     int c = 0;
-    for (; c + 4 <= nch; c += 4) {
-      // entering: a[0..2] hold chunks c..c+2, b0 holds chunk c.  The scheduling barriers keep
-      // the compiler from moving loads across the MFMAs they should overlap, or conversions up
-      // to their loads.
-      load_b(b1, c + 1, full);
-      load_a(a[3], c + 3);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[0], b0, full);
-      __builtin_amdgcn_sched_barrier(0);
-      load_b(b0, c + 2, full);
-      load_a(a[0], c + 4);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[1], b1, full);
-      __builtin_amdgcn_sched_barrier(0);
-      load_b(b1, c + 3, full);
-      load_a(a[1], c + 5);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[2], b0, full);
-      __builtin_amdgcn_sched_barrier(0);
-      load_b(b0, c + 4, full);
-      load_a(a[2], c + 6);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[3], b1, full);
-      __builtin_amdgcn_sched_barrier(0);
+    for (; c + kRingA <= nch; c += kRingA) {
+      // entering: a[i] holds chunk c+i for i < kRingA-1 and b[0] chunk c.  Fully unrolled, so
+      // every ring index is a constant.  The scheduling barriers keep the compiler from moving
+      // loads across the MFMAs they should overlap, or conversions up to their loads.
+#pragma unroll
+      for (int i = 0; i < kRingA; ++i) {
+        load_b(b[(i + 1) & 1], c + i + 1, full);
+        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a[i], b[i & 1], full);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
-    // at most three chunks left: c..c+2 in a[0..2], chunk c's right-hand side in b0
-    const int rem = nch - c;
-    if (rem > 0) mma(a[0], b0, full);
-    if (rem > 1) { load_b(b1, c + 1, full); mma(a[1], b1, full); }
-    if (rem > 2) { load_b(b0, c + 2, full); mma(a[2], b0, full); }
+    // fewer than kRingA chunks left: chunk c+i is in a[i], chunk c's right-hand side in b[0]
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) {
+      if (c + i >= nch) break;
+      if (i > 0) load_b(b[i & 1], c + i, full);
+      mma(a[i], b[i & 1], full);
+    }
   };
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
   else run(std::false_type{});
@@ -174,115 +172,186 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// LDS-staged forward product.  A block of four waves owns four consecutive 16*RF-row tiles of
+// one task and one column group, so all four multiply the same right-hand-side chunk: the block
+// loads it once per chunk into an LDS double buffer (through a few staging registers per
+// thread) instead of each wave loading it into its own registers.  The Phi ring and the
+// accumulators are per wave as in k_phi_v.
+template <typename VT>
+struct LdsChunk {
+  static constexpr int kPer16 = 16 / (int)sizeof(VT);            // elements per 16-byte piece
+  static constexpr int kPieces = 16 / kPer16;                    // pieces per 16-element column
+  static constexpr int kLd = 16 + kPer16;                        // padded LDS row (elements)
+  static constexpr int kMaxPieces = 16 * kColGroup * kPieces;
+  static constexpr int kPerThread = (kMaxPieces + 64 * kOpWaves - 1) / (64 * kOpWaves);
+  typedef typename VecOf<VT, kPer16>::type piece_t;
+};
+
+// B fragment cf of the chunk in LDS buffer `buf` for lane (i16, g4): elements 4 g4 .. 4 g4 + 3
+// of column cf*16 + i16, read as 16-byte pieces (rows are 16-byte aligned, not 32).
+template <typename VT>
+__device__ inline typename VecOf<VT, 4>::type lds_frag(const VT* row) {
+  typedef typename VecOf<VT, 4>::type vt4;
+  if constexpr (sizeof(VT) == 8) {
+    const d2 x = *(const d2*)row, y = *(const d2*)(row + 2);
+    return vt4{x[0], x[1], y[0], y[1]};
+  } else {
+    return *(const vt4*)row;
+  }
+}
+
+// The 16-row FP64 LDS-staged tile fits two waves per SIMD without spilling once the
+// right-hand side no longer sits in registers (larger tiles do not).
 template <typename VT, int RF>
-__global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restrict__ phi,
-                                                const int64_t* __restrict__ row_off,
-                                                const int64_t* __restrict__ w_off,
-                                                const int4* __restrict__ tiles, int ntiles,
-                                                const VT* __restrict__ W, const VT* __restrict__ V,
-                                                VT* __restrict__ AV,
-                                                const float* __restrict__ alpha,
-                                                const int* __restrict__ colc, double beta,
-                                                const int* __restrict__ act, int D, int Rp) {
+constexpr int lds_waves_per_simd() { return (sizeof(VT) == 8 ? RF == 1 : RF == 2) ? 2 : 1; }
+
+template <typename VT, int RF>
+__global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void k_phi_v_lds(const float* __restrict__ phi,
+                                                   const int64_t* __restrict__ row_off,
+                                                   const int64_t* __restrict__ w_off,
+                                                   const int4* __restrict__ tiles, int ntiles,
+                                                   const VT* __restrict__ V, VT* __restrict__ W,
+                                                   const int* __restrict__ act, int D, int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<VT, 4>::type vt4;
-  typedef typename VecOf<float, RF>::type frf;
-  typedef typename VecOf<VT, RF>::type vrf;
-  const int lane = threadIdx.x & 63;
+  typedef LdsChunk<VT> L;
+  typedef typename L::piece_t piece_t;
+  constexpr int kRingA = ring_depth<VT>();
+  __shared__ VT lds[2][16 * kColGroup][L::kLd];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
-  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * kOpWaves + (threadIdx.x >> 6));
-  if (tile >= ntiles) return;
-  const int4 tl = tiles[tile];
-  const int t = uniform(tl.x), d0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
-  if (act != nullptr && act[t] == 0) return;
+  const int blk = uniform(xcd_block(blockIdx.x, gridDim.x));
+  if (blk >= ntiles) return;
+  const int4 tl = tiles[blk];
+  const int t = uniform(tl.x), cf0 = uniform(tl.z) * kColGroup;
+  const int n0 = uniform(tl.y) + uniform(wave) * 16 * RF;
+  if (act != nullptr && act[t] == 0) return;   // uniform over the block
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
-  const int dl = d0 + RF * i16;          // first of the RF output rows this lane loads
-  const bool dval = dl < D;
-  const float* pbase = phi + r0 * (int64_t)D + (dval ? dl : 0);
-  const VT* wbase = W + w_off[t] + (int64_t)(cf0 * 16 + i16) * np + 4 * g4;
+
+  const float* prow[RF];
+#pragma unroll
+  for (int rf = 0; rf < RF; ++rf) {
+    // as in k_phi_v: rows past N_t (also whole tiles of the block past np) read row 0 and
+    // their outputs are zeroed or not stored
+    const int row = n0 + rf * 16 + Mfma<VT>::a_row(i16);
+    prow[rf] = phi + (r0 + (row < nt ? row : 0)) * (int64_t)D + 4 * g4;
+  }
+  // staging: piece p of the chunk is column p / kPieces, 16-byte piece p % kPieces; pieces past
+  // the group's columns are clamped onto the last one (a duplicate load and an identical store)
+  const int npieces = 16 * ncf * L::kPieces;
+  const VT* ssrc[L::kPerThread];
+  VT* sdst[2][L::kPerThread];
+#pragma unroll
+  for (int i = 0; i < L::kPerThread; ++i) {
+    const int p = min((int)threadIdx.x + i * 64 * kOpWaves, npieces - 1);
+    const int col = p / L::kPieces, q = p % L::kPieces;
+    ssrc[i] = V + ((int64_t)t * Rp + cf0 * 16 + col) * D + q * L::kPer16;
+    sdst[0][i] = &lds[0][col][q * L::kPer16];
+    sdst[1][i] = &lds[1][col][q * L::kPer16];
+  }
 
   acc_t acc[RF][kColGroup];
 #pragma unroll
-  for (int f = 0; f < RF; ++f)
+  for (int rf = 0; rf < RF; ++rf)
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
+    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
 
-  // Software pipeline as in k_phi_v, over chunks of 16 along n (Phi three chunks ahead, W one).
-  // Rows past N_t read row 0 of the task: they meet rows of W that the forward product wrote as
-  // zeros.  Lanes past D read column 0 and feed only output rows that are not stored.
-  const int nch = np / 16;
-  frf a[4][4];
-  vt4 b0[kColGroup], b1[kColGroup];
-  auto load_a = [&](frf (&x)[4], int c) __attribute__((always_inline)) {
-    const int nb = min(c, nch - 1) * 16;
+  const int nch = D / 16;
+  f4 a[kRingA][RF];
+  piece_t stg[L::kPerThread];
+  auto load_a = [&](f4 (&x)[RF], int c) __attribute__((always_inline)) {
+    const int d0 = min(c, nch - 1) * 16;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int n = nb + 4 * g4 + s;
-      x[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
-    }
+    for (int rf = 0; rf < RF; ++rf) x[rf] = *(const f4*)(prow[rf] + d0);
   };
-  auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
-    const int nb = min(c, nch - 1) * 16;
+  auto stage_load = [&](int c) __attribute__((always_inline)) {
+    const int d0 = min(c, nch - 1) * 16;
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) {
-      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      x[cf] = *(const vt4*)(wbase + (int64_t)f * 16 * np + nb);
-    }
+    for (int i = 0; i < L::kPerThread; ++i) stg[i] = *(const piece_t*)(ssrc[i] + d0);
   };
-  auto mma = [&](const frf (&x)[4], const vt4 (&y)[kColGroup], auto full)
-      __attribute__((always_inline)) {
+  auto stage_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < L::kPerThread; ++i) *(piece_t*)sdst[buf][i] = stg[i];
+  };
+  auto step = [&](const f4 (&x)[RF], int buf, auto full) __attribute__((always_inline)) {
+    vt4 b[kColGroup];
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (decltype(full)::value || cf < ncf) b[cf] = lds_frag<VT>(&lds[buf][cf * 16 + i16][4 * g4]);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
 #pragma unroll
-          for (int f = 0; f < RF; ++f) {
-            float av;
-            if constexpr (RF == 1) av = x[s]; else av = x[s][f];
-            acc[f][cf] = Mfma<VT>::mma((VT)av, y[cf][s], acc[f][cf]);
-          }
+          for (int rf = 0; rf < RF; ++rf)
+            acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], b[cf][s], acc[rf][cf]);
   };
+  // Per chunk c (buffer c & 1): multiply; store the staged chunk c+1 into the other buffer
+  // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+2; then the
+  // Phi load of chunk c + kRingA - 1, issued after the staging loads so that the next wait for
+  // staged data does not also wait for it; barrier.
   auto run = [&](auto full) __attribute__((always_inline)) {
-    if (nch == 0) return;   // empty task: the product is zero
-    load_b(b0, 0, full);
-    load_a(a[0], 0);
-    load_a(a[1], 1);
-    load_a(a[2], 2);
+    stage_load(0);
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
+    stage_store(0);
+    stage_load(1);
+    __syncthreads();
     int c = 0;
-    for (; c + 4 <= nch; c += 4) {
-      load_b(b1, c + 1, full);
-      load_a(a[3], c + 3);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[0], b0, full);
-      __builtin_amdgcn_sched_barrier(0);
-      load_b(b0, c + 2, full);
-      load_a(a[0], c + 4);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[1], b1, full);
-      __builtin_amdgcn_sched_barrier(0);
-      load_b(b1, c + 3, full);
-      load_a(a[1], c + 5);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[2], b0, full);
-      __builtin_amdgcn_sched_barrier(0);
-      load_b(b0, c + 4, full);
-      load_a(a[2], c + 6);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a[3], b1, full);
-      __builtin_amdgcn_sched_barrier(0);
+    for (; c + kRingA <= nch; c += kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
+#pragma unroll
+      for (int i = 0; i < kRingA; ++i) {
+        step(a[i], i & 1, full);
+        stage_store((i + 1) & 1);
+        stage_load(c + i + 2);
+        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+        __syncthreads();
+      }
     }
-    const int rem = nch - c;
-    if (rem > 0) mma(a[0], b0, full);
-    if (rem > 1) { load_b(b1, c + 1, full); mma(a[1], b1, full); }
-    if (rem > 2) { load_b(b0, c + 2, full); mma(a[2], b0, full); }
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) {
+      if (c + i >= nch) break;
+      step(a[i], i & 1, full);
+      stage_store((i + 1) & 1);
+      stage_load(c + i + 2);
+      __syncthreads();
+    }
   };
-  if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
+  if (ncf == kColGroup) run(std::true_type{});
   else run(std::false_type{});
 
+  VT* Wt = W + w_off[t];
+#pragma unroll
+  for (int rf = 0; rf < RF; ++rf) {
+    const int rb = n0 + rf * 16;
+    if (rb >= np) continue;
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      if (cf >= ncf) continue;
+      const int j = (cf0 + cf) * 16 + i16;
+      vt4 o;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = rb + 4 * g4 + r < nt ? (VT)acc[rf][cf][r] : (VT)0;
+      *(vt4*)(Wt + (int64_t)j * np + rb + 4 * g4) = o;
+    }
+  }
+}
+
+// Epilogue of the adjoint product for one wave's tile (rows d0 .. d0 + 16 RF - 1 of task t,
+// column fragments cf0 .. cf0 + ncf - 1): with no alpha the bare Phi^T W, else
+// beta Phi^T W + alpha_c (.) V with one explicit fused multiply-add per element.
+template <typename VT, int RF>
+__device__ inline void phit_w_store(const typename Mfma<VT>::acc_t (&acc)[RF][kColGroup], int t,
+                                    int d0, int cf0, int ncf, int i16, int g4, int D, int Rp,
+                                    VT* __restrict__ AV, const VT* __restrict__ V,
+                                    const float* __restrict__ alpha,
+                                    const int* __restrict__ colc, double beta) {
+  typedef typename VecOf<VT, RF>::type vrf;
   if (alpha == nullptr) {
     // bare product Phi^T W (the CG update adds beta and the diagonal term): stores only, so
     // the epilogue issues no load and never waits on memory
@@ -339,6 +408,237 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
 }
 
 template <typename VT, int RF>
+__global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restrict__ phi,
+                                                const int64_t* __restrict__ row_off,
+                                                const int64_t* __restrict__ w_off,
+                                                const int4* __restrict__ tiles, int ntiles,
+                                                const VT* __restrict__ W, const VT* __restrict__ V,
+                                                VT* __restrict__ AV,
+                                                const float* __restrict__ alpha,
+                                                const int* __restrict__ colc, double beta,
+                                                const int* __restrict__ act, int D, int Rp) {
+  typedef typename Mfma<VT>::acc_t acc_t;
+  typedef typename VecOf<VT, 4>::type vt4;
+  constexpr int kRingA = ring_depth<VT>();
+  typedef typename VecOf<float, RF>::type frf;
+  typedef typename VecOf<VT, RF>::type vrf;
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * kOpWaves + (threadIdx.x >> 6));
+  if (tile >= ntiles) return;
+  const int4 tl = tiles[tile];
+  const int t = uniform(tl.x), d0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
+  if (act != nullptr && act[t] == 0) return;
+  const int64_t r0 = row_off[t];
+  const int nt = (int)(row_off[t + 1] - r0);
+  const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
+  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  const int dl = d0 + RF * i16;          // first of the RF output rows this lane loads
+  const bool dval = dl < D;
+  const float* pbase = phi + r0 * (int64_t)D + (dval ? dl : 0);
+  const VT* wbase = W + w_off[t] + (int64_t)(cf0 * 16 + i16) * np + 4 * g4;
+
+  acc_t acc[RF][kColGroup];
+#pragma unroll
+  for (int f = 0; f < RF; ++f)
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
+
+  // Software pipeline as in k_phi_v, over chunks of 16 along n (Phi kRingA - 1 chunks ahead, W
+  // one).
+  // Rows past N_t read row 0 of the task: they meet rows of W that the forward product wrote as
+  // zeros.  Lanes past D read column 0 and feed only output rows that are not stored.
+  const int nch = np / 16;
+  frf a[kRingA][4];
+  vt4 b[2][kColGroup];
+  auto load_a = [&](frf (&x)[4], int c) __attribute__((always_inline)) {
+    const int nb = min(c, nch - 1) * 16;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int n = nb + 4 * g4 + s;
+      x[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
+    }
+  };
+  auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
+    const int nb = min(c, nch - 1) * 16;
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) {
+      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
+      x[cf] = *(const vt4*)(wbase + (int64_t)f * 16 * np + nb);
+    }
+  };
+  auto mma = [&](const frf (&x)[4], const vt4 (&y)[kColGroup], auto full)
+      __attribute__((always_inline)) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int cf = 0; cf < kColGroup; ++cf)
+        if (decltype(full)::value || cf < ncf)
+#pragma unroll
+          for (int f = 0; f < RF; ++f) {
+            float av;
+            if constexpr (RF == 1) av = x[s]; else av = x[s][f];
+            acc[f][cf] = Mfma<VT>::mma((VT)av, y[cf][s], acc[f][cf]);
+          }
+  };
+  auto run = [&](auto full) __attribute__((always_inline)) {
+    if (nch == 0) return;   // empty task: the product is zero
+    load_b(b[0], 0, full);
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
+    int c = 0;
+    for (; c + kRingA <= nch; c += kRingA) {
+      // entering: a[i] holds chunk c+i for i < kRingA-1 and b[0] chunk c.  Fully unrolled, so
+      // every ring index is a constant.  The scheduling barriers keep the compiler from moving
+      // loads across the MFMAs they should overlap, or conversions up to their loads.
+#pragma unroll
+      for (int i = 0; i < kRingA; ++i) {
+        load_b(b[(i + 1) & 1], c + i + 1, full);
+        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a[i], b[i & 1], full);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    // fewer than kRingA chunks left: chunk c+i is in a[i], chunk c's right-hand side in b[0]
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) {
+      if (c + i >= nch) break;
+      if (i > 0) load_b(b[i & 1], c + i, full);
+      mma(a[i], b[i & 1], full);
+    }
+  };
+  if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
+  else run(std::false_type{});
+
+  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
+}
+
+// LDS-staged adjoint product: as k_phi_v_lds, a block of four waves owns four consecutive
+// 16*RF-row tiles (rows of d) of one task and column group and shares each chunk of W_t (16 rows
+// of n for the group's columns) through an LDS double buffer; Phi^T comes from the rows of Phi
+// as in k_phit_w.
+template <typename VT, int RF>
+__global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void k_phit_w_lds(
+    const float* __restrict__ phi, const int64_t* __restrict__ row_off,
+    const int64_t* __restrict__ w_off, const int4* __restrict__ tiles, int ntiles,
+    const VT* __restrict__ W, const VT* __restrict__ V, VT* __restrict__ AV,
+    const float* __restrict__ alpha, const int* __restrict__ colc, double beta,
+    const int* __restrict__ act, int D, int Rp) {
+  typedef typename Mfma<VT>::acc_t acc_t;
+  typedef typename VecOf<VT, 4>::type vt4;
+  typedef typename VecOf<float, RF>::type frf;
+  typedef LdsChunk<VT> L;
+  typedef typename L::piece_t piece_t;
+  constexpr int kRingA = ring_depth<VT>();
+  __shared__ VT lds[2][16 * kColGroup][L::kLd];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int blk = uniform(xcd_block(blockIdx.x, gridDim.x));
+  if (blk >= ntiles) return;
+  const int4 tl = tiles[blk];
+  const int t = uniform(tl.x), cf0 = uniform(tl.z) * kColGroup;
+  const int d0 = uniform(tl.y) + uniform(wave) * 16 * RF;
+  if (act != nullptr && act[t] == 0) return;   // uniform over the block
+  const int64_t r0 = row_off[t];
+  const int nt = (int)(row_off[t + 1] - r0);
+  const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
+  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  // as in k_phit_w: lanes past D (also whole tiles of the block past D) read column 0 and their
+  // outputs are not stored; rows past N_t read row 0 and meet zero rows of W
+  const int dl = d0 + RF * i16;
+  const float* pbase = phi + r0 * (int64_t)D + (dl < D ? dl : 0);
+  const int npieces = 16 * ncf * L::kPieces;
+  const VT* ssrc[L::kPerThread];
+  VT* sdst[2][L::kPerThread];
+#pragma unroll
+  for (int i = 0; i < L::kPerThread; ++i) {
+    const int p = min((int)threadIdx.x + i * 64 * kOpWaves, npieces - 1);
+    const int col = p / L::kPieces, q = p % L::kPieces;
+    ssrc[i] = W + w_off[t] + (int64_t)(cf0 * 16 + col) * np + q * L::kPer16;
+    sdst[0][i] = &lds[0][col][q * L::kPer16];
+    sdst[1][i] = &lds[1][col][q * L::kPer16];
+  }
+
+  acc_t acc[RF][kColGroup];
+#pragma unroll
+  for (int f = 0; f < RF; ++f)
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
+
+  const int nch = np / 16;
+  frf a[kRingA][4];
+  piece_t stg[L::kPerThread];
+  auto load_a = [&](frf (&x)[4], int c) __attribute__((always_inline)) {
+    const int nb = min(c, nch - 1) * 16;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int n = nb + 4 * g4 + s;
+      x[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
+    }
+  };
+  auto stage_load = [&](int c) __attribute__((always_inline)) {
+    const int nb = min(c, nch - 1) * 16;
+#pragma unroll
+    for (int i = 0; i < L::kPerThread; ++i) stg[i] = *(const piece_t*)(ssrc[i] + nb);
+  };
+  auto stage_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < L::kPerThread; ++i) *(piece_t*)sdst[buf][i] = stg[i];
+  };
+  auto step = [&](const frf (&x)[4], int buf, auto full) __attribute__((always_inline)) {
+    vt4 b[kColGroup];
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (decltype(full)::value || cf < ncf) b[cf] = lds_frag<VT>(&lds[buf][cf * 16 + i16][4 * g4]);
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int cf = 0; cf < kColGroup; ++cf)
+        if (decltype(full)::value || cf < ncf)
+#pragma unroll
+          for (int f = 0; f < RF; ++f) {
+            float av;
+            if constexpr (RF == 1) av = x[s]; else av = x[s][f];
+            acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], acc[f][cf]);
+          }
+  };
+  // the same schedule as k_phi_v_lds
+  auto run = [&](auto full) __attribute__((always_inline)) {
+    stage_load(0);
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
+    stage_store(0);
+    stage_load(1);
+    __syncthreads();
+    int c = 0;
+    for (; c + kRingA <= nch; c += kRingA) {
+#pragma unroll
+      for (int i = 0; i < kRingA; ++i) {
+        step(a[i], i & 1, full);
+        stage_store((i + 1) & 1);
+        stage_load(c + i + 2);
+        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) {
+      if (c + i >= nch) break;
+      step(a[i], i & 1, full);
+      stage_store((i + 1) & 1);
+      stage_load(c + i + 2);
+      __syncthreads();
+    }
+  };
+  if (nch > 0) {   // uniform over the block; an empty task's product is zero
+    if (ncf == kColGroup) run(std::true_type{});
+    else run(std::false_type{});
+  }
+  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
+}
+
+template <typename VT, int RF>
 static hipError_t phi_v_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                            const VT* V, VT* W, const int* act, hipStream_t st) {
   hipLaunchKernelGGL((k_phi_v<VT, RF>), dim3((ntiles + kOpWaves - 1) / kOpWaves), dim3(64 * kOpWaves), 0, st, phi,
@@ -356,10 +656,24 @@ static hipError_t phit_w_rf(const Geometry& g, const float* phi, const int4* til
   return hipGetLastError();
 }
 
+template <typename VT, int RF>
+static hipError_t phi_v_lds_rf(const Geometry& g, const float* phi, const int4* tiles,
+                               int ntiles, const VT* V, VT* W, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL((k_phi_v_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
+                     g.row_off, g.w_off, tiles, ntiles, V, W, act, g.D, g.Rp);
+  return hipGetLastError();
+}
+
 template <typename VT>
 hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                         const VT* V, VT* W, const int* act, int rows, hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
+  if (rows < 0) {   // LDS-staged variant: one tile per block of four waves of -rows rows each
+    if constexpr (sizeof(VT) == 8) {
+      if (rows == -16) return phi_v_lds_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
+    }
+    return hipErrorInvalidValue;
+  }
   if constexpr (sizeof(VT) == 8) {
     if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
     if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, st);
@@ -370,11 +684,28 @@ hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, 
   return hipErrorInvalidValue;
 }
 
+template <typename VT, int RF>
+static hipError_t phit_w_lds_rf(const Geometry& g, const float* phi, const int4* tiles,
+                                int ntiles, const VT* W, const VT* V, VT* AV, const float* alpha,
+                                const int* colc, double beta, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL((k_phit_w_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
+                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
+                     g.Rp);
+  return hipGetLastError();
+}
+
 template <typename VT>
 hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
                          double beta, const int* act, int rows, hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
+  if (rows < 0) {   // LDS-staged variant: one tile per block of four waves of -rows rows each
+    if constexpr (sizeof(VT) == 8) {
+      if (rows == -16)
+        return phit_w_lds_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+    }
+    return hipErrorInvalidValue;
+  }
   if constexpr (sizeof(VT) == 8) {
     if (rows == 16)
       return phit_w_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);

@@ -53,6 +53,34 @@ def test_apply(math, tol, shape):
     assert err <= tol
 
 
+@pytest.mark.parametrize("math,tol,tiles", [
+    ("f64", 1e-12, "32,32"), ("f64", 1e-12, "16,16"), ("f64", 1e-12, "-16,-16"),
+    ("f64", 1e-12, "32,-16"), ("f32", 1e-5, "64,64"), ("f32", 1e-5, "32,32")])
+@pytest.mark.parametrize("shape", [
+    dict(T=4, C=3, D=208, N=[0, 17, 70, 129], R=37),      # ragged rows, partial tiles
+    dict(T=2, C=4, D=512, N=[256, 200], R=150),            # two column groups
+])
+def test_apply_every_tile_shape(math, tol, tiles, shape, monkeypatch):
+    """Every tile shape of both products (pinned through CMTCS_TILES), including the LDS-staged
+    kernels, whose four-wave tiles run past the rows of small tasks and past D."""
+    monkeypatch.setenv("CMTCS_TILES", tiles)
+    shape = dict(shape)
+    R = shape.pop("R")
+    w = synth.make(synth.Config("op", sparsity=3, groups=1, K=1, **shape))
+    m = device_model(w, math=math, K=0, max_rhs=R)
+    assert [int(v) for v in tiles.split(",")] == list(m.tiles())
+    rng = np.random.default_rng(4)
+    V = rng.standard_normal((w.T, R, w.cfg.D))
+    cc = rng.integers(0, w.cfg.C, R)
+    dt = torch.float64 if math == "f64" else torch.float32
+    Vd = torch.tensor(V, dtype=dt, device=DEV)
+    got = m.apply(alpha_dev(w.alpha0), Vd, cc).cpu().numpy()
+    ref = _ref_apply(w, w.alpha0, Vd.cpu().numpy().astype(np.float64), cc)
+    err = rel_cols(got, ref)
+    print("\napply %s tiles %s %s: rel %.2e" % (math, tiles, dict(shape, R=R), err))
+    assert err <= tol
+
+
 def test_solve_matches_oracle_cg():
     """cmtcs_solve on the tiny problem with random right-hand sides, fixed 20 steps: X, gamma_u
     and xi_u against Alg. 1 in FP64.  At 20 of D = 64 steps CG is still far from its
