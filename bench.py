@@ -76,7 +76,7 @@ def cpu_baseline(w, ntasks):
     except Exception:
         threads = os.cpu_count()
     cfg = w.cfg
-    tasks = list(np.linspace(0, cfg.T - 1, ntasks).round().astype(int))
+    tasks = [int(v) for v in np.linspace(0, cfg.T - 1, ntasks).round()]
     pol = ocg.CGPolicy(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters)
     Phi, y = w.phi_list(), w.y_list()
     b = cofem.rhs([Phi[t] for t in tasks], [y[t] for t in tasks], w.beta)
@@ -167,9 +167,9 @@ def main():
         flops = 2.0 * cfg.D * row_iters
         achieved = flops / (tot_ms * 1e-3) / 1e12
         peak = PEAK_TFLOPS[a.math]
-        rows = m.tiles()[0 if name == "phi_v" else 1]
+        trows = m.tiles()[0 if name == "phi_v" else 1]
         vt = "double" if a.math == "f64" else "float"
-        kname = "k_%s%s<%s, %d>" % (name, "_lds" if rows < 0 else "", vt, abs(rows) // 16)
+        kname = "k_%s%s<%s, %d>" % (name, "_lds" if trows < 0 else "", vt, abs(trows) // 16)
         roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(kname, a.config, a.math),
