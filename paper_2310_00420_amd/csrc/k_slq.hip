@@ -248,12 +248,13 @@ hipError_t launch_slq(const Geometry& g, const CgState& s, int K, int steps, dou
                       double* rmax, hipStream_t st) {
   const long P = (long)g.T * g.C * K;
   if (P == 0) return hipSuccess;
-  // The QR sweeps are bound by instruction issue: a wave pays for every instruction whatever
-  // number of its lanes hold a probe.  Up to 40 KB of LDS per one-wave block (four blocks per
-  // CU, one per SIMD) holds as many probes per wave as fit; with many probes (more than fit
-  // on chip in one round), one probe per lane in full waves with the global-memory layout
-  // needs fewer rounds and wins.
-  constexpr long kLdsBytes = 40 * 1024;
+  // A wave pays for every instruction whatever number of its lanes hold a probe, and one wave
+  // per SIMD leaves the long dependent chains of its rotations exposed.  27 KB of LDS per
+  // one-wave block balances the two: at 200 steps, 5 probes per wave and six blocks per CU
+  // (measured at 8192 probes: 22 ms, against 25 ms at 20 KB, 29 ms at 40 KB and 36 ms at 10 KB).
+  // With many probes (more than fit on chip in one round), one probe per lane in full waves
+  // with the global-memory layout needs fewer rounds and wins.
+  constexpr long kLdsBytes = 27 * 1024;
   constexpr long kLdsMaxProbes = 16384;
   const long Um = steps > 0 ? steps : 1;
   const long PB = std::min<long>(64, kLdsBytes / (24 * (Um + 1)));
