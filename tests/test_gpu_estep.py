@@ -122,6 +122,16 @@ def test_estep_fp32_config_f64_sampled_tasks():
     assert err["iters_excess"] <= 0
 
 
+def test_estep_precision_config_f64_sampled_tasks():
+    """The measured workload exactly as the benchmark runs it (T=64, C=4, D=4096, N=1024, K=32,
+    tol 1e-6, <= 200 steps, FP64, the autotuner's tile shapes): the whole batch of 8448
+    right-hand sides on the device; the oracle checks one task from each of two true clusters."""
+    w = synth.make("prec")
+    err, g, ref, sp = _run(w, [0, 40])
+    _assert(err, sp)
+    assert err["iters_excess"] <= 0
+
+
 def test_estep_batch_config_f64_sampled_tasks():
     """Batching configuration: T=256 tasks with N_t ~ U{128..2048} (sum 272,620 rows), D=2048,
     C=8, K=32 -- all 67,584 right-hand sides in one batched solve on the device; the oracle
