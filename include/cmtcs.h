@@ -80,7 +80,12 @@ typedef struct {
   int32_t D;                /* signal length, a positive multiple of 16 (of 32 for
                                MATH_MIXED), <= 16384                                        */
   const int64_t* row_off;   /* HOST, T+1 non-decreasing prefix sums of N_t, row_off[0] = 0;
-                               N_t = 0 is allowed (then A_tc = diag(alpha_c))               */
+                               N_t = 0 is allowed (then A_tc = diag(alpha_c)).  Each task's
+                               blocks are addressed with 32-bit offsets: round16(N_t)*D*4 bytes of Phi,
+                               and slots*round16(N_t)*8 and slots*D*8 bytes of workspace
+                               (slots = max_rhs rounded up to whole 16-column fragments, or to
+                               whole 144-column groups past 144) must each stay below 4 GiB,
+                               else CMTCS_E_UNSUPPORTED                                     */
   const void* phi;          /* device [row_off[T]][D] float: the stacked Phi_t              */
   cmtcs_dtype_t phi_dtype;  /* F32 for MATH_F64 / MATH_F32; for MATH_MIXED the 16-bit type
                                (BF16 or F16) the library stores Phi in                      */

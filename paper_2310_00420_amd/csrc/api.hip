@@ -561,6 +561,19 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   for (int t = 0; t < p->T; ++t)
     if (p->row_off[t + 1] - p->row_off[t] > (1 << 30))
       return fail(CMTCS_E_INVALID, "N_t too large");
+  {
+    // the operator products address each task's blocks with 32-bit byte offsets
+    const int64_t lim = int64_t(1) << 32, slots = col_slots(p->max_rhs);
+    if (slots * p->D * 8 >= lim)
+      return fail(CMTCS_E_UNSUPPORTED, "column slots * D * 8 bytes must be below 4 GiB");
+    for (int t = 0; t < p->T; ++t) {
+      const int64_t nt = p->row_off[t + 1] - p->row_off[t];
+      if ((nt + 15) / 16 * 16 * p->D * 4 >= lim)
+        return fail(CMTCS_E_UNSUPPORTED, "a task's Phi block (N_t * D * 4 bytes) must be below 4 GiB");
+      if (slots * ((nt + 15) / 16 * 16) * 8 >= lim)
+        return fail(CMTCS_E_UNSUPPORTED, "a task's W block (slots * N_t * 8 bytes) must be below 4 GiB");
+    }
+  }
 
   cmtcs_handle_s* h = new (std::nothrow) cmtcs_handle_s();
   if (h == nullptr) return fail(CMTCS_E_NOMEM, "host allocation failed");

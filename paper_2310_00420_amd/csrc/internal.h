@@ -87,6 +87,39 @@ __device__ inline double block_sum(double v, double* sh) {
   return s;
 }
 
+// Buffer resources for the operator products: loads through a 128-bit descriptor (base and
+// byte length in scalar registers) with a 32-bit per-lane byte offset and a wave-uniform scalar
+// offset, so a load needs no per-lane 64-bit address arithmetic, and bytes past the length read
+// as zeros.  Only the per-lane offset is counted against the length here: a kernel that relies
+// on the zeros rebuilds the descriptor at the wave-uniform start instead of using the scalar
+// offset.
+// The base and length must be wave-uniform; they are moved to scalar registers explicitly
+// (the compiler cannot always prove them uniform and would otherwise loop over the lanes).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ inline rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t b = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  const uint32_t n = __builtin_amdgcn_readfirstlane(bytes);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0, (int)n,
+                                           0x00020000);
+}
+template <typename T> __device__ inline T buf_load(rsrc_t r, uint32_t voff, uint32_t soff) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8 || sizeof(T) == 16 || sizeof(T) == 32,
+                "load size");
+  if constexpr (sizeof(T) == 32) {   // two 16-byte loads
+    typedef uint32_t u8v __attribute__((ext_vector_type(8)));
+    const auto lo = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    const auto hi = __builtin_amdgcn_raw_buffer_load_b128(r, voff + 16, soff, 0);
+    return __builtin_bit_cast(T, u8v{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]});
+  } else if constexpr (sizeof(T) == 16)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  else if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
 // A value every lane of the wave holds equally, moved to a scalar register.
 __device__ inline int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 

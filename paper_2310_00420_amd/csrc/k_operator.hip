@@ -38,13 +38,16 @@ constexpr int kOpWaves = 4;
 // element type of the right-hand sides: measured best at 6 for FP64 (8 spills) and 4 for FP32.
 template <typename VT> constexpr int ring_depth() { return sizeof(VT) == 8 ? 6 : 4; }
 
-// The LDS-staged kernels are offered where they won in the CG loop: FP64 with 16 rows per wave
-// (two waves per SIMD).  With 32 FP64 rows they stay at one wave per SIMD and lose to the
-// register-pipelined kernel, and in FP32 the register-pipelined 64-row tile is faster.
+// The LDS-staged kernel is offered where it won in the CG loop: the FP64 forward product with
+// 16 rows per wave (two waves per SIMD).  With 32 FP64 rows it stays at one wave per SIMD and
+// loses to the register-pipelined kernel; in FP32 the register-pipelined 64-row tile is faster;
+// and an LDS-staged adjoint product, whose contraction over n is four times shorter, lost to
+// the register-pipelined one.
 int op_row_candidates(bool f64, int kind, int* rows) {
-  (void)kind;   // both products offer the same shapes
   if (!f64) { rows[0] = 64; rows[1] = 32; return 2; }   // the first entry is the default
-  rows[0] = 32; rows[1] = 16; rows[2] = -16;
+  rows[0] = 32; rows[1] = 16;
+  if (kind == 1) return 2;
+  rows[2] = -16;
   return 3;
 }
 
@@ -72,17 +75,19 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
 
-  const float* prow[RF];
+  // Phi rows of the task and V_t through buffer descriptors (per-lane 32-bit byte offsets, the
+  // chunk's start as a scalar offset).  Matrix row i16 of fragment rf is Phi row
+  // n0 + rf*16 + a_row(i16), so that the accumulator of lane (g4, r) holds the consecutive rows
+  // n0 + rf*16 + 4 g4 + r.  Rows past N_t lie past the descriptor's end and read as zeros; the
+  // epilogue writes their outputs as zeros anyway.
+  const rsrc_t rphi = make_rsrc(phi + r0 * (int64_t)D, (uint32_t)((int64_t)nt * D * 4));
+  uint32_t aoff[RF];
 #pragma unroll
-  for (int rf = 0; rf < RF; ++rf) {
-    // matrix row i16 of fragment rf is Phi row n0 + rf*16 + a_row(i16), so that the
-    // accumulator of lane (g4, r) holds the consecutive rows n0 + rf*16 + 4 g4 + r.  Rows past
-    // N_t read row 0 of the task instead; they only reach output rows past N_t, which the
-    // epilogue writes as zeros.
-    const int row = n0 + rf * 16 + Mfma<VT>::a_row(i16);
-    prow[rf] = phi + (r0 + (row < nt ? row : 0)) * (int64_t)D + 4 * g4;
-  }
-  const VT* vbase = V + ((int64_t)t * Rp + cf0 * 16 + i16) * D + 4 * g4;
+  for (int rf = 0; rf < RF; ++rf)
+    aoff[rf] = (uint32_t)(((n0 + rf * 16 + Mfma<VT>::a_row(i16)) * D + 4 * g4) * 4);
+  const rsrc_t rv = make_rsrc(V + (int64_t)t * Rp * D, (uint32_t)((int64_t)Rp * D * sizeof(VT)));
+  const uint32_t boff0 = (uint32_t)(((cf0 * 16 + i16) * D + 4 * g4) * sizeof(VT));
+  const uint32_t bstep = (uint32_t)(16 * D * sizeof(VT));
 
   acc_t acc[RF][kColGroup];
 #pragma unroll
@@ -102,16 +107,16 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   f4 a[kRingA][RF];
   vt4 b[2][kColGroup];
   auto load_a = [&](f4 (&x)[RF], int c) __attribute__((always_inline)) {
-    const int d0 = min(c, nch - 1) * 16;
+    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 64);
 #pragma unroll
-    for (int rf = 0; rf < RF; ++rf) x[rf] = *(const f4*)(prow[rf] + d0);
+    for (int rf = 0; rf < RF; ++rf) x[rf] = buf_load<f4>(rphi, aoff[rf], soff);
   };
   auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
-    const int d0 = min(c, nch - 1) * 16;
+    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 16 * (int)sizeof(VT));
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
       const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      x[cf] = *(const vt4*)(vbase + (int64_t)f * 16 * D + d0);
+      x[cf] = buf_load<vt4>(rv, boff0 + (uint32_t)f * bstep, soff);
     }
   };
   auto mma = [&](const f4 (&x)[RF], const vt4 (&y)[kColGroup], auto full)
@@ -232,24 +237,24 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
 
-  const float* prow[RF];
+  // as in k_phi_v: Phi through a buffer descriptor; rows past N_t (also whole tiles of the
+  // block past np) read as zeros and their outputs are zeroed or not stored
+  const rsrc_t rphi = make_rsrc(phi + r0 * (int64_t)D, (uint32_t)((int64_t)nt * D * 4));
+  uint32_t aoff[RF];
 #pragma unroll
-  for (int rf = 0; rf < RF; ++rf) {
-    // as in k_phi_v: rows past N_t (also whole tiles of the block past np) read row 0 and
-    // their outputs are zeroed or not stored
-    const int row = n0 + rf * 16 + Mfma<VT>::a_row(i16);
-    prow[rf] = phi + (r0 + (row < nt ? row : 0)) * (int64_t)D + 4 * g4;
-  }
+  for (int rf = 0; rf < RF; ++rf)
+    aoff[rf] = (uint32_t)(((n0 + rf * 16 + Mfma<VT>::a_row(i16)) * D + 4 * g4) * 4);
   // staging: piece p of the chunk is column p / kPieces, 16-byte piece p % kPieces; pieces past
   // the group's columns are clamped onto the last one (a duplicate load and an identical store)
   const int npieces = 16 * ncf * L::kPieces;
-  const VT* ssrc[L::kPerThread];
+  const rsrc_t rv = make_rsrc(V + (int64_t)t * Rp * D, (uint32_t)((int64_t)Rp * D * sizeof(VT)));
+  uint32_t soff_v[L::kPerThread];
   VT* sdst[2][L::kPerThread];
 #pragma unroll
   for (int i = 0; i < L::kPerThread; ++i) {
     const int p = min((int)threadIdx.x + i * 64 * kOpWaves, npieces - 1);
     const int col = p / L::kPieces, q = p % L::kPieces;
-    ssrc[i] = V + ((int64_t)t * Rp + cf0 * 16 + col) * D + q * L::kPer16;
+    soff_v[i] = (uint32_t)(((cf0 * 16 + col) * D + q * L::kPer16) * sizeof(VT));
     sdst[0][i] = &lds[0][col][q * L::kPer16];
     sdst[1][i] = &lds[1][col][q * L::kPer16];
   }
@@ -264,14 +269,14 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   f4 a[kRingA][RF];
   piece_t stg[L::kPerThread];
   auto load_a = [&](f4 (&x)[RF], int c) __attribute__((always_inline)) {
-    const int d0 = min(c, nch - 1) * 16;
+    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 64);
 #pragma unroll
-    for (int rf = 0; rf < RF; ++rf) x[rf] = *(const f4*)(prow[rf] + d0);
+    for (int rf = 0; rf < RF; ++rf) x[rf] = buf_load<f4>(rphi, aoff[rf], soff);
   };
   auto stage_load = [&](int c) __attribute__((always_inline)) {
-    const int d0 = min(c, nch - 1) * 16;
+    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 16 * (int)sizeof(VT));
 #pragma unroll
-    for (int i = 0; i < L::kPerThread; ++i) stg[i] = *(const piece_t*)(ssrc[i] + d0);
+    for (int i = 0; i < L::kPerThread; ++i) stg[i] = buf_load<piece_t>(rv, soff_v[i], soff);
   };
   auto stage_store = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
@@ -434,9 +439,15 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
   const int dl = d0 + RF * i16;          // first of the RF output rows this lane loads
-  const bool dval = dl < D;
-  const float* pbase = phi + r0 * (int64_t)D + (dval ? dl : 0);
-  const VT* wbase = W + w_off[t] + (int64_t)(cf0 * 16 + i16) * np + 4 * g4;
+  // Phi rows of the task and W_t through buffer descriptors: per-lane 32-bit byte offsets,
+  // the chunk's start in scalar registers.  Lanes past D read column 0 (outputs not stored).
+  const float* phit = phi + r0 * (int64_t)D;
+  uint32_t aoff[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) aoff[s] = (uint32_t)(((4 * g4 + s) * D + (dl < D ? dl : 0)) * 4);
+  const rsrc_t rw = make_rsrc(W + w_off[t], (uint32_t)((int64_t)Rp * np * sizeof(VT)));
+  const uint32_t boff0 = (uint32_t)(((cf0 * 16 + i16) * np + 4 * g4) * sizeof(VT));
+  const uint32_t bstep = (uint32_t)(16 * np * sizeof(VT));
 
   acc_t acc[RF][kColGroup];
 #pragma unroll
@@ -445,26 +456,23 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
     for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
 
   // Software pipeline as in k_phi_v, over chunks of 16 along n (Phi kRingA - 1 chunks ahead, W
-  // one).
-  // Rows past N_t read row 0 of the task: they meet rows of W that the forward product wrote as
-  // zeros.  Lanes past D read column 0 and feed only output rows that are not stored.
+  // one).  The Phi descriptor of a chunk starts at its first row and ends at row N_t, so rows
+  // past N_t read as zeros (and would meet zero rows of W anyway).
   const int nch = np / 16;
   frf a[kRingA][4];
   vt4 b[2][kColGroup];
   auto load_a = [&](frf (&x)[4], int c) __attribute__((always_inline)) {
-    const int nb = min(c, nch - 1) * 16;
+    const int nb = uniform(min(c, nch - 1) * 16);
+    const rsrc_t ra = make_rsrc(phit + (int64_t)nb * D, (uint32_t)((int64_t)(nt - nb) * D * 4));
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int n = nb + 4 * g4 + s;
-      x[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
-    }
+    for (int s = 0; s < 4; ++s) x[s] = buf_load<frf>(ra, aoff[s], 0);
   };
   auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
-    const int nb = min(c, nch - 1) * 16;
+    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 16 * (int)sizeof(VT));
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
       const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      x[cf] = *(const vt4*)(wbase + (int64_t)f * 16 * np + nb);
+      x[cf] = buf_load<vt4>(rw, boff0 + (uint32_t)f * bstep, soff);
     }
   };
   auto mma = [&](const frf (&x)[4], const vt4 (&y)[kColGroup], auto full)
@@ -514,130 +522,6 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
   phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
 }
 
-// LDS-staged adjoint product: as k_phi_v_lds, a block of four waves owns four consecutive
-// 16*RF-row tiles (rows of d) of one task and column group and shares each chunk of W_t (16 rows
-// of n for the group's columns) through an LDS double buffer; Phi^T comes from the rows of Phi
-// as in k_phit_w.
-template <typename VT, int RF>
-__global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void k_phit_w_lds(
-    const float* __restrict__ phi, const int64_t* __restrict__ row_off,
-    const int64_t* __restrict__ w_off, const int4* __restrict__ tiles, int ntiles,
-    const VT* __restrict__ W, const VT* __restrict__ V, VT* __restrict__ AV,
-    const float* __restrict__ alpha, const int* __restrict__ colc, double beta,
-    const int* __restrict__ act, int D, int Rp) {
-  typedef typename Mfma<VT>::acc_t acc_t;
-  typedef typename VecOf<VT, 4>::type vt4;
-  typedef typename VecOf<float, RF>::type frf;
-  typedef LdsChunk<VT> L;
-  typedef typename L::piece_t piece_t;
-  constexpr int kRingA = ring_depth<VT>();
-  __shared__ VT lds[2][16 * kColGroup][L::kLd];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i16 = lane & 15, g4 = lane >> 4;
-  const int blk = uniform(xcd_block(blockIdx.x, gridDim.x));
-  if (blk >= ntiles) return;
-  const int4 tl = tiles[blk];
-  const int t = uniform(tl.x), cf0 = uniform(tl.z) * kColGroup;
-  const int d0 = uniform(tl.y) + uniform(wave) * 16 * RF;
-  if (act != nullptr && act[t] == 0) return;   // uniform over the block
-  const int64_t r0 = row_off[t];
-  const int nt = (int)(row_off[t + 1] - r0);
-  const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
-  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
-  // as in k_phit_w: lanes past D (also whole tiles of the block past D) read column 0 and their
-  // outputs are not stored; rows past N_t read row 0 and meet zero rows of W
-  const int dl = d0 + RF * i16;
-  const float* pbase = phi + r0 * (int64_t)D + (dl < D ? dl : 0);
-  const int npieces = 16 * ncf * L::kPieces;
-  const VT* ssrc[L::kPerThread];
-  VT* sdst[2][L::kPerThread];
-#pragma unroll
-  for (int i = 0; i < L::kPerThread; ++i) {
-    const int p = min((int)threadIdx.x + i * 64 * kOpWaves, npieces - 1);
-    const int col = p / L::kPieces, q = p % L::kPieces;
-    ssrc[i] = W + w_off[t] + (int64_t)(cf0 * 16 + col) * np + q * L::kPer16;
-    sdst[0][i] = &lds[0][col][q * L::kPer16];
-    sdst[1][i] = &lds[1][col][q * L::kPer16];
-  }
-
-  acc_t acc[RF][kColGroup];
-#pragma unroll
-  for (int f = 0; f < RF; ++f)
-#pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
-
-  const int nch = np / 16;
-  frf a[kRingA][4];
-  piece_t stg[L::kPerThread];
-  auto load_a = [&](frf (&x)[4], int c) __attribute__((always_inline)) {
-    const int nb = min(c, nch - 1) * 16;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int n = nb + 4 * g4 + s;
-      x[s] = *(const frf*)(pbase + (n < nt ? (int64_t)n * D : 0));
-    }
-  };
-  auto stage_load = [&](int c) __attribute__((always_inline)) {
-    const int nb = min(c, nch - 1) * 16;
-#pragma unroll
-    for (int i = 0; i < L::kPerThread; ++i) stg[i] = *(const piece_t*)(ssrc[i] + nb);
-  };
-  auto stage_store = [&](int buf) __attribute__((always_inline)) {
-#pragma unroll
-    for (int i = 0; i < L::kPerThread; ++i) *(piece_t*)sdst[buf][i] = stg[i];
-  };
-  auto step = [&](const frf (&x)[4], int buf, auto full) __attribute__((always_inline)) {
-    vt4 b[kColGroup];
-#pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf)
-      if (decltype(full)::value || cf < ncf) b[cf] = lds_frag<VT>(&lds[buf][cf * 16 + i16][4 * g4]);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-      for (int cf = 0; cf < kColGroup; ++cf)
-        if (decltype(full)::value || cf < ncf)
-#pragma unroll
-          for (int f = 0; f < RF; ++f) {
-            float av;
-            if constexpr (RF == 1) av = x[s]; else av = x[s][f];
-            acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], acc[f][cf]);
-          }
-  };
-  // the same schedule as k_phi_v_lds
-  auto run = [&](auto full) __attribute__((always_inline)) {
-    stage_load(0);
-#pragma unroll
-    for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
-    stage_store(0);
-    stage_load(1);
-    __syncthreads();
-    int c = 0;
-    for (; c + kRingA <= nch; c += kRingA) {
-#pragma unroll
-      for (int i = 0; i < kRingA; ++i) {
-        step(a[i], i & 1, full);
-        stage_store((i + 1) & 1);
-        stage_load(c + i + 2);
-        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
-        __syncthreads();
-      }
-    }
-#pragma unroll
-    for (int i = 0; i + 1 < kRingA; ++i) {
-      if (c + i >= nch) break;
-      step(a[i], i & 1, full);
-      stage_store((i + 1) & 1);
-      stage_load(c + i + 2);
-      __syncthreads();
-    }
-  };
-  if (nch > 0) {   // uniform over the block; an empty task's product is zero
-    if (ncf == kColGroup) run(std::true_type{});
-    else run(std::false_type{});
-  }
-  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
-}
-
 template <typename VT, int RF>
 static hipError_t phi_v_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                            const VT* V, VT* W, const int* act, hipStream_t st) {
@@ -684,28 +568,12 @@ hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, 
   return hipErrorInvalidValue;
 }
 
-template <typename VT, int RF>
-static hipError_t phit_w_lds_rf(const Geometry& g, const float* phi, const int4* tiles,
-                                int ntiles, const VT* W, const VT* V, VT* AV, const float* alpha,
-                                const int* colc, double beta, const int* act, hipStream_t st) {
-  hipLaunchKernelGGL((k_phit_w_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
-                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
-                     g.Rp);
-  return hipGetLastError();
-}
-
 template <typename VT>
 hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
                          double beta, const int* act, int rows, hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
-  if (rows < 0) {   // LDS-staged variant: one tile per block of four waves of -rows rows each
-    if constexpr (sizeof(VT) == 8) {
-      if (rows == -16)
-        return phit_w_lds_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
-    }
-    return hipErrorInvalidValue;
-  }
+
   if constexpr (sizeof(VT) == 8) {
     if (rows == 16)
       return phit_w_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);

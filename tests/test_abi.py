@@ -63,6 +63,8 @@ def _problem(**over):
     (dict(math=_lib.CMTCS_MATH_MIXED), "MATH_MIXED"),
     (dict(math=_lib.CMTCS_MATH_MIXED, phi_dtype=_lib.CMTCS_BF16, D=48), "multiple of 32"),
     (dict(phi_dtype=_lib.CMTCS_BF16), "phi_dtype F32"),
+    (dict(D=16384, row_off=np.array([0, 4, 65540], np.int64)), "Phi block"),
+    (dict(D=16384, max_rhs=40000), "column slots"),
 ])
 def test_create_rejects_bad_problems(over, frag):
     lib = _lib.load()
