@@ -145,6 +145,20 @@ def test_estep_batch_config_f64_sampled_tasks():
     assert err["iters_excess"] <= 0
 
 
+@pytest.mark.parametrize("D", [8192, 16384])
+def test_estep_largest_d_f64(D):
+    """The two widest column shapes of the CG kernels (1024 threads with 8 and 16 elements each)
+    up to the largest supported D, with ragged tasks.  beta = 1 and alpha in (1, 2) make the
+    systems well conditioned (condition ~ D / N_t), so CG converges to tol 1e-10 and the
+    solution is unique up to rounding; at the configurations' beta = 1e4 and a few dozen fixed
+    steps the oracle moves by up to 2% with its own summation order and pins nothing."""
+    w = synth.make(synth.Config("wide", T=2, C=2, D=D, N=[48, 17], sparsity=8, groups=2, K=3,
+                                tol=1e-10, max_iters=400, sigma=1.0))
+    err, g, ref, sp = _run(w, range(w.T), alpha=w.alpha0 + 1.0)
+    _assert(err, sp)
+    assert (g["status"].cpu().numpy() == 0).all()
+
+
 def test_estep_ragged_edge_f64():
     """Ragged N_t including an empty task, D spanning several tiles with a partial last one,
     C*(K+1) not a multiple of 16, tolerance mode."""
