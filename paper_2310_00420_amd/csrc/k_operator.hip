@@ -16,6 +16,7 @@
 // right-hand-side block (V_t or W_t) is re-read by all tiles of a task and stays in L2, which is
 // why the block index is remapped so that the tiles of one task run on the same XCD.
 #include <type_traits>
+#include <utility>
 
 #include "internal.h"
 
@@ -90,10 +91,12 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   const uint32_t bstep = (uint32_t)(16 * D * sizeof(VT));
 
   acc_t acc[RF][kColGroup];
+  auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
-  for (int rf = 0; rf < RF; ++rf)
+    for (int rf = 0; rf < RF; ++rf)
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
+      for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
+  };
 
   // Software pipeline over chunks of 16 along d.  The Phi operand streams from HBM (it misses
   // L2 every time), so it is prefetched kRingA - 1 chunks ahead in a ring of register buffers;
@@ -119,7 +122,8 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
       x[cf] = buf_load<vt4>(rv, boff0 + (uint32_t)f * bstep, soff);
     }
   };
-  auto mma = [&](const f4 (&x)[RF], const vt4 (&y)[kColGroup], auto full)
+  // first: the chunk that starts the accumulation (its first k-step takes a zero accumulator)
+  auto mma = [&](const f4 (&x)[RF], const vt4 (&y)[kColGroup], auto full, auto first)
       __attribute__((always_inline)) {
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -127,33 +131,47 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
 #pragma unroll
-          for (int rf = 0; rf < RF; ++rf)
-            acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], y[cf][s], acc[rf][cf]);
+          for (int rf = 0; rf < RF; ++rf) {
+            const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[rf][cf];
+            acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], y[cf][s], cin);
+          }
+  };
+  auto slot = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic)::value;
+    load_b(b[(i + 1) & 1], c + i + 1, full);
+    load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+    // the scheduling barriers keep the compiler from moving loads across the MFMAs they
+    // should overlap, or conversions up to their loads
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a[i], b[i & 1], full, first);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+    static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
+      slot(c, ic, full,
+           std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
+    });
   };
   auto run = [&](auto full) __attribute__((always_inline)) {
     load_b(b[0], 0, full);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
     int c = 0;
-    for (; c + kRingA <= nch; c += kRingA) {
-      // entering: a[i] holds chunk c+i for i < kRingA-1 and b[0] chunk c.  Fully unrolled, so
-      // every ring index is a constant.  The scheduling barriers keep the compiler from moving
-      // loads across the MFMAs they should overlap, or conversions up to their loads.
-#pragma unroll
-      for (int i = 0; i < kRingA; ++i) {
-        load_b(b[(i + 1) & 1], c + i + 1, full);
-        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(a[i], b[i & 1], full);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+    if (nch >= kRingA) {
+      // rounds of kRingA chunks; the first is peeled so that the accumulators start in the
+      // matrix-core result registers (a zero input to the first k-step) instead of as zeros
+      // carried into the loop, which made the compiler copy them across every iteration
+      ring(0, full, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
+    } else {
+      zero_acc();
     }
     // fewer than kRingA chunks left: chunk c+i is in a[i], chunk c's right-hand side in b[0]
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
       if (i > 0) load_b(b[i & 1], c + i, full);
-      mma(a[i], b[i & 1], full);
+      mma(a[i], b[i & 1], full, std::false_type{});
     }
   };
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
@@ -260,10 +278,12 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   }
 
   acc_t acc[RF][kColGroup];
+  auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
-  for (int rf = 0; rf < RF; ++rf)
+    for (int rf = 0; rf < RF; ++rf)
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
+      for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
+  };
 
   const int nch = D / 16;
   f4 a[kRingA][RF];
@@ -282,7 +302,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
 #pragma unroll
     for (int i = 0; i < L::kPerThread; ++i) *(piece_t*)sdst[buf][i] = stg[i];
   };
-  auto step = [&](const f4 (&x)[RF], int buf, auto full) __attribute__((always_inline)) {
+  auto step = [&](const f4 (&x)[RF], int buf, auto full, auto first) __attribute__((always_inline)) {
     vt4 b[kColGroup];
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
@@ -293,13 +313,29 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
 #pragma unroll
-          for (int rf = 0; rf < RF; ++rf)
-            acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], b[cf][s], acc[rf][cf]);
+          for (int rf = 0; rf < RF; ++rf) {
+            const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[rf][cf];
+            acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], b[cf][s], cin);
+          }
   };
   // Per chunk c (buffer c & 1): multiply; store the staged chunk c+1 into the other buffer
   // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+2; then the
   // Phi load of chunk c + kRingA - 1, issued after the staging loads so that the next wait for
   // staged data does not also wait for it; barrier.
+  auto chunk = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic)::value;
+    step(a[i], i & 1, full, first);
+    stage_store((i + 1) & 1);
+    stage_load(c + i + 2);
+    load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+    __syncthreads();
+  };
+  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+    static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
+      chunk(c, ic, full,
+            std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
+    });
+  };
   auto run = [&](auto full) __attribute__((always_inline)) {
     stage_load(0);
 #pragma unroll
@@ -308,20 +344,17 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     stage_load(1);
     __syncthreads();
     int c = 0;
-    for (; c + kRingA <= nch; c += kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
-#pragma unroll
-      for (int i = 0; i < kRingA; ++i) {
-        step(a[i], i & 1, full);
-        stage_store((i + 1) & 1);
-        stage_load(c + i + 2);
-        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
-        __syncthreads();
-      }
+    if (nch >= kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
+      // first round peeled so that the accumulators start in the matrix-core result registers
+      ring(0, full, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
+    } else {
+      zero_acc();
     }
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
-      step(a[i], i & 1, full);
+      step(a[i], i & 1, full, std::false_type{});
       stage_store((i + 1) & 1);
       stage_load(c + i + 2);
       __syncthreads();
@@ -423,10 +456,13 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
                                                 const int* __restrict__ colc, double beta,
                                                 const int* __restrict__ act, int D, int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
-  typedef typename VecOf<VT, 4>::type vt4;
-  constexpr int kRingA = ring_depth<VT>();
   typedef typename VecOf<float, RF>::type frf;
-  typedef typename VecOf<VT, RF>::type vrf;
+  // k-steps of the 16x16x4 tiles per chunk (chunks of KC = 16 rows of n; 8-row chunks, with
+  // 16-byte right-hand-side fragments, measured 2.5% slower in FP64)
+  constexpr int KS = 4;
+  constexpr int KC = 4 * KS;
+  typedef typename VecOf<VT, KS>::type vtk;
+  constexpr int kRingA = ring_depth<VT>();
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * kOpWaves + (threadIdx.x >> 6));
@@ -442,43 +478,50 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
   // Phi rows of the task and W_t through buffer descriptors: per-lane 32-bit byte offsets,
   // the chunk's start in scalar registers.  Lanes past D read column 0 (outputs not stored).
   const float* phit = phi + r0 * (int64_t)D;
-  uint32_t aoff[4];
+  uint32_t aoff[KS];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) aoff[s] = (uint32_t)(((4 * g4 + s) * D + (dl < D ? dl : 0)) * 4);
+  for (int s = 0; s < KS; ++s) aoff[s] = (uint32_t)(((KS * g4 + s) * D + (dl < D ? dl : 0)) * 4);
   const rsrc_t rw = make_rsrc(W + w_off[t], (uint32_t)((int64_t)Rp * np * sizeof(VT)));
-  const uint32_t boff0 = (uint32_t)(((cf0 * 16 + i16) * np + 4 * g4) * sizeof(VT));
+  const uint32_t boff0 = (uint32_t)(((cf0 * 16 + i16) * np + KS * g4) * sizeof(VT));
   const uint32_t bstep = (uint32_t)(16 * np * sizeof(VT));
 
   acc_t acc[RF][kColGroup];
+  auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
-  for (int f = 0; f < RF; ++f)
+    for (int f = 0; f < RF; ++f)
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
-
-  // Software pipeline as in k_phi_v, over chunks of 16 along n (Phi kRingA - 1 chunks ahead, W
-  // one).  The Phi descriptor of a chunk starts at its first row and ends at row N_t, so rows
-  // past N_t read as zeros (and would meet zero rows of W anyway).
-  const int nch = np / 16;
-  frf a[kRingA][4];
-  vt4 b[2][kColGroup];
-  auto load_a = [&](frf (&x)[4], int c) __attribute__((always_inline)) {
-    const int nb = uniform(min(c, nch - 1) * 16);
-    const rsrc_t ra = make_rsrc(phit + (int64_t)nb * D, (uint32_t)((int64_t)(nt - nb) * D * 4));
-#pragma unroll
-    for (int s = 0; s < 4; ++s) x[s] = buf_load<frf>(ra, aoff[s], 0);
+      for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
   };
-  auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
-    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 16 * (int)sizeof(VT));
+
+  // Software pipeline as in k_phi_v, over chunks of KC rows of n (Phi kRingA - 1 chunks ahead,
+  // W one; lane g4 takes rows KS g4 .. KS g4 + KS - 1 of a chunk in the KS k-steps).  The Phi
+  // descriptor of a chunk starts at its first row and ends at row N_t, so rows past N_t read as
+  // zeros (and would meet zero rows of W anyway).
+  const int nch = np / KC;
+  frf a[kRingA][KS];
+  vtk b[2][kColGroup];
+  auto load_a = [&](frf (&x)[KS], int c) __attribute__((always_inline)) {
+    // a chunk starting past N_t gets length zero, so every lane reads zeros (a negative
+    // length would wrap to an unchecked one)
+    const int nb = uniform(min(c, nch - 1) * KC);
+    const rsrc_t ra = make_rsrc(phit + (int64_t)nb * D,
+                                (uint32_t)((int64_t)max(nt - nb, 0) * D * 4));
+#pragma unroll
+    for (int s = 0; s < KS; ++s) x[s] = buf_load<frf>(ra, aoff[s], 0);
+  };
+  auto load_b = [&](vtk (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
+    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * KC * (int)sizeof(VT));
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
       const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      x[cf] = buf_load<vt4>(rw, boff0 + (uint32_t)f * bstep, soff);
+      x[cf] = buf_load<vtk>(rw, boff0 + (uint32_t)f * bstep, soff);
     }
   };
-  auto mma = [&](const frf (&x)[4], const vt4 (&y)[kColGroup], auto full)
+  // first: the chunk that starts the accumulation (its first k-step takes a zero accumulator)
+  auto mma = [&](const frf (&x)[KS], const vtk (&y)[kColGroup], auto full, auto first)
       __attribute__((always_inline)) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
@@ -486,34 +529,46 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
           for (int f = 0; f < RF; ++f) {
             float av;
             if constexpr (RF == 1) av = x[s]; else av = x[s][f];
-            acc[f][cf] = Mfma<VT>::mma((VT)av, y[cf][s], acc[f][cf]);
+            const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[f][cf];
+            acc[f][cf] = Mfma<VT>::mma((VT)av, y[cf][s], cin);
           }
   };
+  // one slot of the pipeline: chunk c + i from ring entry i, loads for the chunks ahead
+  auto slot = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic)::value;
+    load_b(b[(i + 1) & 1], c + i + 1, full);
+    load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mma(a[i], b[i & 1], full, first);
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+    static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
+      slot(c, ic, full,
+           std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
+    });
+  };
   auto run = [&](auto full) __attribute__((always_inline)) {
-    if (nch == 0) return;   // empty task: the product is zero
+    if (nch < kRingA) {   // small task: a zero start and the tail alone
+      zero_acc();
+      if (nch == 0) return;   // empty task: the product is zero
+    }
     load_b(b[0], 0, full);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
     int c = 0;
-    for (; c + kRingA <= nch; c += kRingA) {
-      // entering: a[i] holds chunk c+i for i < kRingA-1 and b[0] chunk c.  Fully unrolled, so
-      // every ring index is a constant.  The scheduling barriers keep the compiler from moving
-      // loads across the MFMAs they should overlap, or conversions up to their loads.
-#pragma unroll
-      for (int i = 0; i < kRingA; ++i) {
-        load_b(b[(i + 1) & 1], c + i + 1, full);
-        load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(a[i], b[i & 1], full);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+    if (nch >= kRingA) {
+      // the first round is peeled so that the accumulators start in the matrix-core result
+      // registers (a zero input to the first k-step) rather than as zeros carried into the loop
+      ring(0, full, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
     }
     // fewer than kRingA chunks left: chunk c+i is in a[i], chunk c's right-hand side in b[0]
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
       if (i > 0) load_b(b[i & 1], c + i, full);
-      mma(a[i], b[i & 1], full);
+      mma(a[i], b[i & 1], full, std::false_type{});
     }
   };
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
