@@ -242,9 +242,9 @@ struct cmtcs_handle_s {
       for (int t = 0; t < T; ++t) {
         const int np = (int)((row_off[t + 1] - row_off[t] + 31) / 32 * 32);
         w16[t + 1] = w16[t] + (int64_t)Rp * np;
-        for (int n0 = 0; n0 < np; n0 += kRows16)
+        for (int n0 = 0; n0 < np; n0 += 4 * kRows16)   // one tile per block of four waves
           for (int cg = 0; cg < ng; ++cg) f16.push_back(make_int4(t, n0, cg, 0));
-        for (int d0 = 0; d0 < D; d0 += kRows16)
+        for (int d0 = 0; d0 < D; d0 += 4 * kRows16)
           for (int cg = 0; cg < ng; ++cg) a16.push_back(make_int4(t, d0, cg, 0));
       }
       HIP_TRY(hipMemcpyAsync(w16_off_d, w16.data(), sizeof(int64_t) * (T + 1),

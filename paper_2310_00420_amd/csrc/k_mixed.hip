@@ -48,45 +48,120 @@ constexpr int kRF16 = kRows16 / 16;   // 64 output rows per wave tile
 // is unconditional (chunk index clamped, a missing column fragment re-reads the last present
 // one) and no loaded value is touched before its MFMA, so each chunk waits only for the buffer
 // it multiplies.
+// Shared main loop of the 16-bit products for one block of four waves (four consecutive 64-row
+// tiles of one task and column group): acc[rf][cf] += M[rows of rf][k] * V[cols of cf][k] over
+// k in [0, K), K a multiple of 32.  mrow[rf] points at this wave's row (tile row rf*16 + i16)
+// + 8*g4 (a row past the end of M points at a valid row, whose outputs the caller drops); vsrc
+// points at column cf0*16 of the right-hand-side block, columns vld elements apart.
+//
+// The right-hand-side chunk (32 k x up to 144 columns, 9 KB) that all four waves multiply is
+// staged once per block into an LDS double buffer (rows padded to 80 bytes, so that the eight
+// lanes served together read distinct banks): loading it per wave made the kernel bound by the
+// CU's vector-memory throughput.  Phi is prefetched kRing16 - 1 chunks ahead in registers.  As in
+// the FP64/FP32 products, every load is unconditional, and the first round is peeled so that
+// the accumulators start in the matrix-core result registers.
+constexpr int kRing16 = 4;
+constexpr int kLd16 = 40;                                      // padded LDS row (elements)
+constexpr int kPieces16 = 4;                                   // 16-byte pieces per column chunk
+constexpr int kPer16 = (16 * kColGroup * kPieces16 + 255) / 256;
+
 template <typename T16>
 __device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* const (&mrow)[kRF16],
-                                     const T16* vcol, int64_t vld, int ncf, int K) {
+                                     const T16* vsrc, int64_t vld, int ncf, int K,
+                                     T16 (*lds)[16 * kColGroup][kLd16]) {
   typedef typename Mfma16<T16>::v8 v8;
+  const int lane = threadIdx.x & 63, i16 = lane & 15, g4 = lane >> 4;
   const int nch = K / 32;
-  if (nch == 0) return;
-  v8 a0[kRF16], a1[kRF16], b0[kColGroup], b1[kColGroup];
-  auto load = [&](v8 (&a)[kRF16], v8 (&b)[kColGroup], int c, auto full)
-      __attribute__((always_inline)) {
+  auto zero_acc = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int rf = 0; rf < kRF16; ++rf)
+#pragma unroll
+      for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = f4{0.f, 0.f, 0.f, 0.f};
+  };
+  if (nch == 0) { zero_acc(); return; }   // uniform over the block
+  // staging: piece p is column p / kPieces16, 16-byte piece p % kPieces16; pieces past the
+  // group's columns are clamped onto the last one (a duplicate load and an identical store)
+  const int npieces = 16 * ncf * kPieces16;
+  const T16* ssrc[kPer16];
+  T16* sdst[2][kPer16];
+#pragma unroll
+  for (int i = 0; i < kPer16; ++i) {
+    const int p = min((int)threadIdx.x + i * 256, npieces - 1);
+    const int col = p / kPieces16, q = p % kPieces16;
+    ssrc[i] = vsrc + (int64_t)col * vld + q * 8;
+    sdst[0][i] = &lds[0][col][q * 8];
+    sdst[1][i] = &lds[1][col][q * 8];
+  }
+  v8 a[kRing16][kRF16], stg[kPer16];
+  auto load_a = [&](v8 (&x)[kRF16], int c) __attribute__((always_inline)) {
     const int k0 = min(c, nch - 1) * 32;
 #pragma unroll
-    for (int rf = 0; rf < kRF16; ++rf) a[rf] = *(const v8*)(mrow[rf] + k0);
-#pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) {
-      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      b[cf] = *(const v8*)(vcol + (int64_t)f * 16 * vld + k0);
-    }
+    for (int rf = 0; rf < kRF16; ++rf) x[rf] = *(const v8*)(mrow[rf] + k0);
   };
-  auto mma = [&](const v8 (&a)[kRF16], const v8 (&b)[kColGroup], auto full)
+  auto stage_load = [&](int c) __attribute__((always_inline)) {
+    const int k0 = min(c, nch - 1) * 32;
+#pragma unroll
+    for (int i = 0; i < kPer16; ++i) stg[i] = *(const v8*)(ssrc[i] + k0);
+  };
+  auto stage_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < kPer16; ++i) *(v8*)sdst[buf][i] = stg[i];
+  };
+  auto step = [&](const v8 (&x)[kRF16], int buf, auto full, auto first)
       __attribute__((always_inline)) {
+    v8 bv[kColGroup];
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (decltype(full)::value || cf < ncf) bv[cf] = *(const v8*)&lds[buf][cf * 16 + i16][8 * g4];
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (decltype(full)::value || cf < ncf)
 #pragma unroll
-        for (int rf = 0; rf < kRF16; ++rf) acc[rf][cf] = Mfma16<T16>::mma(a[rf], b[cf], acc[rf][cf]);
+        for (int rf = 0; rf < kRF16; ++rf) {
+          const f4 cin = decltype(first)::value ? f4{0.f, 0.f, 0.f, 0.f} : acc[rf][cf];
+          acc[rf][cf] = Mfma16<T16>::mma(x[rf], bv[cf], cin);
+        }
+  };
+  // per chunk c (buffer c & 1): multiply; store the staged chunk c+1 into the other buffer
+  // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+2; then the Phi
+  // load of chunk c + kRing16 - 1 (after the staging loads: the memory counter completes in
+  // issue order); barrier
+  auto chunk = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic)::value;
+    step(a[i], i & 1, full, first);
+    stage_store((i + 1) & 1);
+    stage_load(c + i + 2);
+    load_a(a[(i + kRing16 - 1) % kRing16], c + i + kRing16 - 1);
+    __syncthreads();
+  };
+  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+    static_for<kRing16>([&](auto ic) __attribute__((always_inline)) {
+      chunk(c, ic, full,
+            std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
+    });
   };
   auto run = [&](auto full) __attribute__((always_inline)) {
-    load(a0, b0, 0, full);
-    for (int c = 0; c + 1 < nch; c += 2) {
-      load(a1, b1, c + 1, full);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a0, b0, full);
-      __builtin_amdgcn_sched_barrier(0);
-      load(a0, b0, c + 2, full);
-      __builtin_amdgcn_sched_barrier(0);
-      mma(a1, b1, full);
-      __builtin_amdgcn_sched_barrier(0);
+    stage_load(0);
+#pragma unroll
+    for (int i = 0; i + 1 < kRing16; ++i) load_a(a[i], i);
+    stage_store(0);
+    stage_load(1);
+    __syncthreads();
+    int c = 0;
+    if (nch >= kRing16) {   // kRing16 is even: chunk c + i is in buffer i & 1
+      ring(0, full, std::true_type{});
+      for (c = kRing16; c + kRing16 <= nch; c += kRing16) ring(c, full, std::false_type{});
+    } else {
+      zero_acc();
     }
-    if (nch & 1) mma(a0, b0, full);   // odd chunk count: the last chunk is in buffer 0
+#pragma unroll
+    for (int i = 0; i + 1 < kRing16; ++i) {
+      if (c + i >= nch) break;
+      step(a[i], i & 1, full, std::false_type{});
+      stage_store((i + 1) & 1);
+      stage_load(c + i + 2);
+      __syncthreads();
+    }
   };
   if (ncf == kColGroup) run(std::true_type{});
   else run(std::false_type{});
@@ -101,12 +176,15 @@ __global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
                                                  const T16* __restrict__ V16,
                                                  T16* __restrict__ W16,
                                                  const int* __restrict__ act, int D, int Rp) {
+  __shared__ T16 lds[2][16 * kColGroup][kLd16];
   const int lane = threadIdx.x & 63, i16 = lane & 15, g4 = lane >> 4;
-  const int tile = uniform(xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
-  if (tile >= ntiles) return;
-  const int4 tl = tiles[tile];
-  const int t = uniform(tl.x), n0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
-  if (act != nullptr && act[t] == 0) return;
+  // one tile per block: four waves of kRows16 rows each
+  const int blk = uniform(xcd_block16(blockIdx.x, gridDim.x));
+  if (blk >= ntiles) return;
+  const int4 tl = tiles[blk];
+  const int t = uniform(tl.x), cf0 = uniform(tl.z) * kColGroup;
+  const int n0 = uniform(tl.y) + uniform((int)(threadIdx.x >> 6)) * kRows16;
+  if (act != nullptr && act[t] == 0) return;   // uniform over the block
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w16_off[t + 1] - w16_off[t]) / Rp);
@@ -118,13 +196,8 @@ __global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
     const int row = n0 + rf * 16 + i16;
     mrow[rf] = phi16 + (r0 + (row < nt ? row : 0)) * (int64_t)D + 8 * g4;
   }
-  const T16* vcol = V16 + ((int64_t)t * Rp + cf0 * 16 + i16) * D + 8 * g4;
   f4 acc[kRF16][kColGroup];
-#pragma unroll
-  for (int rf = 0; rf < kRF16; ++rf)
-#pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = f4{0.f, 0.f, 0.f, 0.f};
-  nt16_mainloop<T16>(acc, mrow, vcol, D, ncf, D);
+  nt16_mainloop<T16>(acc, mrow, V16 + ((int64_t)t * Rp + cf0 * 16) * D, D, ncf, D, lds);
   typedef T16 t4 __attribute__((ext_vector_type(4)));
   T16* Wt = W16 + w16_off[t];
 #pragma unroll
@@ -155,12 +228,15 @@ __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16
                                                   const float* __restrict__ alpha,
                                                   const int* __restrict__ colc, double beta,
                                                   const int* __restrict__ act, int D, int Rp) {
+  __shared__ T16 lds[2][16 * kColGroup][kLd16];
   const int lane = threadIdx.x & 63, i16 = lane & 15, g4 = lane >> 4;
-  const int tile = uniform(xcd_block16(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
-  if (tile >= ntiles) return;
-  const int4 tl = tiles[tile];
-  const int t = uniform(tl.x), d0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
-  if (act != nullptr && act[t] == 0) return;
+  // one tile per block: four waves of kRows16 rows (of d) each
+  const int blk = uniform(xcd_block16(blockIdx.x, gridDim.x));
+  if (blk >= ntiles) return;
+  const int4 tl = tiles[blk];
+  const int t = uniform(tl.x), cf0 = uniform(tl.z) * kColGroup;
+  const int d0 = uniform(tl.y) + uniform((int)(threadIdx.x >> 6)) * kRows16;
+  if (act != nullptr && act[t] == 0) return;   // uniform over the block
   const int64_t wo = w16_off[t];
   const int np = (int)((w16_off[t + 1] - wo) / Rp);
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
@@ -172,13 +248,8 @@ __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16
     const int row = d0 + rf * 16 + i16;
     mrow[rf] = M + (int64_t)(row < D ? row : 0) * np + 8 * g4;
   }
-  const T16* vcol = W16 + wo + (int64_t)(cf0 * 16 + i16) * np + 8 * g4;
   f4 acc[kRF16][kColGroup];
-#pragma unroll
-  for (int rf = 0; rf < kRF16; ++rf)
-#pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = f4{0.f, 0.f, 0.f, 0.f};
-  nt16_mainloop<T16>(acc, mrow, vcol, np, ncf, np);
+  nt16_mainloop<T16>(acc, mrow, W16 + wo + (int64_t)(cf0 * 16) * np, np, ncf, np, lds);
   if (alpha == nullptr) {   // bare product: stores only
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
@@ -331,13 +402,13 @@ hipError_t launch_mixed_products(const Geometry& g16, const void* phi16, const v
                                  const int* act, int which, hipStream_t st) {
   if (which == 1) {
     if (nfwd == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_phi_v16<T16>), dim3((nfwd + 3) / 4), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_phi_v16<T16>), dim3(nfwd), dim3(256), 0, st,
                        (const T16*)phi16, g16.row_off, g16.w_off, fwd, nfwd, (const T16*)V16,
                        (T16*)W16, act, g16.D, g16.Rp);
     return hipGetLastError();
   }
   if (nadj == 0) return hipSuccess;
-  hipLaunchKernelGGL((k_phit_w16<T16>), dim3((nadj + 3) / 4), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_phit_w16<T16>), dim3(nadj), dim3(256), 0, st,
                      (const T16*)phiT16, g16.w_off, adj, nadj, (const T16*)W16, V, AV, alpha,
                      colc, beta, act, g16.D, g16.Rp);
   return hipGetLastError();
