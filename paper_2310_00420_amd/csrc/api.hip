@@ -201,6 +201,7 @@ struct cmtcs_handle_s {
     s.rr = rr; s.thr = thr; s.state = state; s.iters = iters;
     s.gam = gam; s.xi = xi; s.act = act;
     s.alpha = nullptr; s.colc = colc; s.beta = beta;
+    s.d16 = nullptr; s.d16_kind = 0;
     return s;
   }
 
@@ -344,7 +345,11 @@ struct cmtcs_handle_s {
   template <typename VT>
   cmtcs_status_t run_cg(const Geometry& g, const float* alpha, int steps, int fixed,
                         const RhsSource& src, int refine_every) {
-    const CgState s = cg_loop(alpha);
+    CgState s = cg_loop(alpha);
+    if (mixed()) {
+      s.d16 = D16;
+      s.d16_kind = phi_dtype == CMTCS_BF16 ? 1 : 2;
+    }
     const Geometry g16 = geom16(g.R, g.Rp);
     if (mixed()) HIP_TRY(round_direction(g), "launch(round16)");
     for (int u = 0; u < steps; ++u) {
@@ -383,7 +388,8 @@ struct cmtcs_handle_s {
         HIP_TRY(hipEventRecord(e4[3], st), "hipEventRecord");
         if (++ev_pending == kCheckEvery) HIP_TRY(harvest(), "profile events");
       }
-      if (mixed()) HIP_TRY(round_direction(g), "launch(round16)");
+      // the update wrote the 16-bit direction itself, except on replacement steps
+      if (replace) HIP_TRY(round_direction(g), "launch(round16)");
       if ((u + 1) % kCheckEvery == 0 && u + 1 < steps) {
         HIP_TRY(hipMemcpyAsync(act_host, act + (size_t)(u + 1) * T, sizeof(int) * T,
                                hipMemcpyDeviceToHost, st), "hipMemcpyAsync(active counts)");

@@ -205,6 +205,10 @@ struct CgState {
   const float* alpha;   // [C][D]
   const int* colc;      // [T*Rp] cluster of each column
   double beta;
+  // 16-bit copy of the direction for the mixed-precision products, written by the CG update
+  // beside d (same rounding as a separate conversion pass): 0 none, 1 bf16, 2 fp16
+  void* d16;
+  int d16_kind;
 };
 // Source of the right-hand sides for cg_init.
 struct RhsSource {

@@ -83,7 +83,8 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
                                                   int u, int steps, int fixed, int T, int R,
                                                   int Rp, int D, int split,
                                                   const float* __restrict__ alpha,
-                                                  const int* __restrict__ colc, double beta) {
+                                                  const int* __restrict__ colc, double beta,
+                                                  void* __restrict__ d16, int d16_kind) {
   __shared__ double sh[BS / 64];
   const int t = blockIdx.x / R, j = blockIdx.x % R;
   const int64_t idx = (int64_t)t * Rp + j;
@@ -150,8 +151,11 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
   for (int e = 0; e < EPT; ++e) {
     const int d = threadIdx.x + e * BS;
     if (d < D) {
+      const VT dn = rv[e] + xv_ * dv[e];
       Rv[base + d] = rv[e];
-      Dv[base + d] = rv[e] + xv_ * dv[e];
+      Dv[base + d] = dn;
+      if (d16_kind == 1) ((__bf16*)d16)[base + d] = (__bf16)(float)dn;
+      else if (d16_kind == 2) ((_Float16*)d16)[base + d] = (_Float16)(float)dn;
     }
   }
   if (threadIdx.x == 0) {
@@ -334,7 +338,7 @@ static hipError_t update_one(const Geometry& g, const CgState& s, int u, int ste
   hipLaunchKernelGGL((k_cg_update<VT, BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, (VT*)s.X,
                      (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state, s.iters,
                      s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split, s.alpha,
-                     s.colc, s.beta);
+                     s.colc, s.beta, s.d16, s.d16_kind);
   return hipGetLastError();
 }
 
