@@ -66,7 +66,8 @@ struct cmtcs_handle_s {
   // output rows per wave tile of the two products (autotuned per column count)
   int fwd_rows = 0, adj_rows = 0, cur_fwd_rows = -1, cur_adj_rows = -1, tuned_Rp = -1;
   bool autotune = true;
-  double *dg = nullptr, *of = nullptr, *zz = nullptr, *tau = nullptr, *rmin = nullptr,
+  void* slq_ws = nullptr;
+  double *tau = nullptr, *rmin = nullptr,
          *rmax = nullptr, *slog = nullptr;
   uint8_t* ok = nullptr;
   int* act_host = nullptr;   // pinned
@@ -464,7 +465,7 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key, o.probes, mu, sd, st),
             "launch(estep_finalize)");
     HIP_TRY(launch_sum_log_alpha(C, D, alpha, slog, st), "launch(sum_log_alpha)");
-    HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, dg, of, zz, tau, ok, rmin, rmax, st),
+    HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, st),
             "launch(slq)");
     HIP_TRY(launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, st),
             "launch(resp)");
@@ -646,10 +647,8 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->colc, sizeof(int) * T * (Rpm + (size_t)h->max_rhs));   // [T][Rp] + map staging
   A(&h->fwd_tiles, sizeof(int4) * fwd_max);
   A(&h->adj_tiles, sizeof(int4) * adj_max);
-  // SLQ tridiagonals [u][probe], u = 0..max_iters (the last row is the eigensolver's scratch)
-  A(&h->dg, sizeof(double) * (it + 1) * P);
-  A(&h->of, sizeof(double) * (it + 1) * P);
-  A(&h->zz, sizeof(double) * (it + 1) * P);
+  // SLQ tridiagonals of runs too long for LDS
+  A(&h->slq_ws, std::max<size_t>(16, slq_workspace_bytes((long)P, (int)it)));
   A(&h->tau, sizeof(double) * P);
   A(&h->rmin, sizeof(double) * P);
   A(&h->rmax, sizeof(double) * P);

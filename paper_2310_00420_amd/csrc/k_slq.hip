@@ -8,264 +8,297 @@
 // is  tau = ||p||^2 sum_u S_{u,1}^2 log lambda_u  (the paper's factor D equals ||p||^2 for
 // Rademacher probes), and Eq. (logdet-est) averages -tau over the probes.
 //
-// Only the eigenvalues and the first component of each unit eigenvector are needed (Gauss
-// quadrature weights), so the eigensolver is the implicit-shift symmetric QR iteration with
-// Wilkinson shifts (Golub & Van Loan, Matrix Computations, Sec. 8.3) that rotates one row
-// vector z = e_1^T Q instead of the whole eigenvector matrix: O(U^2) work per probe.
-// One thread per probe; its three length-U FP64 arrays live in a workspace laid out
-// [u][probe] so that the 64 lanes of a wave touch consecutive addresses.
+// The sum is e_1^T log(Gamma-bar) e_1.  It is computed here without an eigendecomposition, from
+// log x = int_0^inf [1/(1+t) - 1/(x+t)] dt (x > 0) applied to the spectrum:
+//     sum_u S_{u,1}^2 log lambda_u = int_0^inf [1/(1+t) - e_1^T (Gamma-bar + t I)^{-1} e_1] dt.
+// With t = e^s the integrand is analytic in the strip |Im s| < pi (its poles sit at
+// s = log lambda_u +- i pi and +- i pi) and decays like e^{-|s|} outside
+// [min(log lambda_min, 0), max(log lambda_max, 0)], so the trapezoidal rule with step h on that
+// interval widened by L on each side has error of order exp(-2 pi^2 / h) + e^{-L}: h = 0.45 and
+// L = 36 give about 1e-14 relative (against LAPACK's eigendecomposition, tridiagonals of
+// condition up to 1e8).  The resolvent entry is Q_1 / Q_0, Q_u being the determinant of the
+// trailing block (rows u..U-1) of Gamma-bar + t I, from the three-term recurrence
+// Q_u = (a_u + t) Q_{u+1} - b_u^2 Q_{u+2} run from the bottom without divisions and rescaled by
+// powers of two; the integrand is then t ((a_0 - 1) Q_1 - b_0^2 Q_2) / ((1 + t) Q_0), in which
+// the two O(1) terms that cancel for large t have already been subtracted exactly.
+//
+// lambda_min and lambda_max (the interval above, and outputs) come from Sturm counts: for
+// Gamma-bar - x I the number of negative pivots Q_u / Q_{u+1} equals the number of eigenvalues
+// below x (Sylvester's law of inertia applied to the U D U^T factorisation).  They are as
+// accurate as bisection, i.e. to about eps * ||Gamma-bar|| in absolute terms.
+//
+// Every quadrature node and every Sturm point is independent of the others, so one wave
+// handles one probe: its 64 lanes share the two searches (32 points per end and round) and then
+// the nodes, with the probe's U rows in LDS read by all lanes at once.  All loops have trip
+// counts fixed by U and the round count, whatever the data.
 #include <algorithm>
 #include <cmath>
-#include <type_traits>
+#include <cstdint>
 
 #include "internal.h"
 
 namespace cmtcs {
 
-// Reciprocal square root of r2 > 0 for the Givens rotations.  On the device: the hardware
-// estimate y0 refined by one third-order step, y = y0 (1 + e/2 + 3 e^2/8) with
-// e = 1 - r2 y0^2 (the series of (1 - e)^(-1/2)), which cubes the relative error of the
-// estimate; four dependent operations where two Newton steps take six, and the rotation's
-// dependent chain is what bounds this kernel.
-struct RsqDevice {
-  __device__ double operator()(double r2) const {
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double e = __builtin_fma(-r2, y0 * y0, 1.0);
-    const double p = __builtin_fma(0.375, e, 0.5);
-    return __builtin_fma(y0 * e, p, y0);
-  }
-};
-// The same on the host (for host builds of this routine, which the tests compile).
-struct RsqHost {
-  __host__ double operator()(double r2) const { return 1.0 / std::sqrt(r2); }
+// Row u of Gamma-bar: diagonal entry and squared off-diagonal to row u + 1 (0 for the last).
+struct alignas(16) TriRow {
+  double a, b2;
 };
 
-// Eigenvalues (left in dg) and first eigenvector components (left in zz, which must enter as
-// e_1) of the symmetric tridiagonal with diagonal dg[0..n-1] and off-diagonal of[0..n-2];
-// element i of each array is at index i * stride (index type I: int for on-chip arrays).
-// Each array must provide n + 1 entries: entry n (and of[n-1]) is scratch that a sweep may read
-// ahead or write and never uses.  Returns 0 on success, 1 if the sweep limit was reached.
-//
-// The routine runs one probe per thread, and a wave executes the union of its lanes' control
-// paths, so every branch is kept short: the bottom deflations run in their own small loop (so
-// that each round of the outer loop is one sweep for every lane that is not done), the scan for
-// the block start tests four off-diagonals per round, and the rotation loop has no branch.
-template <typename I, typename Rsq>
-__host__ __device__ inline int tridiag_eig_first_row(double* dg, double* of, double* zz, int n,
-                                                     I stride, int max_sweeps, Rsq rsq) {
-  const double eps = 2.220446049250313e-16;
-  // off-diagonal j is negligible against its two diagonal neighbours
-  auto small = [&](int j) __attribute__((always_inline)) {
-    return fabs(of[(I)j * stride]) <=
-           eps * (fabs(dg[(I)j * stride]) + fabs(dg[(I)(j + 1) * stride]));
+// Multiplies x and y by the power of two that brings the larger magnitude into [0.5, 1).
+struct ScaleDevice {
+  __device__ void operator()(double& x, double& y) const {
+    const int e = __builtin_amdgcn_frexp_exp(fmax(fabs(x), fabs(y)));
+    x = __builtin_amdgcn_ldexp(x, -e);
+    y = __builtin_amdgcn_ldexp(y, -e);
+  }
+};
+// The same on the host (for host builds of these routines, which the tests compile).
+struct ScaleHost {
+  __host__ void operator()(double& x, double& y) const {
+    int e = 0;
+    (void)std::frexp(std::fmax(std::fabs(x), std::fabs(y)), &e);
+    x = std::ldexp(x, -e);
+    y = std::ldexp(y, -e);
+  }
+};
+
+constexpr double kQuadStep = 0.45;    // h
+constexpr double kQuadTail = 36.0;    // L
+constexpr int kSecPoints = 32;        // Sturm points per end and round
+constexpr int kSecRounds = 11;        // (kSecPoints + 1)^11 = 5e16: the bracket reaches rounding
+
+// Q_1 and Q_2 of Gamma-bar + t I (rows r[0..n-1], n >= 1, at one common power-of-two scale)
+// by the recurrence from the bottom; with kCount, also the number of negative pivots
+// Q_u / Q_{u+1} for u = n-1..1 (a zero pivot is replaced by a tiny negative one, as in
+// bisection codes, so that the next pivot stays finite).  Rescaled after every fourth row: a
+// row changes the magnitude of the pair by a factor between its off-diagonal squared and
+// |a + t| + b^2, well within the exponent range for four rows.
+template <bool kCount, typename Rows, typename Scale>
+__host__ __device__ inline int trailing_det(const Rows& r, int n, double t, double& q1, double& q2,
+                                            Scale sc) {
+  double x1 = 1.0, x2 = 0.0;   // Q_{u+1}, Q_{u+2}
+  int neg = 0;
+  auto row = [&](const TriRow w) __attribute__((always_inline)) {
+    double q = std::fma(w.a + t, x1, -(w.b2 * x2));
+    if (kCount) {
+      if (q == 0.0) q = -0x1p-80 * x1;
+      neg += (q < 0.0) != (x1 < 0.0);
+    }
+    x2 = x1;
+    x1 = q;
   };
-  int hi = n - 1;
-  int sweeps = 0;
-  while (true) {
-    while (hi > 0 && small(hi - 1)) {
-      of[(I)(hi - 1) * stride] = 0.0;
-      --hi;
-    }
-    if (hi <= 0) break;
-    // start of the unreduced block that ends at hi
-    int lo = hi - 1;
-    while (lo >= 4) {
-      const bool s1 = small(lo - 1), s2 = small(lo - 2), s3 = small(lo - 3), s4 = small(lo - 4);
-      if (s1 || s2 || s3 || s4) break;
-      lo -= 4;
-    }
-    while (lo > 0 && !small(lo - 1)) --lo;
-    if (lo > 0) of[(I)(lo - 1) * stride] = 0.0;
-    if (++sweeps > max_sweeps) return 1;
-    // Wilkinson shift: the eigenvalue of the trailing 2x2 block nearer its last diagonal entry
-    const double a = dg[(I)(hi - 1) * stride], bq = of[(I)(hi - 1) * stride];
-    const double cq = dg[(I)hi * stride];
-    const double delta = 0.5 * (a - cq);
-    const double den = delta + copysign(hypot(delta, bq), delta);
-    const double mu = cq - bq * bq / den;
-    // Bulge chase: rotations in planes (k, k+1), k = lo..hi-1.  Rotation k writes positions
-    // k-1 and k only, so the untouched entries at k+2 that the next rotation needs are loaded
-    // one rotation ahead (up to position hi+1 <= n, the scratch entry at the end); the
-    // off-diagonal read past the block end only feeds values the last rotation discards.  The
-    // first rotation is peeled: it has no finished off-diagonal to store.
-    double a0 = dg[(I)lo * stride], b0 = of[(I)lo * stride], z0 = zz[(I)lo * stride];
-    double a1 = dg[(I)(lo + 1) * stride], z1 = zz[(I)(lo + 1) * stride];
-    double b1 = of[(I)(lo + 1) * stride];
-    double x = a0 - mu;
-    double y = b0;
-    auto rotate = [&](int k, auto first) __attribute__((always_inline)) {
-      const double a2 = dg[(I)(k + 2) * stride], z2 = zz[(I)(k + 2) * stride];
-      const double b2 = of[(I)(k + 2) * stride];
-      // Givens rotation (cs, sn) = (x, y) / r zeroing y against x.  The entries are
-      // eigenvalue-sized (CG step sizes of a positive definite system), far from FP64
-      // overflow, so r needs no scaling.  The next x, the new off-diagonal
-      //   nb = cs sn (a1 - a0) + (cs^2 - sn^2) b0 = [x y (a1 - a0) + (x - y)(x + y) b0] / r^2,
-      // takes its bracket from values known before the rotation, so that the chain from one
-      // rotation's x to the next runs through r^2, one reciprocal square root and two
-      // products only.  r2 = 0 (x = y = 0) keeps the identity rotation.
-      const double r2 = x * x + y * y;
-      const double num = (x * y) * (a1 - a0) + ((x - y) * (x + y)) * b0;
-      const double inv = rsq(fmax(r2, 1e-300));
-      const double cs = r2 > 0.0 ? x * inv : 1.0;
-      const double sn = y * inv;   // y = 0 when r2 = 0
-      if constexpr (!decltype(first)::value) of[(I)(k - 1) * stride] = r2 * inv;
-      const double nb = (num * inv) * inv;
-      const double na0 = cs * cs * a0 + 2.0 * cs * sn * b0 + sn * sn * a1;
-      const double na1 = sn * sn * a0 - 2.0 * cs * sn * b0 + cs * cs * a1;
-      dg[(I)k * stride] = na0;
-      of[(I)k * stride] = nb;
-      zz[(I)k * stride] = cs * z0 + sn * z1;
-      z0 = -sn * z0 + cs * z1;
-      a0 = na1;
-      y = (y * inv) * b1;   // bulge at (k+2, k): sn b1
-      b0 = cs * b1;         // off-diagonal (k+1, k+2) after this rotation
-      x = nb;
-      a1 = a2; z1 = z2; b1 = b2;
-    };
-    rotate(lo, std::true_type{});
-    for (int k = lo + 1; k < hi; ++k) rotate(k, std::false_type{});
-    dg[(I)hi * stride] = a0;
-    zz[(I)hi * stride] = z0;
+  int u = n - 1;
+  for (; u >= 4; u -= 4) {
+    const TriRow w0 = r[u], w1 = r[u - 1], w2 = r[u - 2], w3 = r[u - 3];   // loads together
+    row(w0);
+    row(w1);
+    row(w2);
+    row(w3);
+    sc(x1, x2);
   }
-  return 0;
+  for (; u >= 1; --u) row(r[u]);
+  q1 = x1;
+  q2 = x2;
+  return neg;
 }
 
-__global__ __launch_bounds__(64) void k_slq(const double* __restrict__ gam,
-                                            const double* __restrict__ xi,
-                                            const int* __restrict__ iters, int T, int C, int K,
-                                            int Rp, double pnorm2, double* __restrict__ dg,
-                                            double* __restrict__ of, double* __restrict__ zz,
-                                            double* __restrict__ tau, uint8_t* __restrict__ ok,
-                                            double* __restrict__ rmin,
-                                            double* __restrict__ rmax) {
-  const long P = (long)T * C * K;
-  const long p = (long)blockIdx.x * 64 + threadIdx.x;
-  if (p >= P) return;
-  const int t = (int)(p / ((long)C * K));
-  const int c = (int)((p / K) % C);
-  const int k = (int)(p % K);
-  const long idx = (long)t * Rp + (long)c * (K + 1) + 1 + k;
-  const long ncol = (long)T * Rp;
-  const int n = iters[idx];
-  if (n == 0) {
-    tau[p] = 0.0; ok[p] = 0; rmin[p] = NAN; rmax[p] = NAN;
-    return;
-  }
-  double gprev = 1.0, xprev = 0.0;
-  for (int u = 0; u < n; ++u) {
-    const double g = gam[(long)u * ncol + idx];
-    dg[(long)u * P + p] = 1.0 / g + (u > 0 ? xprev / gprev : 0.0);
-    if (u + 1 < n) {
-      const double x = xi[(long)u * ncol + idx];
-      of[(long)u * P + p] = sqrt(x) / g;
-      xprev = x;
-    }
-    zz[(long)u * P + p] = (u == 0) ? 1.0 : 0.0;
-    gprev = g;
-  }
-  const int fail = tridiag_eig_first_row<long>(dg + p, of + p, zz + p, n, P, 30 * n,
-                                               RsqDevice());
-  double acc = 0.0, lo = INFINITY, hi = -INFINITY;
-  bool pos = true;
-  for (int u = 0; u < n; ++u) {
-    const double lam = dg[(long)u * P + p];
-    const double z = zz[(long)u * P + p];
-    lo = fmin(lo, lam);
-    hi = fmax(hi, lam);
-    if (!(lam > 0.0)) pos = false;
-    else acc += z * z * log(lam);
-  }
-  tau[p] = pnorm2 * acc;
-  ok[p] = (pos && !fail) ? 1 : 0;
-  rmin[p] = lo;
-  rmax[p] = hi;
+// Number of eigenvalues of Gamma-bar below x (negative pivots of Gamma-bar - x I).
+template <typename Rows, typename Scale>
+__host__ __device__ inline int sturm_count(const Rows& r, int n, double x, Scale sc) {
+  double q1, q2;
+  int neg = trailing_det<true>(r, n, -x, q1, q2, sc);
+  double q0 = std::fma(r[0].a - x, q1, -(r[0].b2 * q2));
+  if (q0 == 0.0) q0 = -0x1p-80 * q1;
+  return neg + ((q0 < 0.0) != (q1 < 0.0));
 }
 
-// The same computation with each probe's three arrays in LDS: PB probes per block (one
-// thread each), arrays laid out [u][probe] in dynamic shared memory of 3 * PB * (Um + 1)
-// doubles.
-// Keeping the O(U) working set of a probe on chip removes the global-memory round trips of
-// the QR sweeps, which otherwise dominate this kernel.
-__global__ __launch_bounds__(64) void k_slq_lds(const double* __restrict__ gam,
-                                                const double* __restrict__ xi,
-                                                const int* __restrict__ iters, int T, int C,
-                                                int K, int Rp, double pnorm2,
-                                                double* __restrict__ tau,
-                                                uint8_t* __restrict__ ok,
-                                                double* __restrict__ rmin,
-                                                double* __restrict__ rmax, int PB, int Um) {
-  extern __shared__ double sm[];
-  const int lp = threadIdx.x;
-  if (lp >= PB) return;
+// Integrand at s (t = e^s): t [1/(1+t) - e_1^T (Gamma-bar + t I)^{-1} e_1].
+template <typename Rows, typename Scale>
+__host__ __device__ inline double quad_node(const Rows& r, int n, double s, Scale sc) {
+  const double t = std::exp(s);
+  double q1, q2;
+  (void)trailing_det<false>(r, n, t, q1, q2, sc);
+  const TriRow w = r[0];
+  const double q0 = std::fma(w.a + t, q1, -(w.b2 * q2));
+  return t * std::fma(w.a - 1.0, q1, -(w.b2 * q2)) / ((1.0 + t) * q0);
+}
+
+// Nodes s_j = s0 + j h, j < nodes, covering [min(log lo, 0) - L, max(log hi, 0) + L] for a
+// spectrum inside [lo, hi], lo > 0.
+__host__ __device__ inline void quad_range(double lo, double hi, double& s0, int& nodes) {
+  s0 = std::fmin(std::log(lo), 0.0) - kQuadTail;
+  const double s1 = std::fmax(std::log(hi), 0.0) + kQuadTail;
+  nodes = (int)std::ceil((s1 - s0) / kQuadStep) + 1;
+}
+
+// Point k (1..kSecPoints) of a bracket split into kSecPoints + 1 parts, and the bracket after a
+// round given the points that reached the count sought (bit k-1 of hit): from the last point
+// below the first hit to the first hit (the ends of the old bracket where there is none).
+__host__ __device__ inline double sec_point(double lo, double hi, int k) {
+  return lo + (hi - lo) * (double)k * (1.0 / (kSecPoints + 1));
+}
+__host__ __device__ inline void sec_update(double& lo, double& hi, uint32_t hit) {
+  const int k = hit ? __builtin_ctz(hit) + 1 : kSecPoints + 1;
+  const double nlo = k > 1 ? sec_point(lo, hi, k - 1) : lo;
+  const double nhi = k <= kSecPoints ? sec_point(lo, hi, k) : hi;
+  lo = nlo;
+  hi = nhi;
+}
+
+// Starting bracket for both ends: the Gershgorin interval, widened by a margin well above the
+// rounding of the Sturm counts.
+__host__ __device__ inline void sec_start(double& glo, double& ghi) {
+  const double m = std::ldexp(std::fmax(std::fabs(glo), std::fabs(ghi)), -40) + 1e-300;
+  glo -= m;
+  ghi += m;
+}
+
+template <typename VT>
+__device__ inline VT wave_sum(VT v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// One wave per probe, W = blockDim.x / 64 probes per block.  kLds: the rows live in dynamic LDS
+// (Um rows per wave); otherwise in the workspace rows_ws, Um rows per probe.
+template <bool kLds>
+__global__ __launch_bounds__(256) void k_slq(const double* __restrict__ gam,
+                                             const double* __restrict__ xi,
+                                             const int* __restrict__ iters, int T, int C,
+                                             int K, int Rp, double pnorm2, int Um,
+                                             TriRow* __restrict__ rows_ws,
+                                             double* __restrict__ tau,
+                                             uint8_t* __restrict__ ok,
+                                             double* __restrict__ rmin,
+                                             double* __restrict__ rmax) {
+  extern __shared__ TriRow sm_rows[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long P = (long)T * C * K;
-  const long p = (long)blockIdx.x * PB + lp;
-  if (p >= P) return;
-  const int t = (int)(p / ((long)C * K));
-  const int c = (int)((p / K) % C);
-  const int k = (int)(p % K);
-  const long idx = (long)t * Rp + (long)c * (K + 1) + 1 + k;
-  const long ncol = (long)T * Rp;
-  const int n = iters[idx];
-  if (n == 0) {
-    tau[p] = 0.0; ok[p] = 0; rmin[p] = NAN; rmax[p] = NAN;
-    return;
+  const long p = (long)blockIdx.x * (blockDim.x >> 6) + wv;
+  long idx = 0;
+  int n = 0;
+  if (p < P) {
+    const int t = (int)(p / ((long)C * K));
+    const int c = (int)((p / K) % C);
+    const int k = (int)(p % K);
+    idx = (long)t * Rp + (long)c * (K + 1) + 1 + k;
+    n = iters[idx];
   }
-  // Um + 1 positions per array: the eigensolver's scratch entry follows the last step
-  double* dg = sm + lp;
-  double* of = sm + (long)PB * (Um + 1) + lp;
-  double* zz = sm + 2L * PB * (Um + 1) + lp;
-  double gprev = 1.0, xprev = 0.0;
-  for (int u = 0; u < n; ++u) {
+  n = __builtin_amdgcn_readfirstlane(n);
+  TriRow* r = kLds ? sm_rows + (long)wv * Um : rows_ws + (p < P ? p : 0) * (long)Um;
+  const long ncol = (long)T * Rp;
+  // rows of Gamma-bar (Eq. (tridiag)) and the Gershgorin interval
+  double glo = INFINITY, ghi = -INFINITY;
+  bool finite = true;
+  for (int u = lane; u < n; u += 64) {
     const double g = gam[(long)u * ncol + idx];
-    dg[(long)u * PB] = 1.0 / g + (u > 0 ? xprev / gprev : 0.0);
+    double a = 1.0 / g, bu = 0.0, bl = 0.0;
+    if (u > 0) {
+      const double gp = gam[(long)(u - 1) * ncol + idx];
+      const double xp = xi[(long)(u - 1) * ncol + idx];
+      a += xp / gp;
+      bl = sqrt(xp) / gp;
+    }
+    TriRow w{a, 0.0};
     if (u + 1 < n) {
       const double x = xi[(long)u * ncol + idx];
-      of[(long)u * PB] = sqrt(x) / g;
-      xprev = x;
+      w.b2 = x / (g * g);
+      bu = sqrt(x) / g;
     }
-    zz[(long)u * PB] = (u == 0) ? 1.0 : 0.0;
-    gprev = g;
+    r[u] = w;
+    glo = fmin(glo, a - bl - bu);
+    ghi = fmax(ghi, a + bl + bu);
+    finite = finite && isfinite(a) && isfinite(w.b2);
   }
-  const int fail = tridiag_eig_first_row<int>(dg, of, zz, n, PB, 30 * n, RsqDevice());
-  double acc = 0.0, lo = INFINITY, hi = -INFINITY;
-  bool pos = true;
-  for (int u = 0; u < n; ++u) {
-    const double lam = dg[(long)u * PB];
-    const double z = zz[(long)u * PB];
-    lo = fmin(lo, lam);
-    hi = fmax(hi, lam);
-    if (!(lam > 0.0)) pos = false;
-    else acc += z * z * log(lam);
+  // the rows are read by every lane of the wave: a block barrier for LDS, a device-scope fence
+  // (stores completed, caches made coherent) for the workspace
+  if (kLds) __syncthreads();
+  else __threadfence();
+  if (n == 0) {
+    if (p < P && lane == 0) { tau[p] = 0.0; ok[p] = 0; rmin[p] = NAN; rmax[p] = NAN; }
+    return;
   }
-  tau[p] = pnorm2 * acc;
-  ok[p] = (pos && !fail) ? 1 : 0;
-  rmin[p] = lo;
-  rmax[p] = hi;
+  glo = wave_min(glo);
+  ghi = wave_max(ghi);
+  const bool all_finite = __all(finite);
+  if (!all_finite) {
+    if (lane == 0) { tau[p] = 0.0; ok[p] = 0; rmin[p] = NAN; rmax[p] = NAN; }
+    return;
+  }
+  sec_start(glo, ghi);
+  // multisection: lanes 0..31 search lambda_min (first point with a count >= 1), lanes 32..63
+  // lambda_max (first point with a count >= n)
+  const int end = lane >> 5, kp = (lane & 31) + 1;
+  const int want = end ? n : 1;
+  double lo = glo, hi = ghi;
+  for (int it = 0; it < kSecRounds; ++it) {
+    const int cnt = sturm_count(r, n, sec_point(lo, hi, kp), ScaleDevice());
+    const uint64_t hit = __ballot(cnt >= want);
+    sec_update(lo, hi, end ? (uint32_t)(hit >> 32) : (uint32_t)hit);
+  }
+  const double lmin_lo = __shfl(lo, 0, 64), lmin_hi = __shfl(hi, 0, 64);
+  const double lmax_lo = __shfl(lo, 32, 64), lmax_hi = __shfl(hi, 32, 64);
+  // positive definite: no eigenvalue at or below the lower end of lambda_min's bracket
+  const bool pd = lmin_lo > 0.0;
+  double acc = 0.0;
+  if (pd) {
+    double s0;
+    int nodes;
+    quad_range(lmin_lo, lmax_hi, s0, nodes);
+    for (int j0 = 0; j0 < nodes; j0 += 64) {
+      const int j = j0 + lane;
+      const double f = quad_node(r, n, s0 + (double)(j < nodes ? j : 0) * kQuadStep,
+                                 ScaleDevice());
+      acc += j < nodes ? f : 0.0;
+    }
+    acc = wave_sum(acc) * kQuadStep;
+  }
+  if (lane == 0) {
+    tau[p] = pd ? pnorm2 * acc : 0.0;
+    ok[p] = pd ? 1 : 0;
+    rmin[p] = 0.5 * (lmin_lo + lmin_hi);
+    rmax[p] = 0.5 * (lmax_lo + lmax_hi);
+  }
+}
+
+// Four probes (waves) per block while their rows fit in 64 KB of LDS, fewer for long runs,
+// and the workspace beyond one wave's worth.
+constexpr long kSlqLdsBytes = 64 * 1024;
+static long slq_waves(long Um) {
+  return std::min<long>(4, kSlqLdsBytes / (long)(sizeof(TriRow) * Um));
+}
+
+size_t slq_workspace_bytes(long P, int steps) {
+  const long Um = steps > 0 ? steps : 1;
+  return slq_waves(Um) >= 1 ? 0 : sizeof(TriRow) * (size_t)P * (size_t)Um;
 }
 
 hipError_t launch_slq(const Geometry& g, const CgState& s, int K, int steps, double pnorm2,
-                      double* dg, double* of, double* zz, double* tau, uint8_t* ok, double* rmin,
-                      double* rmax, hipStream_t st) {
+                      void* rows_ws, double* tau, uint8_t* ok, double* rmin, double* rmax,
+                      hipStream_t st) {
   const long P = (long)g.T * g.C * K;
   if (P == 0) return hipSuccess;
-  // A wave pays for every instruction whatever number of its lanes hold a probe, and one wave
-  // per SIMD leaves the long dependent chains of its rotations exposed.  27 KB of LDS per
-  // one-wave block balances the two: at 200 steps, 5 probes per wave and six blocks per CU
-  // (measured at 8192 probes: 22 ms, against 25 ms at 20 KB, 29 ms at 40 KB and 36 ms at 10 KB).
-  // With many probes (more than fit on chip in one round), one probe per lane in full waves
-  // with the global-memory layout needs fewer rounds and wins.
-  constexpr long kLdsBytes = 27 * 1024;
-  constexpr long kLdsMaxProbes = 16384;
   const long Um = steps > 0 ? steps : 1;
-  const long PB = std::min<long>(64, kLdsBytes / (24 * (Um + 1)));
-  if (PB >= 1 && P <= kLdsMaxProbes) {
-    hipLaunchKernelGGL(k_slq_lds, dim3((unsigned)((P + PB - 1) / PB)), dim3(64),
-                       (size_t)(24 * PB * (Um + 1)), st, s.gam, s.xi, s.iters, g.T, g.C, K, g.Rp,
-                       pnorm2, tau, ok, rmin, rmax, (int)PB, (int)Um);
+  const long W = slq_waves(Um);
+  if (W >= 1) {
+    hipLaunchKernelGGL(k_slq<true>, dim3((unsigned)((P + W - 1) / W)), dim3((unsigned)(64 * W)),
+                       (size_t)(sizeof(TriRow) * W * Um), st, s.gam, s.xi, s.iters, g.T, g.C, K,
+                       g.Rp, pnorm2, (int)Um, (TriRow*)rows_ws, tau, ok, rmin, rmax);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_slq, dim3((unsigned)((P + 63) / 64)), dim3(64), 0, st, s.gam, s.xi,
-                     s.iters, g.T, g.C, K, g.Rp, pnorm2, dg, of, zz, tau, ok, rmin, rmax);
+  hipLaunchKernelGGL(k_slq<false>, dim3((unsigned)P), dim3(64), 0, st, s.gam, s.xi, s.iters, g.T,
+                     g.C, K, g.Rp, pnorm2, (int)Um, (TriRow*)rows_ws, tau, ok, rmin, rmax);
   return hipGetLastError();
 }
 

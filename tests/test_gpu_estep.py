@@ -17,9 +17,10 @@ inside the Krylov space the self-spread is far below 1e-5 and the fixed bar is w
 import numpy as np
 import pytest
 import torch
+from scipy.linalg import eigvalsh_tridiagonal
 
 import synth
-from oracle import cofem, cg as ocg, probes as oprobes
+from oracle import cofem, cg as ocg, probes as oprobes, slq
 from gpu_common import (DEV, device_model, alpha_dev, log_pi_dev, compare_estep, estep_errors,
                         rel_cols)
 
@@ -102,15 +103,35 @@ def test_estep_tiny_f64():
     assert err["iters_maxdiff"] == 0           # fixed mode: every column takes 64 steps
 
 
+def _ritz_errors(g, ref, tasks, K):
+    """Largest relative difference of the device's extreme Ritz values (stats ritz_min/ritz_max)
+    from the eigenvalues of the oracle's tridiagonal of Eq. (tridiag) for the same probe."""
+    rmin, rmax = g["ritz_min"].cpu().numpy(), g["ritz_max"].cpu().numpy()
+    worst = 0.0
+    for a, t in enumerate(tasks):
+        for c in range(rmin.shape[1]):
+            for k in range(K):
+                j = c * (K + 1) + 1 + k
+                d, e = slq.tridiagonal(ref["gammas"][a][j], ref["xis"][a][j])
+                lam = eigvalsh_tridiagonal(d, e) if len(d) > 1 else d
+                worst = max(worst, abs(rmin[t, c, k] - lam.min()) / lam.max(),
+                            abs(rmax[t, c, k] - lam.max()) / lam.max())
+    return worst
+
+
 def test_estep_tiny_converged_f64():
     """Tiny problem with CG run to convergence (tol 1e-13, at most 10 D steps): the solution is
-    unique up to rounding, so the fixed bar applies (the oracle's self-spread here is ~1e-11)."""
+    unique up to rounding, so the fixed bar applies (the oracle's self-spread here is ~1e-11).
+    The extreme Ritz values of every probe's tridiagonal match the oracle's eigenvalues."""
     w = synth.make(synth.Config("tiny-conv", T=4, C=2, D=64, N=32, sparsity=6, groups=2, K=16,
                                 tol=1e-13, max_iters=640))
     err, g, ref, sp = _run(w, range(w.T))
     _assert(err, sp)
     assert max(float(np.max(v)) for v in sp.values()) < 1e-8   # converged: unique up to rounding
     assert (g["status"].cpu().numpy() == 0).all()
+    ritz = _ritz_errors(g, ref, range(w.T), w.cfg.K)
+    print("ritz values vs oracle eigenvalues: %.2e" % ritz)
+    assert ritz < 1e-6
 
 
 def test_estep_fp32_config_f64_sampled_tasks():
