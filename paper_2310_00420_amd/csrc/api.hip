@@ -202,7 +202,7 @@ struct cmtcs_handle_s {
     s.rr = rr; s.thr = thr; s.state = state; s.iters = iters;
     s.gam = gam; s.xi = xi; s.act = act;
     s.alpha = nullptr; s.colc = colc; s.beta = beta;
-    s.d16 = nullptr; s.d16_kind = 0;
+    s.d16 = nullptr; s.d16_kind = 0; s.d16_ld = 0;
     return s;
   }
 
@@ -243,7 +243,7 @@ struct cmtcs_handle_s {
       std::vector<int4> f16, a16;
       for (int t = 0; t < T; ++t) {
         const int np = (int)((row_off[t + 1] - row_off[t] + 31) / 32 * 32);
-        w16[t + 1] = w16[t] + (int64_t)Rp * np;
+        w16[t + 1] = w16[t] + (int64_t)Rp * ld16(np);
         for (int n0 = 0; n0 < np; n0 += 4 * kRows16)   // one tile per block of four waves
           for (int cg = 0; cg < ng; ++cg) f16.push_back(make_int4(t, n0, cg, 0));
         for (int d0 = 0; d0 < D; d0 += 4 * kRows16)
@@ -338,9 +338,10 @@ struct cmtcs_handle_s {
   }
 
   hipError_t round_direction(const Geometry& g) {
-    const int64_t n = (int64_t)T * g.Rp * D;
-    if (phi_dtype == CMTCS_BF16) return launch_round16<__bf16>((const float*)Dv, D16, n, st);
-    return launch_round16<_Float16>((const float*)Dv, D16, n, st);
+    const int64_t rows = (int64_t)T * g.Rp;
+    if (phi_dtype == CMTCS_BF16)
+      return launch_round16<__bf16>((const float*)Dv, D, D16, ld16(D), rows, D, st);
+    return launch_round16<_Float16>((const float*)Dv, D, D16, ld16(D), rows, D, st);
   }
 
   template <typename VT>
@@ -350,6 +351,7 @@ struct cmtcs_handle_s {
     if (mixed()) {
       s.d16 = D16;
       s.d16_kind = phi_dtype == CMTCS_BF16 ? 1 : 2;
+      s.d16_ld = ld16(D);
     }
     const Geometry g16 = geom16(g.R, g.Rp);
     if (mixed()) HIP_TRY(round_direction(g), "launch(round16)");
@@ -658,13 +660,13 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
     size_t np32_sum = 0, f16_max = 0;
     for (size_t t = 0; t < T; ++t) {
       const size_t np = (size_t)((h->row_off[t + 1] - h->row_off[t] + 31) / 32 * 32);
-      np32_sum += np;
+      np32_sum += (size_t)ld16((int64_t)np);
       h->max_np32 = std::max(h->max_np32, (int)np);
       f16_max += (np + kRows16 - 1) / kRows16 * ngm;
     }
-    A(&h->phi16, 2 * D * (size_t)rows);
+    A(&h->phi16, 2 * (size_t)ld16(D) * (size_t)rows);
     A(&h->phiT16, 2 * D * np32_sum);
-    A(&h->D16, 2 * T * Rpm * D);
+    A(&h->D16, 2 * T * Rpm * (size_t)ld16(D));
     A(&h->W16, 2 * Rpm * np32_sum);
     A(&h->w16_off_d, sizeof(int64_t) * (T + 1));
     A(&h->fwd16_tiles, sizeof(int4) * f16_max);
@@ -696,13 +698,13 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
       return rs;
     }
     const Geometry g16 = h->geom16(1, h->Rp_max);
-    const int64_t n = (int64_t)rows * h->D;
+    const int64_t lp = ld16(h->D);
     if (h->phi_dtype == CMTCS_BF16) {
-      e = launch_round16<__bf16>(h->phi, h->phi16, n, h->st);
+      e = launch_round16<__bf16>((const float*)h->phi, h->D, h->phi16, lp, rows, h->D, h->st);
       if (e == hipSuccess)
         e = launch_transpose16<__bf16>(g16, h->phi16, h->phiT16, h->max_np32, h->st);
     } else {
-      e = launch_round16<_Float16>(h->phi, h->phi16, n, h->st);
+      e = launch_round16<_Float16>((const float*)h->phi, h->D, h->phi16, lp, rows, h->D, h->st);
       if (e == hipSuccess)
         e = launch_transpose16<_Float16>(g16, h->phi16, h->phiT16, h->max_np32, h->st);
     }

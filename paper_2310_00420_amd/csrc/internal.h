@@ -209,6 +209,7 @@ struct CgState {
   // beside d (same rounding as a separate conversion pass): 0 none, 1 bf16, 2 fp16
   void* d16;
   int d16_kind;
+  int64_t d16_ld;   // pitch of d16's columns (elements)
 };
 // Source of the right-hand sides for cg_init.
 struct RhsSource {
@@ -269,13 +270,20 @@ hipError_t launch_mixed_products(const Geometry& g16, const void* phi16, const v
 template <typename T16>
 hipError_t launch_transpose16(const Geometry& g16, const void* phi16, void* phiT16, int max_np,
                               hipStream_t st);
+// y[r][c] = round16(x[r][c]) for rows x cols, row pitches ldx and ldy (elements).
 template <typename T16>
-hipError_t launch_round16(const float* x, void* y, int64_t n, hipStream_t st);
+hipError_t launch_round16(const float* x, int64_t ldx, void* y, int64_t ldy, int64_t rows,
+                          int cols, hipStream_t st);
 // Second half of a residual-replacement step u: r = src - A x (A x in AX), then r.r, xi,
 // d = r + xi d and the stop decision of the step, as in the unsplit update.
 hipError_t launch_replace(const Geometry& g, const CgState& s, const float* AX,
                           const RhsSource& src, int u, int steps, int fixed, hipStream_t st);
 constexpr int kRows16 = 64;   // output rows per wave tile of the 16-bit products
+// Row pitch (elements) of the 16-bit arrays of the mixed path for rows of n elements: 128 bytes
+// past a multiple of 256.  Many waves read their rows in step, so rows that all start on the
+// same power-of-two boundary put the reads of a step on the same few memory channels (measured:
+// 4.3 TB/s for 64-row tiles at an 8 KB pitch, 6.1 TB/s at 8 KB + 128 B, like a linear stream).
+__host__ __device__ constexpr int64_t ld16(int64_t n) { return (n + 127) / 128 * 128 + 64; }
 
 // Launchers (k_em.hip).
 template <typename VT>

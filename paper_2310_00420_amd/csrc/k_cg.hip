@@ -84,7 +84,8 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
                                                   int Rp, int D, int split,
                                                   const float* __restrict__ alpha,
                                                   const int* __restrict__ colc, double beta,
-                                                  void* __restrict__ d16, int d16_kind) {
+                                                  void* __restrict__ d16, int d16_kind,
+                                                  int64_t d16_ld) {
   __shared__ double sh[BS / 64];
   const int t = blockIdx.x / R, j = blockIdx.x % R;
   const int64_t idx = (int64_t)t * Rp + j;
@@ -154,8 +155,8 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
       const VT dn = rv[e] + xv_ * dv[e];
       Rv[base + d] = rv[e];
       Dv[base + d] = dn;
-      if (d16_kind == 1) ((__bf16*)d16)[base + d] = (__bf16)(float)dn;
-      else if (d16_kind == 2) ((_Float16*)d16)[base + d] = (_Float16)(float)dn;
+      if (d16_kind == 1) ((__bf16*)d16)[idx * d16_ld + d] = (__bf16)(float)dn;
+      else if (d16_kind == 2) ((_Float16*)d16)[idx * d16_ld + d] = (_Float16)(float)dn;
     }
   }
   if (threadIdx.x == 0) {
@@ -338,7 +339,7 @@ static hipError_t update_one(const Geometry& g, const CgState& s, int u, int ste
   hipLaunchKernelGGL((k_cg_update<VT, BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, (VT*)s.X,
                      (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state, s.iters,
                      s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split, s.alpha,
-                     s.colc, s.beta, s.d16, s.d16_kind);
+                     s.colc, s.beta, s.d16, s.d16_kind, s.d16_ld);
   return hipGetLastError();
 }
 

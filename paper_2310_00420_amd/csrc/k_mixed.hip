@@ -5,12 +5,14 @@
 //
 // Both products are laid out so that the contraction index is contiguous in memory for both
 // operands (one 16-byte load gives a lane its 8 consecutive k values):
-//   fwd:  W16_t = round16(Phi16_t V16_t)       M = Phi16_t   [N_t][D]   (caller layout), K = D
+//   fwd:  W16_t = round16(Phi16_t V16_t)       M = Phi16_t   [N_t][D]   (caller's rows), K = D
 //   adj:  AV_t  = beta PhiT16_t W16_t + alpha (.) V_t
 //                                              M = PhiT16_t  [D][np_t] (built once at create,
 //                                              a transposed copy: HBM is plentiful, and the
 //                                              16-bit path is bound by streaming Phi)
-// np_t = N_t rounded up to 32; W16_t is [Rp][np_t] with zero rows beyond N_t.
+// np_t = N_t rounded up to 32; W16_t is [Rp][np_t] with zero rows beyond N_t.  Every 16-bit
+// array has the padded row pitch ld16 (Phi16 and the direction ld16(D), PhiT16 and W16
+// ld16(np_t)); the padding is never read.
 // The true residual b - A x that replaces the recursive residual every m steps is computed by
 // the FP32 kernels of k_operator.hip from the FP32 copy of Phi.
 #include <type_traits>
@@ -61,6 +63,7 @@ constexpr int kRF16 = kRows16 / 16;   // 64 output rows per wave tile
 // the FP64/FP32 products, every load is unconditional, and the first round is peeled so that
 // the accumulators start in the matrix-core result registers.
 constexpr int kRing16 = 4;
+constexpr int kStg16 = 2;   // staged chunks in flight in registers (divides kRing16)
 constexpr int kLd16 = 40;                                      // padded LDS row (elements)
 constexpr int kPieces16 = 4;                                   // 16-byte pieces per column chunk
 constexpr int kPer16 = (16 * kColGroup * kPieces16 + 255) / 256;
@@ -92,20 +95,20 @@ __device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* con
     sdst[0][i] = &lds[0][col][q * 8];
     sdst[1][i] = &lds[1][col][q * 8];
   }
-  v8 a[kRing16][kRF16], stg[kPer16];
+  v8 a[kRing16][kRF16], stg[kStg16][kPer16];
   auto load_a = [&](v8 (&x)[kRF16], int c) __attribute__((always_inline)) {
     const int k0 = min(c, nch - 1) * 32;
 #pragma unroll
     for (int rf = 0; rf < kRF16; ++rf) x[rf] = *(const v8*)(mrow[rf] + k0);
   };
-  auto stage_load = [&](int c) __attribute__((always_inline)) {
+  auto stage_load = [&](v8 (&x)[kPer16], int c) __attribute__((always_inline)) {
     const int k0 = min(c, nch - 1) * 32;
 #pragma unroll
-    for (int i = 0; i < kPer16; ++i) stg[i] = *(const v8*)(ssrc[i] + k0);
+    for (int i = 0; i < kPer16; ++i) x[i] = *(const v8*)(ssrc[i] + k0);
   };
-  auto stage_store = [&](int buf) __attribute__((always_inline)) {
+  auto stage_store = [&](const v8 (&x)[kPer16], int buf) __attribute__((always_inline)) {
 #pragma unroll
-    for (int i = 0; i < kPer16; ++i) *(v8*)sdst[buf][i] = stg[i];
+    for (int i = 0; i < kPer16; ++i) *(v8*)sdst[buf][i] = x[i];
   };
   auto step = [&](const v8 (&x)[kRF16], int buf, auto full, auto first)
       __attribute__((always_inline)) {
@@ -113,6 +116,9 @@ __device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* con
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (decltype(full)::value || cf < ncf) bv[cf] = *(const v8*)&lds[buf][cf * 16 + i16][8 * g4];
+    // all nine reads in flight before the first product (the scheduler would otherwise pair
+    // each read with its products and wait out the LDS latency nine times)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (decltype(full)::value || cf < ncf)
@@ -123,14 +129,16 @@ __device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* con
         }
   };
   // per chunk c (buffer c & 1): multiply; store the staged chunk c+1 into the other buffer
-  // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+2; then the Phi
-  // load of chunk c + kRing16 - 1 (after the staging loads: the memory counter completes in
-  // issue order); barrier
+  // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+1+kStg16 into
+  // the registers just stored from; then the Phi load of chunk c + kRing16 - 1 (after the
+  // staging loads: the memory counter completes in issue order); barrier.  A staged chunk is
+  // loaded kStg16 chunks before it is stored, the Phi operand kRing16 - 1 before it is used.
   auto chunk = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
     constexpr int i = decltype(ic)::value;
+    constexpr int si = (i + 1) % kStg16;
     step(a[i], i & 1, full, first);
-    stage_store((i + 1) & 1);
-    stage_load(c + i + 2);
+    stage_store(stg[si], (i + 1) & 1);
+    stage_load(stg[si], c + i + 1 + kStg16);
     load_a(a[(i + kRing16 - 1) % kRing16], c + i + kRing16 - 1);
     __syncthreads();
   };
@@ -141,11 +149,12 @@ __device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* con
     });
   };
   auto run = [&](auto full) __attribute__((always_inline)) {
-    stage_load(0);
+#pragma unroll
+    for (int i = 0; i < kStg16; ++i) stage_load(stg[i], i);
 #pragma unroll
     for (int i = 0; i + 1 < kRing16; ++i) load_a(a[i], i);
-    stage_store(0);
-    stage_load(1);
+    stage_store(stg[0], 0);
+    stage_load(stg[0], kStg16);
     __syncthreads();
     int c = 0;
     if (nch >= kRing16) {   // kRing16 is even: chunk c + i is in buffer i & 1
@@ -158,8 +167,8 @@ __device__ inline void nt16_mainloop(f4 (&acc)[kRF16][kColGroup], const T16* con
     for (int i = 0; i + 1 < kRing16; ++i) {
       if (c + i >= nch) break;
       step(a[i], i & 1, full, std::false_type{});
-      stage_store((i + 1) & 1);
-      stage_load(c + i + 2);
+      stage_store(stg[(i + 1) % kStg16], (i + 1) & 1);
+      stage_load(stg[(i + 1) % kStg16], c + i + 1 + kStg16);
       __syncthreads();
     }
   };
@@ -187,17 +196,18 @@ __global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
   if (act != nullptr && act[t] == 0) return;   // uniform over the block
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
-  const int np = (int)((w16_off[t + 1] - w16_off[t]) / Rp);
+  const int np = (nt + 31) / 32 * 32;
+  const int64_t ldw = (w16_off[t + 1] - w16_off[t]) / Rp, ldd = ld16(D);
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
   // rows past N_t read row 0 of the task; the epilogue writes their outputs as zeros
   const T16* mrow[kRF16];
 #pragma unroll
   for (int rf = 0; rf < kRF16; ++rf) {
     const int row = n0 + rf * 16 + i16;
-    mrow[rf] = phi16 + (r0 + (row < nt ? row : 0)) * (int64_t)D + 8 * g4;
+    mrow[rf] = phi16 + (r0 + (row < nt ? row : 0)) * ldd + 8 * g4;
   }
   f4 acc[kRF16][kColGroup];
-  nt16_mainloop<T16>(acc, mrow, V16 + ((int64_t)t * Rp + cf0 * 16) * D, D, ncf, D, lds);
+  nt16_mainloop<T16>(acc, mrow, V16 + ((int64_t)t * Rp + cf0 * 16) * ldd, ldd, ncf, D, lds);
   typedef T16 t4 __attribute__((ext_vector_type(4)));
   T16* Wt = W16 + w16_off[t];
 #pragma unroll
@@ -211,7 +221,7 @@ __global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
       t4 o;
 #pragma unroll
       for (int r = 0; r < 4; ++r) o[r] = rb + 4 * g4 + r < nt ? (T16)acc[rf][cf][r] : (T16)0.f;
-      *(t4*)(Wt + (int64_t)j * np + rb + 4 * g4) = o;
+      *(t4*)(Wt + (int64_t)j * ldw + rb + 4 * g4) = o;
     }
   }
 }
@@ -220,6 +230,7 @@ __global__ __launch_bounds__(256) void k_phi_v16(const T16* __restrict__ phi16,
 // the bare PhiT16_t W16_t (the CG update then adds beta and the diagonal term).
 template <typename T16>
 __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16,
+                                                  const int64_t* __restrict__ row_off,
                                                   const int64_t* __restrict__ w16_off,
                                                   const int4* __restrict__ tiles, int ntiles,
                                                   const T16* __restrict__ W16,
@@ -238,7 +249,8 @@ __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16
   const int d0 = uniform(tl.y) + uniform((int)(threadIdx.x >> 6)) * kRows16;
   if (act != nullptr && act[t] == 0) return;   // uniform over the block
   const int64_t wo = w16_off[t];
-  const int np = (int)((w16_off[t + 1] - wo) / Rp);
+  const int np = (int)((row_off[t + 1] - row_off[t] + 31) / 32 * 32);
+  const int64_t ldw = (w16_off[t + 1] - wo) / Rp;
   const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
   const T16* M = phiT16 + (wo / Rp) * (int64_t)D;
   // rows past D read row 0; their outputs are not stored
@@ -246,10 +258,10 @@ __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16
 #pragma unroll
   for (int rf = 0; rf < kRF16; ++rf) {
     const int row = d0 + rf * 16 + i16;
-    mrow[rf] = M + (int64_t)(row < D ? row : 0) * np + 8 * g4;
+    mrow[rf] = M + (int64_t)(row < D ? row : 0) * ldw + 8 * g4;
   }
   f4 acc[kRF16][kColGroup];
-  nt16_mainloop<T16>(acc, mrow, W16 + wo + (int64_t)(cf0 * 16) * np, np, ncf, np, lds);
+  nt16_mainloop<T16>(acc, mrow, W16 + wo + (int64_t)(cf0 * 16) * ldw, ldw, ncf, np, lds);
   if (alpha == nullptr) {   // bare product: stores only
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
@@ -284,7 +296,8 @@ __global__ __launch_bounds__(256) void k_phit_w16(const T16* __restrict__ phiT16
   }
 }
 
-// PhiT16 of every task: [D][np_t] with zero columns n >= N_t.  32x32 tiles through LDS.
+// PhiT16 of every task: [D][np_t] (pitch ld16(np_t)) with zero columns N_t <= n < np_t.
+// 32x32 tiles through LDS.
 template <typename T16>
 __global__ __launch_bounds__(256) void k_transpose16(const T16* __restrict__ phi16,
                                                      const int64_t* __restrict__ row_off,
@@ -293,37 +306,47 @@ __global__ __launch_bounds__(256) void k_transpose16(const T16* __restrict__ phi
   __shared__ T16 tileb[32][33];
   const int t = blockIdx.z;
   const int64_t wo = w16_off[t];
-  const int np = (int)((w16_off[t + 1] - wo) / Rp);
-  const int n0 = blockIdx.y * 32, d0 = blockIdx.x * 32;
-  if (n0 >= np) return;
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
+  const int np = (nt + 31) / 32 * 32;
+  const int64_t ldw = (w16_off[t + 1] - wo) / Rp, ldd = ld16(D);
+  const int n0 = blockIdx.y * 32, d0 = blockIdx.x * 32;
+  if (n0 >= np) return;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
   for (int i = ty; i < 32; i += 8) {
     const int n = n0 + i, d = d0 + tx;
-    tileb[i][tx] = (n < nt && d < D) ? phi16[(r0 + n) * (int64_t)D + d] : (T16)0.f;
+    tileb[i][tx] = (n < nt && d < D) ? phi16[(r0 + n) * ldd + d] : (T16)0.f;
   }
   __syncthreads();
   T16* out = phiT16 + (wo / Rp) * (int64_t)D;
   for (int i = ty; i < 32; i += 8) {
     const int d = d0 + i, n = n0 + tx;
-    if (d < D) out[(int64_t)d * np + n] = tileb[tx][i];
+    if (d < D) out[(int64_t)d * ldw + n] = tileb[tx][i];
   }
 }
 
+// y[r][c] = round16(x[r][c]); four consecutive elements of one row per thread (cols is a
+// multiple of 4 where the rows' starts are 16-byte aligned; otherwise element by element).
 template <typename T16>
-__global__ __launch_bounds__(256) void k_round16(const float* __restrict__ x,
-                                                 T16* __restrict__ y, int64_t n) {
-  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (i + 3 < n) {
-    const f4 v = *(const f4*)(x + i);
+__global__ __launch_bounds__(256) void k_round16(const float* __restrict__ x, int64_t ldx,
+                                                 T16* __restrict__ y, int64_t ldy, int64_t rows,
+                                                 int cols) {
+  const int quads = (cols + 3) / 4;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows * quads) return;
+  const int64_t r = i / quads;
+  const int c = (int)(i - r * quads) * 4;
+  const float* xr = x + r * ldx;
+  T16* yr = y + r * ldy;
+  if (c + 3 < cols && (ldx & 3) == 0 && (ldy & 3) == 0) {
+    const f4 v = *(const f4*)(xr + c);
     typedef T16 t4 __attribute__((ext_vector_type(4)));
     t4 o;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) o[r] = (T16)v[r];
-    *(t4*)(y + i) = o;
+    for (int k = 0; k < 4; ++k) o[k] = (T16)v[k];
+    *(t4*)(yr + c) = o;
   } else {
-    for (int64_t k = i; k < n; ++k) y[k] = (T16)x[k];
+    for (int k = c; k < c + 4 && k < cols; ++k) yr[k] = (T16)xr[k];
   }
 }
 
@@ -409,7 +432,8 @@ hipError_t launch_mixed_products(const Geometry& g16, const void* phi16, const v
   }
   if (nadj == 0) return hipSuccess;
   hipLaunchKernelGGL((k_phit_w16<T16>), dim3(nadj), dim3(256), 0, st,
-                     (const T16*)phiT16, g16.w_off, adj, nadj, (const T16*)W16, V, AV, alpha,
+                     (const T16*)phiT16, g16.row_off, g16.w_off, adj, nadj, (const T16*)W16, V,
+                     AV, alpha,
                      colc, beta, act, g16.D, g16.Rp);
   return hipGetLastError();
 }
@@ -425,10 +449,12 @@ hipError_t launch_transpose16(const Geometry& g16, const void* phi16, void* phiT
 }
 
 template <typename T16>
-hipError_t launch_round16(const float* x, void* y, int64_t n, hipStream_t st) {
+hipError_t launch_round16(const float* x, int64_t ldx, void* y, int64_t ldy, int64_t rows,
+                          int cols, hipStream_t st) {
+  const int64_t n = rows * ((cols + 3) / 4);
   if (n == 0) return hipSuccess;
-  const int64_t blocks = (n / 4 + 255) / 256 + 1;
-  hipLaunchKernelGGL((k_round16<T16>), dim3((unsigned)blocks), dim3(256), 0, st, x, (T16*)y, n);
+  hipLaunchKernelGGL((k_round16<T16>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, x,
+                     ldx, (T16*)y, ldy, rows, cols);
   return hipGetLastError();
 }
 
@@ -460,7 +486,8 @@ hipError_t launch_replace(const Geometry& g, const CgState& s, const float* AX,
       int, hipStream_t);                                                                       \
   template hipError_t launch_transpose16<T16>(const Geometry&, const void*, void*, int,       \
                                               hipStream_t);                                    \
-  template hipError_t launch_round16<T16>(const float*, void*, int64_t, hipStream_t);
+  template hipError_t launch_round16<T16>(const float*, int64_t, void*, int64_t, int64_t, int, \
+                                          hipStream_t);
 CMTCS_INST16(__bf16)
 CMTCS_INST16(_Float16)
 
