@@ -34,6 +34,7 @@ def _ref_apply(w, alpha, V, cc):
     dict(T=4, C=3, D=208, N=[0, 17, 70, 129], R=37),      # ragged rows, partial tiles
     dict(T=2, C=4, D=512, N=256, R=150),                   # two column groups
     dict(T=4, C=1, D=48, N=[5, 16, 33, 1], R=9),           # one-chunk tasks, odd chunk count
+    dict(T=3, C=2, D=96, N=[40, 0, 23], R=130),            # last fragment 2/16 full, empty task
 ])
 def test_apply(math, tol, shape):
     shape = dict(shape)
@@ -59,10 +60,13 @@ def test_apply(math, tol, shape):
 @pytest.mark.parametrize("shape", [
     dict(T=4, C=3, D=208, N=[0, 17, 70, 129], R=37),      # ragged rows, partial tiles
     dict(T=2, C=4, D=512, N=[256, 200], R=150),            # two column groups
+    dict(T=2, C=4, D=256, N=[96, 40], R=132),              # the measured workload's 132 columns
+    dict(T=2, C=3, D=128, N=[64, 33], R=275),              # two groups, last fragment 3/16 full
 ])
 def test_apply_every_tile_shape(math, tol, tiles, shape, monkeypatch):
     """Every tile shape of both products (pinned through CMTCS_TILES), including the LDS-staged
-    forward kernel, whose four-wave tiles run past the rows of small tasks."""
+    forward kernel, whose four-wave tiles run past the rows of small tasks, and column counts
+    whose last 16-column fragment is mostly padding (R = 132, 275)."""
     monkeypatch.setenv("CMTCS_TILES", tiles)
     shape = dict(shape)
     R = shape.pop("R")
