@@ -122,7 +122,8 @@ typedef struct {
                                given shape, alpha pointer and step policy and replayed after
                                that (all steps are launched; work for right-hand sides that
                                have stopped is skipped inside the kernels, and kernel timing by
-                               cmtcs_profile is not available); 0 = launch step by step     */
+                               cmtcs_profile is not available); 0 = launch step by step.
+                               cmtcs_em_iter: 1 = record the whole EM iteration (see there) */
 } cmtcs_opts_t;
 
 /* Optional per-right-hand-side outputs, device pointers, each may be NULL.  For cmtcs_estep
@@ -173,6 +174,20 @@ cmtcs_status_t cmtcs_estep(cmtcs_handle_t h, const float* alpha, const double* l
  *   mu, s [T][C][D] float; q [T][C] double; alpha_inout [C][D] float, updated in place. */
 cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, const double* q,
                            const cmtcs_opts_t* opts, float* alpha_inout);
+
+/* One EM iteration of Alg. 2: cmtcs_estep from alpha_inout (no stats) followed by cmtcs_mstep
+ * into alpha_inout, with the same arguments, outputs and results as those two calls.  With
+ * opts->graph = 1 (MATH_F64 and MATH_F32) the device work of the whole iteration -- CG start,
+ * all CG steps (as in the graph mode of cmtcs_estep), diagonal estimate, log-determinant,
+ * responsibilities and M-step -- is recorded once as a HIP graph and replayed by later calls
+ * with the same shape (K), step policy, tol, alpha_max and the same eight array pointers
+ * (alpha_inout, log_pi, mu, s, logdet, ell, q, opts->probes); opts->seed and opts->em_iter may
+ * change between calls (the probe key is a device word set before each replay).  Other calls
+ * on the handle between iterations are allowed.  MATH_MIXED, or graph = 0, launches step by
+ * step.  Errors as cmtcs_estep and cmtcs_mstep. */
+cmtcs_status_t cmtcs_em_iter(cmtcs_handle_t h, float* alpha_inout, const double* log_pi,
+                             const cmtcs_opts_t* opts, float* mu, float* s, double* logdet,
+                             double* ell, double* q);
 
 /* Batched CG (Alg. 1) on caller-supplied right-hand sides: for task t and column j solves
  * (beta Phi_t^T Phi_t + diag(alpha_{col_cluster[t][j]})) X[t][j] = B[t][j] from x = 0.

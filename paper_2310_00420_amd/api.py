@@ -146,6 +146,29 @@ class Cmtcs:
                                            _ptr(alpha)))
         return alpha
 
+    def em_iter(self, alpha, log_pi, K, out=None, fixed_iters=0, tol=1e-6, max_iters=200,
+                seed=1, em_iter=0, probes=None, alpha_max=1e10, graph=False):
+        """One EM iteration (Alg. 2): E-step from ``alpha``, then the M-step into ``alpha`` (in
+        place).  ``out`` (the dict a previous call returned) is reused for the outputs, so that
+        with ``graph`` the recorded iteration replays on the same buffers."""
+        self._check_stream()
+        T, C, D, dev = self.T, self.C, self.D, self.device
+        _need(alpha, torch.float32, (C, D), "alpha")
+        _need(log_pi, torch.float64, (C,), "log_pi")
+        if probes is not None:
+            _need(probes, torch.int8, (T, C, K, D), "probes")
+        if out is None:
+            out = dict(mu=torch.empty(T, C, D, device=dev), s=torch.empty(T, C, D, device=dev),
+                       logdet=torch.empty(T, C, dtype=torch.float64, device=dev),
+                       ell=torch.empty(T, C, dtype=torch.float64, device=dev),
+                       q=torch.empty(T, C, dtype=torch.float64, device=dev))
+        o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
+                       em_iter=em_iter, probes=probes, alpha_max=alpha_max, graph=graph)
+        _lib.check(_lib.load().cmtcs_em_iter(
+            self._h, _ptr(alpha), _ptr(log_pi), ctypes.byref(o), _ptr(out["mu"]), _ptr(out["s"]),
+            _ptr(out["logdet"]), _ptr(out["ell"]), _ptr(out["q"])))
+        return out
+
     def solve(self, alpha, B, col_cluster, fixed_iters=0, tol=1e-6, max_iters=200,
               coefs=False, stats=False, graph=False):
         """X[t][j] = A_{t, col_cluster[j]}^-1 B[t][j] by CG (Alg. 1)."""
@@ -234,11 +257,22 @@ class Cmtcs:
 def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
         alpha_max=1e10, probes_fn=None, callback=None, graph=False):
     """CoFEM (Alg. 2): n_em iterations of E-step + M-step from alpha0, then a_t = argmax_c q_tc
-    (lowest c on ties) and mu_{t, a_t} from the last E-step."""
+    (lowest c on ties) and mu_{t, a_t} from the last E-step.  With ``graph`` each iteration is
+    one replay of the recorded EM iteration (cmtcs_em_iter), on output buffers reused from one
+    iteration to the next; ``callback(it, alpha, out)`` then sees alpha as the E-step used it
+    (a copy) and the outputs before the next iteration overwrites them."""
     alpha = alpha0.clone()
     out = None
     for it in range(n_em):
         pr = None if probes_fn is None else probes_fn(it)
+        if graph:
+            before = alpha.clone() if callback is not None else None
+            out = model.em_iter(alpha, log_pi, K, out=out, fixed_iters=fixed_iters, tol=tol,
+                                max_iters=max_iters, seed=seed, em_iter=it, probes=pr,
+                                alpha_max=alpha_max, graph=True)
+            if callback is not None:
+                callback(it, before, out)
+            continue
         out = model.estep(alpha, log_pi, K, fixed_iters=fixed_iters, tol=tol,
                           max_iters=max_iters, seed=seed, em_iter=it, probes=pr, graph=graph)
         if callback is not None:

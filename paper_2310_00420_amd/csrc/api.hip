@@ -94,6 +94,24 @@ struct cmtcs_handle_s {
              fwd_rows == o.fwd_rows && adj_rows == o.adj_rows;
     }
   } graph_key{};
+  // recorded EM iteration (cmtcs_em_iter with opts.graph): E-step and M-step as one graph
+  hipGraph_t em_graph = nullptr;
+  hipGraphExec_t em_exec = nullptr;
+  struct EmKey {
+    const void* p[8];   // alpha, log_pi, mu, s, logdet, ell, q, probes
+    int K, steps, fixed, R, Rp, fwd_rows, adj_rows;
+    double tol, alpha_max;
+    bool operator==(const EmKey& o) const {
+      for (int i = 0; i < 8; ++i)
+        if (p[i] != o.p[i]) return false;
+      return K == o.K && steps == o.steps && fixed == o.fixed && R == o.R && Rp == o.Rp &&
+             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows && tol == o.tol &&
+             alpha_max == o.alpha_max;
+    }
+  } em_key{};
+  // probe key of the current E-step, read by the kernels that draw probes (a device word, so
+  // that a recorded E-step replays with the key of each new EM iteration)
+  uint64_t* key_d = nullptr;
 
   // kernel timing (cmtcs_profile)
   bool prof_on = false;
@@ -121,6 +139,8 @@ struct cmtcs_handle_s {
         for (auto& e : row) (void)hipEventDestroy(e);
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (em_exec) (void)hipGraphExecDestroy(em_exec);
+    if (em_graph) (void)hipGraphDestroy(em_graph);
     if (cap_st) (void)hipStreamDestroy(cap_st);
   }
 
@@ -137,17 +157,7 @@ struct cmtcs_handle_s {
         HIP_TRY(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking), "hipStreamCreate");
       HIP_TRY(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed),
               "hipStreamBeginCapture");
-      const CgState s = cg_loop(alpha);
-      hipError_t e = hipSuccess;
-      for (int u = 0; u < steps && e == hipSuccess; ++u) {
-        const int* act_u = act + (size_t)u * T;
-        e = launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, fwd_rows,
-                             cap_st);
-        if (e == hipSuccess)
-          e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
-                                nullptr, colc, beta, act_u, adj_rows, cap_st);
-        if (e == hipSuccess) e = launch_cg_update<VT>(g, s, u, steps, fixed, 0, cap_st);
-      }
+      hipError_t e = cg_steps_all<VT>(g, alpha, steps, fixed, cap_st);
       hipGraph_t gr = nullptr;
       const hipError_t e2 = hipStreamEndCapture(cap_st, &gr);
       if (e != hipSuccess) {
@@ -162,6 +172,25 @@ struct cmtcs_handle_s {
     }
     HIP_TRY(hipGraphLaunch(graph_exec, st), "hipGraphLaunch");
     return CMTCS_OK;
+  }
+
+  // All `steps` CG steps (three launches each) on stream s, with no host check in between:
+  // columns and tasks that have stopped return at once inside the kernels.  The form a graph
+  // records.
+  template <typename VT>
+  hipError_t cg_steps_all(const Geometry& g, const float* alpha, int steps, int fixed,
+                          hipStream_t s) {
+    const CgState cs = cg_loop(alpha);
+    hipError_t e = hipSuccess;
+    for (int u = 0; u < steps && e == hipSuccess; ++u) {
+      const int* act_u = act + (size_t)u * T;
+      e = launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, fwd_rows, s);
+      if (e == hipSuccess)
+        e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
+                              nullptr, colc, beta, act_u, adj_rows, s);
+      if (e == hipSuccess) e = launch_cg_update<VT>(g, cs, u, steps, fixed, 0, s);
+    }
+    return e;
   }
 
   // Adds the durations of the `ev_pending` timed steps recorded so far.
@@ -415,7 +444,7 @@ struct cmtcs_handle_s {
     const Geometry g = geom(R, Rp);
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
     RhsSource src;
-    src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.key = 0; src.probes = nullptr;
+    src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, 0.0, 0, st), "launch(cg_init)");
     HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
                              fwd_rows, st), "launch(phi_v)");
@@ -458,13 +487,14 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, K, nullptr, st), "launch(fill_colc)");
     rs = tune<VT>(g, alpha);
     if (rs != CMTCS_OK) return rs;
+    HIP_TRY(launch_set_key(key_d, key, st), "launch(set_key)");
     RhsSource src;
-    src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.key = key; src.probes = o.probes;
+    src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.keyp = key_d; src.probes = o.probes;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
     if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
     else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
     if (rs != CMTCS_OK) return rs;
-    HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key, o.probes, mu, sd, st),
+    HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, mu, sd, st),
             "launch(estep_finalize)");
     HIP_TRY(launch_sum_log_alpha(C, D, alpha, slog, st), "launch(sum_log_alpha)");
     HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, st),
@@ -484,6 +514,80 @@ struct cmtcs_handle_s {
     return CMTCS_OK;
   }
 
+  // The device work of one EM iteration (E-step without stats, then the M-step) on stream s,
+  // with the fixed-length CG loop: what cmtcs_em_iter records as one graph.
+  template <typename VT>
+  hipError_t em_launches(const Geometry& g, float* alpha, const double* log_pi,
+                         const cmtcs_opts_t& o, int steps, int fixed, float* mu, float* sd,
+                         double* logdet, double* ell, double* q, hipStream_t s) {
+    const int K = o.K;
+    RhsSource src;
+    src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.keyp = key_d; src.probes = o.probes;
+    // the cluster map is rewritten here (other calls on the handle reuse its buffer)
+    hipError_t e = launch_fill_colc(colc, T, g.R, g.Rp, K, nullptr, s);
+    if (e == hipSuccess) e = launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, s);
+    if (e == hipSuccess) e = cg_steps_all<VT>(g, alpha, steps, fixed, s);
+    if (e == hipSuccess)
+      e = launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, mu, sd, s);
+    if (e == hipSuccess) e = launch_sum_log_alpha(C, D, alpha, slog, s);
+    if (e == hipSuccess)
+      e = launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, s);
+    if (e == hipSuccess)
+      e = launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, s);
+    if (e == hipSuccess) e = launch_mstep(T, C, D, mu, sd, q, o.alpha_max, alpha, s);
+    return e;
+  }
+
+  // One EM iteration (Alg. 2): the E-step from alpha, then the M-step into alpha.  With
+  // opts.graph (MATH_F64 / MATH_F32) the whole device sequence is recorded once per shape,
+  // step policy and set of buffers and replayed; only the probe key (a device word set before
+  // the replay) changes from one iteration to the next.
+  template <typename VT>
+  cmtcs_status_t em_iter(float* alpha, const double* log_pi, const cmtcs_opts_t& o, float* mu,
+                         float* sd, double* logdet, double* ell, double* q) {
+    if (!o.graph || mixed()) {
+      cmtcs_status_t rs = estep<VT>(alpha, log_pi, o, mu, sd, logdet, ell, q, nullptr);
+      if (rs != CMTCS_OK) return rs;
+      HIP_TRY(launch_mstep(T, C, D, mu, sd, q, o.alpha_max, alpha, st), "launch(mstep)");
+      return CMTCS_OK;
+    }
+    const int K = o.K, R = C * (K + 1), Rp = col_slots(R);
+    cmtcs_status_t rs = prepare(Rp);
+    if (rs != CMTCS_OK) return rs;
+    const Geometry g = geom(R, Rp);
+    const int fixed = o.fixed_iters > 0 ? 1 : 0;
+    const int steps = fixed ? o.fixed_iters : o.max_iters;
+    HIP_TRY(launch_fill_colc(colc, T, R, Rp, K, nullptr, st), "launch(fill_colc)");
+    rs = tune<VT>(g, alpha);   // trial launches happen here, never inside a recording
+    if (rs != CMTCS_OK) return rs;
+    HIP_TRY(launch_set_key(key_d, probe_key(o.seed, o.em_iter), st), "launch(set_key)");
+    const EmKey key{{alpha, log_pi, mu, sd, logdet, ell, q, o.probes}, K, steps, fixed, R, Rp,
+                    fwd_rows, adj_rows, fixed ? 0.0 : o.tol, o.alpha_max};
+    if (em_exec == nullptr || !(key == em_key)) {
+      if (em_exec) { (void)hipGraphExecDestroy(em_exec); em_exec = nullptr; }
+      if (em_graph) { (void)hipGraphDestroy(em_graph); em_graph = nullptr; }
+      if (cap_st == nullptr)
+        HIP_TRY(hipStreamCreateWithFlags(&cap_st, hipStreamNonBlocking), "hipStreamCreate");
+      HIP_TRY(hipStreamBeginCapture(cap_st, hipStreamCaptureModeRelaxed),
+              "hipStreamBeginCapture");
+      const hipError_t e = em_launches<VT>(g, alpha, log_pi, o, steps, fixed, mu, sd, logdet,
+                                           ell, q, cap_st);
+      hipGraph_t gr = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cap_st, &gr);
+      if (e != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(e, "graph recording (EM iteration)");
+      }
+      if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+      em_graph = gr;
+      HIP_TRY(hipGraphInstantiate(&em_exec, em_graph, nullptr, nullptr, 0),
+              "hipGraphInstantiate");
+      em_key = key;
+    }
+    HIP_TRY(hipGraphLaunch(em_exec, st), "hipGraphLaunch");
+    return CMTCS_OK;
+  }
+
   template <typename VT>
   cmtcs_status_t solve(const float* alpha, int R, const int32_t* col_cluster, const void* B,
                        void* Xout, double* gout, double* xout, const cmtcs_opts_t& o,
@@ -498,7 +602,7 @@ struct cmtcs_handle_s {
     rs = tune<VT>(g, alpha);
     if (rs != CMTCS_OK) return rs;
     RhsSource src;
-    src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.key = 0; src.probes = nullptr;
+    src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
     if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
     else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
@@ -651,6 +755,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->adj_tiles, sizeof(int4) * adj_max);
   // SLQ tridiagonals of runs too long for LDS
   A(&h->slq_ws, std::max<size_t>(16, slq_workspace_bytes((long)P, (int)it)));
+  A(&h->key_d, sizeof(uint64_t));
   A(&h->tau, sizeof(double) * P);
   A(&h->rmin, sizeof(double) * P);
   A(&h->rmax, sizeof(double) * P);
@@ -749,6 +854,20 @@ cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, co
   HIP_TRY(launch_mstep(h->T, h->C, h->D, mu, s, q, opts->alpha_max, alpha_inout, h->st),
           "launch(mstep)");
   return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_em_iter(cmtcs_handle_t h, float* alpha_inout, const double* log_pi,
+                             const cmtcs_opts_t* opts, float* mu, float* s, double* logdet,
+                             double* ell, double* q) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  cmtcs_status_t rs = check_opts(h, opts, true);
+  if (rs != CMTCS_OK) return rs;
+  if (!(opts->alpha_max > 0.0)) return fail(CMTCS_E_INVALID, "alpha_max must be > 0");
+  if (!alpha_inout || !log_pi || !mu || !s || !logdet || !ell || !q)
+    return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  if (h->math == CMTCS_MATH_F64)
+    return h->em_iter<double>(alpha_inout, log_pi, *opts, mu, s, logdet, ell, q);
+  return h->em_iter<float>(alpha_inout, log_pi, *opts, mu, s, logdet, ell, q);
 }
 
 cmtcs_status_t cmtcs_solve(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,

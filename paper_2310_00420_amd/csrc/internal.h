@@ -217,7 +217,8 @@ struct RhsSource {
   const void* b;            // kind 0: [T][D] b_t of the element type
   const void* B;            // kind 1
   int K;                    // kind 0
-  uint64_t key;             // kind 0: probe key
+  const uint64_t* keyp;     // kind 0: device word holding the probe key (read by the kernels,
+                            // so that a recorded launch sequence can be replayed with a new key)
   const int8_t* probes;     // kind 0: optional explicit probes [T][C][K][D]
 };
 template <typename VT>
@@ -228,8 +229,10 @@ hipError_t launch_cg_init(const Geometry& g, const CgState& s, const RhsSource& 
 template <typename VT>
 hipError_t launch_cg_update(const Geometry& g, const CgState& s, int u, int steps, int fixed,
                             int split, hipStream_t st);
+// Writes the probe key of an E-step to the device word keyp (one thread).
+hipError_t launch_set_key(uint64_t* keyp, uint64_t key, hipStream_t st);
 template <typename VT>
-hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, uint64_t key,
+hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, const uint64_t* keyp,
                                  const int8_t* probes, float* mu, float* sdiag, hipStream_t st);
 template <typename VT>
 hipError_t launch_solve_output(const Geometry& g, const CgState& s, void* X, double* gam_out,

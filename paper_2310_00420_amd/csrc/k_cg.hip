@@ -18,7 +18,8 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
                                                 uint8_t* __restrict__ state,
                                                 int* __restrict__ iters, int* __restrict__ act,
                                                 int kind, const VT* __restrict__ b,
-                                                const VT* __restrict__ B, int K, uint64_t key,
+                                                const VT* __restrict__ B, int K,
+                                                const uint64_t* __restrict__ keyp,
                                                 const int8_t* __restrict__ probes, double tol2,
                                                 int C, int R, int Rp, int D) {
   __shared__ double sh[BS / 64];
@@ -34,7 +35,12 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
     return;
   }
   int c = 0, k = 0;
-  if (kind == 0) { c = j / (K + 1); k = j % (K + 1); }
+  uint64_t key = 0;
+  if (kind == 0) {
+    c = j / (K + 1);
+    k = j % (K + 1);
+    if (probes == nullptr) key = *keyp;
+  }
   double acc = 0.0;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
@@ -177,7 +183,7 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
 // mu_tc = x of the mean system; s_tc = (1/K) sum_k p_k (.) x_k  (Eq. (diag-est)).
 template <typename VT>
 __global__ __launch_bounds__(256) void k_estep_finalize(const VT* __restrict__ X, int K,
-                                                        uint64_t key,
+                                                        const uint64_t* __restrict__ keyp,
                                                         const int8_t* __restrict__ probes,
                                                         float* __restrict__ mu,
                                                         float* __restrict__ sdiag, int C, int Rp,
@@ -188,6 +194,7 @@ __global__ __launch_bounds__(256) void k_estep_finalize(const VT* __restrict__ X
   if (d >= D) return;
   const int64_t base = ((int64_t)t * Rp + (int64_t)c * (K + 1)) * D + d;
   mu[(int64_t)tc * D + d] = (float)X[base];
+  const uint64_t key = probes == nullptr ? *keyp : 0;
   double acc = 0.0;
   for (int k = 0; k < K; ++k) {
     const double p = probes != nullptr
@@ -328,7 +335,7 @@ static hipError_t init_one(const Geometry& g, const CgState& s, const RhsSource&
                            double tol2, hipStream_t st) {
   hipLaunchKernelGGL((k_cg_init<VT, BS, EPT>), dim3(g.T * g.Rp), dim3(BS), 0, st, (VT*)s.X,
                      (VT*)s.Rv, (VT*)s.Dv, s.rr, s.thr, s.state, s.iters, s.act, src.kind,
-                     (const VT*)src.b, (const VT*)src.B, src.K, src.key, src.probes, tol2, g.C,
+                     (const VT*)src.b, (const VT*)src.B, src.K, src.keyp, src.probes, tol2, g.C,
                      g.R, g.Rp, g.D);
   return hipGetLastError();
 }
@@ -376,11 +383,20 @@ hipError_t launch_cg_update(const Geometry& g, const CgState& s, int u, int step
   CMTCS_DISPATCH_D(update_one, g, s, u, steps, fixed, split, st);
 }
 
+__global__ void k_set_key(uint64_t* __restrict__ keyp, uint64_t key) {
+  if (threadIdx.x == 0) *keyp = key;
+}
+
+hipError_t launch_set_key(uint64_t* keyp, uint64_t key, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_key, dim3(1), dim3(64), 0, st, keyp, key);
+  return hipGetLastError();
+}
+
 template <typename VT>
-hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, uint64_t key,
+hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, const uint64_t* keyp,
                                  const int8_t* probes, float* mu, float* sdiag, hipStream_t st) {
   hipLaunchKernelGGL((k_estep_finalize<VT>), dim3(g.T * g.C, (g.D + 255) / 256), dim3(256), 0,
-                     st, (const VT*)s.X, K, key, probes, mu, sdiag, g.C, g.Rp, g.D);
+                     st, (const VT*)s.X, K, keyp, probes, mu, sdiag, g.C, g.Rp, g.D);
   return hipGetLastError();
 }
 
@@ -483,9 +499,11 @@ template hipError_t launch_cg_update<double>(const Geometry&, const CgState&, in
                                              int, hipStream_t);
 template hipError_t launch_cg_update<float>(const Geometry&, const CgState&, int, int, int, int,
                                             hipStream_t);
-template hipError_t launch_estep_finalize<double>(const Geometry&, const CgState&, int, uint64_t,
+template hipError_t launch_estep_finalize<double>(const Geometry&, const CgState&, int,
+                                                  const uint64_t*,
                                                   const int8_t*, float*, float*, hipStream_t);
-template hipError_t launch_estep_finalize<float>(const Geometry&, const CgState&, int, uint64_t,
+template hipError_t launch_estep_finalize<float>(const Geometry&, const CgState&, int,
+                                                 const uint64_t*,
                                                  const int8_t*, float*, float*, hipStream_t);
 template hipError_t launch_solve_output<double>(const Geometry&, const CgState&, void*, double*,
                                                 double*, int, int*, uint8_t*, hipStream_t);

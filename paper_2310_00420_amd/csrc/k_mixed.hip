@@ -361,7 +361,8 @@ __global__ __launch_bounds__(BS) void k_replace(const float* __restrict__ AX,
                                                 int* __restrict__ iters,
                                                 double* __restrict__ xi, int* __restrict__ act,
                                                 int kind, const float* __restrict__ b,
-                                                const float* __restrict__ B, int K, uint64_t key,
+                                                const float* __restrict__ B, int K,
+                                                const uint64_t* __restrict__ keyp,
                                                 const int8_t* __restrict__ probes, int u,
                                                 int steps, int fixed, int T, int C, int R,
                                                 int Rp, int D) {
@@ -371,7 +372,12 @@ __global__ __launch_bounds__(BS) void k_replace(const float* __restrict__ AX,
   if (state[idx] != kActive) return;
   const double rr_old = rr[idx];
   int c = 0, k = 0;
-  if (kind == 0) { c = j / (K + 1); k = j % (K + 1); }
+  uint64_t key = 0;
+  if (kind == 0) {
+    c = j / (K + 1);
+    k = j % (K + 1);
+    if (probes == nullptr) key = *keyp;
+  }
   const int64_t base = idx * D;
   float rv[EPT];
   double acc = 0.0;
@@ -463,7 +469,7 @@ static hipError_t replace_one(const Geometry& g, const CgState& s, const float* 
                               const RhsSource& src, int u, int steps, int fixed, hipStream_t st) {
   hipLaunchKernelGGL((k_replace<BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, AX, (float*)s.Rv,
                      (float*)s.Dv, s.rr, s.thr, s.state, s.iters, s.xi, s.act, src.kind,
-                     (const float*)src.b, (const float*)src.B, src.K, src.key, src.probes, u,
+                     (const float*)src.b, (const float*)src.B, src.K, src.keyp, src.probes, u,
                      steps, fixed, g.T, g.C, g.R, g.Rp, g.D);
   return hipGetLastError();
 }

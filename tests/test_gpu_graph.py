@@ -59,3 +59,28 @@ def test_solve_graph_matches_direct():
         g = m.solve(alpha_dev(w.alpha0), B, cc, fixed_iters=30, coefs=True, graph=True)
         for k in ("X", "gamma", "xi"):
             assert torch.equal(d[k], g[k]), k
+
+
+@pytest.mark.parametrize("math", ["f64", "f32"])
+def test_em_iter_graph_replays_match_direct(math):
+    """cmtcs_em_iter recorded as one graph (E-step and M-step) against cmtcs_estep and
+    cmtcs_mstep launched step by step: three EM iterations with new probe keys, and between
+    replays a solve with another column count, which rewrites the cluster map and the tile
+    tables that the recording reads."""
+    w = synth.make("fp32", T=8)
+    m = device_model(w, math=math)
+    kw = dict(tol=w.cfg.tol, max_iters=w.cfg.max_iters, seed=1)
+    a_d = alpha_dev(w.alpha0)
+    a_g = a_d.clone()
+    lp = log_pi_dev(w.log_pi)
+    dt = torch.float64 if math == "f64" else torch.float32
+    B = torch.tensor(np.random.default_rng(2).standard_normal((w.T, 5, w.cfg.D)), dtype=dt,
+                     device=DEV)
+    out = None
+    for it in range(3):
+        d = m.estep(a_d, lp, w.cfg.K, em_iter=it, **kw)
+        m.mstep(d["mu"], d["s"], d["q"], a_d)
+        out = m.em_iter(a_g, lp, w.cfg.K, out=out, em_iter=it, graph=True, **kw)
+        _equal(d, out)
+        assert torch.equal(a_d, a_g)
+        m.solve(a_g, B, [0, 1, 1, 0, 1], max_iters=20)
