@@ -161,7 +161,10 @@ cmtcs_status_t cmtcs_destroy(cmtcs_handle_t h);
  * mix(seed + (em_iter+1) G), G = 0x9E3779B97F4A7C15, and mix is SplitMix64's finaliser
  * (Steele, Lea & Flood, OOPSLA 2014).  Probes are fresh per EM iteration, task and cluster
  * (Alg. 2).  A probe whose tridiagonal has a non-positive eigenvalue is left out of the
- * average of Eq. (logdet-est). */
+ * average of Eq. (logdet-est).  The tridiagonals are held in LDS up to a budget of 64 KB per
+ * block of four probes (runs of up to 4096 CG steps), otherwise in a workspace sized at create
+ * from max_iters; the environment variable CMTCS_SLQ_LDS_BYTES at create lowers that budget
+ * (0: always the workspace).  The results do not depend on it. */
 cmtcs_status_t cmtcs_estep(cmtcs_handle_t h, const float* alpha, const double* log_pi,
                            const cmtcs_opts_t* opts, float* mu, float* s, double* logdet,
                            double* ell, double* q, cmtcs_cg_stats_t* stats);

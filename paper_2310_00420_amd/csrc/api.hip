@@ -67,6 +67,7 @@ struct cmtcs_handle_s {
   int fwd_rows = 0, adj_rows = 0, cur_fwd_rows = -1, cur_adj_rows = -1, tuned_Rp = -1;
   bool autotune = true;
   void* slq_ws = nullptr;
+  long slq_lds = kSlqLdsBytes;   // LDS budget of the SLQ kernel (CMTCS_SLQ_LDS_BYTES)
   double *tau = nullptr, *rmin = nullptr,
          *rmax = nullptr, *slog = nullptr;
   uint8_t* ok = nullptr;
@@ -497,7 +498,7 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, mu, sd, st),
             "launch(estep_finalize)");
     HIP_TRY(launch_sum_log_alpha(C, D, alpha, slog, st), "launch(sum_log_alpha)");
-    HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, st),
+    HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, st),
             "launch(slq)");
     HIP_TRY(launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, st),
             "launch(resp)");
@@ -531,7 +532,7 @@ struct cmtcs_handle_s {
       e = launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, mu, sd, s);
     if (e == hipSuccess) e = launch_sum_log_alpha(C, D, alpha, slog, s);
     if (e == hipSuccess)
-      e = launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, s);
+      e = launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, s);
     if (e == hipSuccess)
       e = launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, s);
     if (e == hipSuccess) e = launch_mstep(T, C, D, mu, sd, q, o.alpha_max, alpha, s);
@@ -713,6 +714,10 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   }
   h->fwd_rows = cand[0][0];
   h->adj_rows = cand[1][0];
+  // CMTCS_SLQ_LDS_BYTES lowers the SLQ kernel's LDS budget (0: every tridiagonal in the HBM
+  // workspace, the form that runs past 4096 CG steps); read here, where the workspace is sized
+  if (const char* sl = std::getenv("CMTCS_SLQ_LDS_BYTES"))
+    h->slq_lds = std::max(0L, std::min(kSlqLdsBytes, std::atol(sl)));
   const char* at = std::getenv("CMTCS_AUTOTUNE");
   h->autotune = !(at != nullptr && at[0] == '0');
   // CMTCS_TILES="fwd,adj" pins both tile heights (each one of the supported candidates) and
@@ -754,7 +759,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->fwd_tiles, sizeof(int4) * fwd_max);
   A(&h->adj_tiles, sizeof(int4) * adj_max);
   // SLQ tridiagonals of runs too long for LDS
-  A(&h->slq_ws, std::max<size_t>(16, slq_workspace_bytes((long)P, (int)it)));
+  A(&h->slq_ws, std::max<size_t>(16, slq_workspace_bytes((long)P, (int)it, h->slq_lds)));
   A(&h->key_d, sizeof(uint64_t));
   A(&h->tau, sizeof(double) * P);
   A(&h->rmin, sizeof(double) * P);

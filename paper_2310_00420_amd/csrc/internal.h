@@ -255,12 +255,15 @@ hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iter
 
 // Launchers (k_slq.hip).
 // steps: the largest number of CG steps any probe took (bounds the tridiagonal size).
-// rows_ws: device workspace of slq_workspace_bytes(T*C*K, steps) bytes (none for runs whose
-// tridiagonals fit in LDS).
-size_t slq_workspace_bytes(long P, int steps);
+// The tridiagonals of up to four probes share a block's LDS while they fit in lds_bytes (at
+// most kSlqLdsBytes); longer runs keep them in rows_ws, a device workspace of
+// slq_workspace_bytes(T*C*K, steps, lds_bytes) bytes (none when they fit).  Both forms give
+// identical results.
+constexpr long kSlqLdsBytes = 64 * 1024;
+size_t slq_workspace_bytes(long P, int steps, long lds_bytes);
 hipError_t launch_slq(const Geometry& g, const CgState& s, int K, int steps, double pnorm2,
                       void* rows_ws, double* tau, uint8_t* ok, double* rmin, double* rmax,
-                      hipStream_t st);
+                      long lds_bytes, hipStream_t st);
 
 // Launchers (k_mixed.hip).  g16.w_off holds the offsets of the 16-bit W (rows padded to 32).
 // which: 1 = the Phi V16 product only, 2 = the Phi^T W16 product only.

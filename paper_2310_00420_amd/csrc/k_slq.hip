@@ -272,25 +272,24 @@ __global__ __launch_bounds__(256) void k_slq(const double* __restrict__ gam,
   }
 }
 
-// Four probes (waves) per block while their rows fit in 64 KB of LDS, fewer for long runs,
-// and the workspace beyond one wave's worth.
-constexpr long kSlqLdsBytes = 64 * 1024;
-static long slq_waves(long Um) {
-  return std::min<long>(4, kSlqLdsBytes / (long)(sizeof(TriRow) * Um));
+// Four probes (waves) per block while their rows fit in the LDS budget (kSlqLdsBytes unless
+// a smaller one is given), fewer for long runs, and the workspace beyond one wave's worth.
+static long slq_waves(long Um, long lds_bytes) {
+  return std::min<long>(4, lds_bytes / (long)(sizeof(TriRow) * Um));
 }
 
-size_t slq_workspace_bytes(long P, int steps) {
+size_t slq_workspace_bytes(long P, int steps, long lds_bytes) {
   const long Um = steps > 0 ? steps : 1;
-  return slq_waves(Um) >= 1 ? 0 : sizeof(TriRow) * (size_t)P * (size_t)Um;
+  return slq_waves(Um, lds_bytes) >= 1 ? 0 : sizeof(TriRow) * (size_t)P * (size_t)Um;
 }
 
 hipError_t launch_slq(const Geometry& g, const CgState& s, int K, int steps, double pnorm2,
                       void* rows_ws, double* tau, uint8_t* ok, double* rmin, double* rmax,
-                      hipStream_t st) {
+                      long lds_bytes, hipStream_t st) {
   const long P = (long)g.T * g.C * K;
   if (P == 0) return hipSuccess;
   const long Um = steps > 0 ? steps : 1;
-  const long W = slq_waves(Um);
+  const long W = slq_waves(Um, lds_bytes);
   if (W >= 1) {
     hipLaunchKernelGGL(k_slq<true>, dim3((unsigned)((P + W - 1) / W)), dim3((unsigned)(64 * W)),
                        (size_t)(sizeof(TriRow) * W * Um), st, s.gam, s.xi, s.iters, g.T, g.C, K,

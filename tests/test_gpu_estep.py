@@ -269,3 +269,23 @@ def test_em_iterations_f64():
     print("\nEM x3 tiny: 1/alpha rel %.2e, mu rel %.2e" % (e_alpha, e_mu))
     assert np.array_equal(out["assign"], ref["assign"])
     assert e_alpha <= TOL and e_mu <= TOL
+
+
+def test_slq_workspace_form_matches_lds_form(monkeypatch):
+    """The log-determinant kernel with the tridiagonals in the HBM workspace (the form used past
+    4096 CG steps, forced here with CMTCS_SLQ_LDS_BYTES=0) gives bit-identical log-determinants,
+    responsibilities and extreme Ritz values to the LDS form, on the same E-step."""
+    w = synth.make("fp32", T=8)
+    kw = dict(tol=w.cfg.tol, max_iters=w.cfg.max_iters, seed=1, em_iter=0, stats=True)
+    out = []
+    for budget in (None, "0"):
+        if budget is None:
+            monkeypatch.delenv("CMTCS_SLQ_LDS_BYTES", raising=False)
+        else:
+            monkeypatch.setenv("CMTCS_SLQ_LDS_BYTES", budget)
+        m = device_model(w)
+        out.append(m.estep(alpha_dev(w.alpha0), log_pi_dev(w.log_pi), w.cfg.K, **kw))
+        torch.cuda.synchronize()
+        m.close()
+    for k in ("logdet", "ell", "q", "ritz_min", "ritz_max", "iters"):
+        assert torch.equal(out[0][k], out[1][k]), k
