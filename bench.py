@@ -9,7 +9,8 @@ device memory before timing starts.
 Printed (one JSON line): CG right-hand-side iterations per second over the timed EM iterations
 (value), the EM iteration time (ms_per_step), the roofline position of the dominant kernel
 (timed with HIP events on the library's stream) and the FP64 oracle's rate on a bounded
-sample on the host CPU.
+sample on the host CPU.  The default FP64 run also times two EM iterations each of the plain
+FP32 form and the bf16 precision form (detail.forms, with the latter's speedup over FP32).
 """
 
 import argparse
@@ -43,10 +44,39 @@ def parse():
     ap.add_argument("--graph", action="store_true",
                     help="also time the same EM iterations as replays of the whole iteration "
                          "recorded as one HIP graph (reported under detail)")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the short FP32 and bf16-precision runs of the same workload that "
+                         "the default FP64 run reports under detail.forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 1 GiB device-to-device three times (a plain copy "
                          "kernel of known size, for scaling HBM byte counters)")
     return ap.parse_args()
+
+
+def time_form(Cmtcs, torch, w, dev, math, phi16, refine_every, warmup, steps):
+    """EM iterations of the same workload in another arithmetic form, on a handle of its own:
+    (ms per EM iteration, CG RHS-iterations per second)."""
+    cfg = w.cfg
+    m = Cmtcs(torch.from_numpy(w.Phi).to(dev), w.row_off, torch.from_numpy(w.y).to(dev), w.beta,
+              cfg.C, math=math, max_iters=cfg.max_iters, max_K=cfg.K, phi16=phi16)
+    alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
+    log_pi = torch.tensor(w.log_pi, device=dev)
+    kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1,
+              refine_every=refine_every if math == "mixed" else 0)
+    iters = []
+    for it in range(warmup + steps):
+        if it == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        out = m.estep(alpha, log_pi, cfg.K, em_iter=it, stats=True, **kw)
+        m.mstep(out["mu"], out["s"], out["q"], alpha)
+        if it >= warmup:
+            iters.append(out["iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rhs = sum(int(i.sum().item()) for i in iters)
+    m.close()
+    return 1e3 * dt / steps, rhs / dt
 
 
 def measured_traffic(kernel, workload, math):
@@ -215,6 +245,16 @@ def main():
         res["detail"]["graph"] = {
             "ms_per_step": 1e3 * gdt / a.steps, "value": rhs_iters / gdt,
             "same_q_as_direct": bool(torch.equal(gout["q"], out["q"]))}
+    if not a.no_forms and a.math == "f64" and a.config == "prec":
+        # the plain FP32 form and the precision form (bf16 Phi, FP32 true-residual replacement
+        # every refine_every steps) on the same workload: the latter's speedup over the former
+        f32_ms, f32_v = time_form(Cmtcs, torch, w, dev, "f32", "bf16", a.refine_every, 1, 2)
+        mx_ms, mx_v = time_form(Cmtcs, torch, w, dev, "mixed", "bf16", a.refine_every, 1, 2)
+        res["detail"]["forms"] = {
+            "f32": {"ms_per_step": round(f32_ms, 2), "value": f32_v},
+            "mixed_bf16": {"ms_per_step": round(mx_ms, 2), "value": mx_v,
+                           "refine_every": a.refine_every},
+            "speedup_mixed_over_f32": round(f32_ms / mx_ms, 3)}
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
