@@ -46,7 +46,7 @@ typedef enum {
   CMTCS_E_INVALID = 1,      /* bad argument: null pointer, bad size, inconsistent options   */
   CMTCS_E_HIP = 2,          /* a HIP runtime call failed (message names the call)           */
   CMTCS_E_NOMEM = 3,        /* workspace allocation failed in cmtcs_create                  */
-  CMTCS_E_UNSUPPORTED = 4   /* valid request outside what this build implements             */
+  CMTCS_E_UNSUPPORTED = 4   /* valid request outside what this library implements           */
 } cmtcs_status_t;
 
 /* Storage type of Phi in device memory. */

@@ -1,6 +1,6 @@
 // Mixed-precision operator (CMTCS_MATH_MIXED): Phi stored in 16 bits (bf16 or fp16), the CG
 // direction rounded to the same type, products on the 16x16x32 matrix cores with FP32
-// accumulation (the brief's precision form; the method itself is Alg. 1 on the operator of
+// accumulation (the precision form of the solver; the method itself is Alg. 1 on the operator of
 // Eq. (lin-sys)).
 //
 // Both products are laid out so that the contraction index is contiguous in memory for both
