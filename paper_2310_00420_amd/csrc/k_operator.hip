@@ -39,16 +39,14 @@ constexpr int kOpWaves = 4;
 // element type of the right-hand sides: measured best at 6 for FP64 (8 spills) and 4 for FP32.
 template <typename VT> constexpr int ring_depth() { return sizeof(VT) == 8 ? 6 : 4; }
 
-// The LDS-staged kernel is offered where it won in the CG loop: the FP64 forward product with
-// 16 rows per wave (two waves per SIMD).  With 32 FP64 rows it stays at one wave per SIMD and
-// loses to the register-pipelined kernel; in FP32 the register-pipelined 64-row tile is faster;
-// and an LDS-staged adjoint product, whose contraction over n is four times shorter, lost to
-// the register-pipelined one.
+// The LDS-staged kernels are offered in FP64 with 16 rows per wave (two waves per SIMD): the
+// forward one wins at the precision workload, the adjoint one at the ragged batching workload
+// (where many tasks are short and two waves per SIMD hide their pipeline starts), and the
+// register-pipelined 32-row adjoint elsewhere.  With 32 FP64 rows an LDS-staged kernel stays at
+// one wave per SIMD and loses; in FP32 the register-pipelined 64-row tile is faster.
 int op_row_candidates(bool f64, int kind, int* rows) {
   if (!f64) { rows[0] = 64; rows[1] = 32; return 2; }   // the first entry is the default
-  rows[0] = 32; rows[1] = 16;
-  if (kind == 1) return 2;
-  rows[2] = -16;
+  rows[0] = 32; rows[1] = 16; rows[2] = -16;
   return 3;
 }
 
@@ -577,6 +575,157 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
   phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
 }
 
+// LDS-staged adjoint product: as k_phi_v_lds for Phi^T W.  A block of four 16*RF-row waves
+// owns 64*RF consecutive rows d of one task and column group; the chunk of W_t (16 rows of n x
+// up to 144 columns) that all four multiply is staged once per block through an LDS double
+// buffer, and the Phi operand (four rows of n per lane and chunk, RF consecutive d each) is
+// prefetched per wave in a register ring, through a per-chunk descriptor as in k_phit_w.  The
+// k-steps, accumulation order and epilogue are those of k_phit_w, so the results are the same.
+template <typename VT, int RF>
+__global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void k_phit_w_lds(
+    const float* __restrict__ phi, const int64_t* __restrict__ row_off,
+    const int64_t* __restrict__ w_off, const int4* __restrict__ tiles, int ntiles,
+    const VT* __restrict__ W, const VT* __restrict__ V, VT* __restrict__ AV,
+    const float* __restrict__ alpha, const int* __restrict__ colc, double beta,
+    const int* __restrict__ act, int D, int Rp) {
+  typedef typename Mfma<VT>::acc_t acc_t;
+  typedef typename VecOf<VT, 4>::type vt4;
+  typedef typename VecOf<float, RF>::type frf;
+  typedef LdsChunk<VT> L;
+  typedef typename L::piece_t piece_t;
+  constexpr int KS = 4;
+  constexpr int KC = 4 * KS;   // rows of n per chunk (the 16-element columns of LdsChunk)
+  // a shallower Phi ring than k_phit_w's: the block shares the W chunk, and the registers
+  // saved keep two waves per SIMD without spilling
+  constexpr int kRingA = 4;
+  __shared__ VT lds[2][16 * kColGroup][L::kLd];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i16 = lane & 15, g4 = lane >> 4;
+  const int blk = uniform(xcd_block(blockIdx.x, gridDim.x));
+  if (blk >= ntiles) return;
+  const int4 tl = tiles[blk];
+  const int t = uniform(tl.x), cf0 = uniform(tl.z) * kColGroup;
+  const int d0 = uniform(tl.y) + uniform(wave) * 16 * RF;
+  if (act != nullptr && act[t] == 0) return;   // uniform over the block
+  const int64_t r0 = row_off[t];
+  const int nt = (int)(row_off[t + 1] - r0);
+  const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
+  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  const int nch = np / KC;
+
+  acc_t acc[RF][kColGroup];
+  auto zero_acc = [&]() __attribute__((always_inline)) {
+#pragma unroll
+    for (int f = 0; f < RF; ++f)
+#pragma unroll
+      for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
+  };
+  if (nch == 0) {   // empty task (uniform over the block): the product is zero
+    zero_acc();
+    phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
+    return;
+  }
+  // Phi as in k_phit_w: lanes past D read column 0 (outputs not stored); a chunk's descriptor
+  // starts at its first row and ends at row N_t, so rows past N_t read as zeros
+  const int dl = d0 + RF * i16;
+  const float* phit = phi + r0 * (int64_t)D;
+  // row KS*g4 + s of the chunk: one per-lane offset, the row step s*D as a scalar offset
+  const uint32_t aoff0 = (uint32_t)((KS * g4 * D + (dl < D ? dl : 0)) * 4);
+  // staging of W_t: piece p of the chunk is column p / kPieces, 16-byte piece p % kPieces;
+  // pieces past the group's columns are clamped onto the last one
+  const int npieces = 16 * ncf * L::kPieces;
+  const rsrc_t rw = make_rsrc(W + w_off[t], (uint32_t)((int64_t)Rp * np * sizeof(VT)));
+  uint32_t soff_w[L::kPerThread];
+  VT* sdst[L::kPerThread];   // in buffer 0; buffer 1 lies kBuf elements further
+  constexpr int kBuf = 16 * kColGroup * L::kLd;
+#pragma unroll
+  for (int i = 0; i < L::kPerThread; ++i) {
+    const int p = min((int)threadIdx.x + i * 64 * kOpWaves, npieces - 1);
+    const int col = p / L::kPieces, q = p % L::kPieces;
+    soff_w[i] = (uint32_t)(((cf0 * 16 + col) * np + q * L::kPer16) * sizeof(VT));
+    sdst[i] = &lds[0][col][q * L::kPer16];
+  }
+
+  frf a[kRingA][KS];
+  piece_t stg[L::kPerThread];
+  auto load_a = [&](frf (&x)[KS], int c) __attribute__((always_inline)) {
+    const int nb = uniform(min(c, nch - 1) * KC);
+    const rsrc_t ra = make_rsrc(phit + (int64_t)nb * D,
+                                (uint32_t)((int64_t)max(nt - nb, 0) * D * 4));
+#pragma unroll
+    for (int s = 0; s < KS; ++s) x[s] = buf_load<frf>(ra, aoff0, (uint32_t)(s * D * 4));
+  };
+  auto stage_load = [&](int c) __attribute__((always_inline)) {
+    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * KC * (int)sizeof(VT));
+#pragma unroll
+    for (int i = 0; i < L::kPerThread; ++i) stg[i] = buf_load<piece_t>(rw, soff_w[i], soff);
+  };
+  auto stage_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < L::kPerThread; ++i) *(piece_t*)(sdst[i] + buf * kBuf) = stg[i];
+  };
+  auto step = [&](const frf (&x)[KS], int buf, auto full, auto first) __attribute__((always_inline)) {
+    vt4 b[kColGroup];
+#pragma unroll
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (decltype(full)::value || cf < ncf) b[cf] = lds_frag<VT>(&lds[buf][cf * 16 + i16][4 * g4]);
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int cf = 0; cf < kColGroup; ++cf)
+        if (decltype(full)::value || cf < ncf)
+#pragma unroll
+          for (int f = 0; f < RF; ++f) {
+            float av;
+            if constexpr (RF == 1) av = x[s]; else av = x[s][f];
+            const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[f][cf];
+            acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], cin);
+          }
+  };
+  // per chunk as in k_phi_v_lds
+  auto chunk = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+    constexpr int i = decltype(ic)::value;
+    step(a[i], i & 1, full, first);
+    stage_store((i + 1) & 1);
+    stage_load(c + i + 2);
+    load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
+    __syncthreads();
+  };
+  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+    static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
+      chunk(c, ic, full,
+            std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
+    });
+  };
+  auto run = [&](auto full) __attribute__((always_inline)) {
+    stage_load(0);
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
+    stage_store(0);
+    stage_load(1);
+    __syncthreads();
+    int c = 0;
+    if (nch >= kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
+      ring(0, full, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
+    } else {
+      zero_acc();
+    }
+#pragma unroll
+    for (int i = 0; i + 1 < kRingA; ++i) {
+      if (c + i >= nch) break;
+      step(a[i], i & 1, full, std::false_type{});
+      stage_store((i + 1) & 1);
+      stage_load(c + i + 2);
+      __syncthreads();
+    }
+  };
+  if (ncf == kColGroup) run(std::true_type{});
+  else run(std::false_type{});
+
+  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
+}
+
 template <typename VT, int RF>
 static hipError_t phi_v_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                            const VT* V, VT* W, const int* act, hipStream_t st) {
@@ -600,6 +749,16 @@ static hipError_t phi_v_lds_rf(const Geometry& g, const float* phi, const int4* 
                                int ntiles, const VT* V, VT* W, const int* act, hipStream_t st) {
   hipLaunchKernelGGL((k_phi_v_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
                      g.row_off, g.w_off, tiles, ntiles, V, W, act, g.D, g.Rp);
+  return hipGetLastError();
+}
+
+template <typename VT, int RF>
+static hipError_t phit_w_lds_rf(const Geometry& g, const float* phi, const int4* tiles,
+                                int ntiles, const VT* W, const VT* V, VT* AV, const float* alpha,
+                                const int* colc, double beta, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL((k_phit_w_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
+                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
+                     g.Rp);
   return hipGetLastError();
 }
 
@@ -628,7 +787,13 @@ hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
                          double beta, const int* act, int rows, hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
-
+  if (rows < 0) {   // LDS-staged variant: one tile per block of four waves of -rows rows each
+    if constexpr (sizeof(VT) == 8) {
+      if (rows == -16)
+        return phit_w_lds_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+    }
+    return hipErrorInvalidValue;
+  }
   if constexpr (sizeof(VT) == 8) {
     if (rows == 16)
       return phit_w_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
