@@ -209,19 +209,6 @@ struct LdsChunk {
   typedef typename VecOf<VT, kPer16>::type piece_t;
 };
 
-// B fragment cf of the chunk in LDS buffer `buf` for lane (i16, g4): elements 4 g4 .. 4 g4 + 3
-// of column cf*16 + i16, read as 16-byte pieces (rows are 16-byte aligned, not 32).
-template <typename VT>
-__device__ inline typename VecOf<VT, 4>::type lds_frag(const VT* row) {
-  typedef typename VecOf<VT, 4>::type vt4;
-  if constexpr (sizeof(VT) == 8) {
-    const d2 x = *(const d2*)row, y = *(const d2*)(row + 2);
-    return vt4{x[0], x[1], y[0], y[1]};
-  } else {
-    return *(const vt4*)row;
-  }
-}
-
 // The 16-row FP64 LDS-staged tile fits two waves per SIMD without spilling once the
 // right-hand side no longer sits in registers (larger tiles do not).
 template <typename VT, int RF>
@@ -300,21 +287,30 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
 #pragma unroll
     for (int i = 0; i < L::kPerThread; ++i) *(piece_t*)sdst[buf][i] = stg[i];
   };
+  // the right-hand-side fragments are read in two halves (k-steps 0-1, then 2-3), which halves
+  // the registers they hold; the products run in the same order as in k_phi_v
+  typedef typename VecOf<VT, 2>::type vt2;
   auto step = [&](const f4 (&x)[RF], int buf, auto full, auto first) __attribute__((always_inline)) {
-    vt4 b[kColGroup];
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf)
-      if (decltype(full)::value || cf < ncf) b[cf] = lds_frag<VT>(&lds[buf][cf * 16 + i16][4 * g4]);
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int h = 0; h < 2; ++h) {
+      vt2 b[kColGroup];
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
+          b[cf] = *(const vt2*)&lds[buf][cf * 16 + i16][4 * g4 + 2 * h];
 #pragma unroll
-          for (int rf = 0; rf < RF; ++rf) {
-            const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[rf][cf];
-            acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], b[cf][s], cin);
-          }
+      for (int ss = 0; ss < 2; ++ss) {
+        const int s = 2 * h + ss;
+#pragma unroll
+        for (int cf = 0; cf < kColGroup; ++cf)
+          if (decltype(full)::value || cf < ncf)
+#pragma unroll
+            for (int rf = 0; rf < RF; ++rf) {
+              const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[rf][cf];
+              acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], b[cf][ss], cin);
+            }
+      }
+    }
   };
   // Per chunk c (buffer c & 1): multiply; store the staged chunk c+1 into the other buffer
   // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+2; then the
@@ -595,8 +591,8 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   typedef typename L::piece_t piece_t;
   constexpr int KS = 4;
   constexpr int KC = 4 * KS;   // rows of n per chunk (the 16-element columns of LdsChunk)
-  // a shallower Phi ring than k_phit_w's: the block shares the W chunk, and the registers
-  // saved keep two waves per SIMD without spilling
+  // a shallower Phi ring than k_phit_w's: with the block sharing the W chunk, four entries keep
+  // two waves per SIMD without spilling (six do not)
   constexpr int kRingA = 4;
   __shared__ VT lds[2][16 * kColGroup][L::kLd];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -664,23 +660,32 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
 #pragma unroll
     for (int i = 0; i < L::kPerThread; ++i) *(piece_t*)(sdst[i] + buf * kBuf) = stg[i];
   };
+  // the W fragments are read in two halves (k-steps 0-1, then 2-3), which halves the registers
+  // they hold; the products run in the same order as in k_phit_w
+  typedef typename VecOf<VT, 2>::type vt2;
   auto step = [&](const frf (&x)[KS], int buf, auto full, auto first) __attribute__((always_inline)) {
-    vt4 b[kColGroup];
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf)
-      if (decltype(full)::value || cf < ncf) b[cf] = lds_frag<VT>(&lds[buf][cf * 16 + i16][4 * g4]);
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int h = 0; h < 2; ++h) {
+      vt2 b[kColGroup];
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
+          b[cf] = *(const vt2*)&lds[buf][cf * 16 + i16][4 * g4 + 2 * h];
 #pragma unroll
-          for (int f = 0; f < RF; ++f) {
-            float av;
-            if constexpr (RF == 1) av = x[s]; else av = x[s][f];
-            const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[f][cf];
-            acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][s], cin);
-          }
+      for (int ss = 0; ss < 2; ++ss) {
+        const int s = 2 * h + ss;
+#pragma unroll
+        for (int cf = 0; cf < kColGroup; ++cf)
+          if (decltype(full)::value || cf < ncf)
+#pragma unroll
+            for (int f = 0; f < RF; ++f) {
+              float av;
+              if constexpr (RF == 1) av = x[s]; else av = x[s][f];
+              const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[f][cf];
+              acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][ss], cin);
+            }
+      }
+    }
   };
   // per chunk as in k_phi_v_lds
   auto chunk = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
