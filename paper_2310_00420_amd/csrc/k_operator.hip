@@ -39,13 +39,17 @@ constexpr int kOpWaves = 4;
 // element type of the right-hand sides: measured best at 6 for FP64 (8 spills) and 4 for FP32.
 template <typename VT> constexpr int ring_depth() { return sizeof(VT) == 8 ? 6 : 4; }
 
-// The LDS-staged kernels are offered in FP64 with 16 rows per wave (two waves per SIMD): the
-// forward one wins at the precision workload, the adjoint one at the ragged batching workload
-// (where many tasks are short and two waves per SIMD hide their pipeline starts), and the
-// register-pipelined 32-row adjoint elsewhere.  With 32 FP64 rows an LDS-staged kernel stays at
-// one wave per SIMD and loses; in FP32 the register-pipelined 64-row tile is faster.
+// The LDS-staged kernels (two waves per SIMD) are offered as 16-row FP64 tiles for both
+// products and as 32-row FP32 tiles for the adjoint product: at the precision and batching
+// workloads the autotuner keeps them.  With 32 FP64 rows an LDS-staged kernel stays at one wave
+// per SIMD and loses; for the FP32 forward product the register-pipelined 64-row tile is faster.
 int op_row_candidates(bool f64, int kind, int* rows) {
-  if (!f64) { rows[0] = 64; rows[1] = 32; return 2; }   // the first entry is the default
+  if (!f64) {   // the first entry is the default
+    rows[0] = 64; rows[1] = 32;
+    if (kind == 0) return 2;
+    rows[2] = -32;
+    return 3;
+  }
   rows[0] = 32; rows[1] = 16; rows[2] = -16;
   return 3;
 }
@@ -796,6 +800,9 @@ hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles,
     if constexpr (sizeof(VT) == 8) {
       if (rows == -16)
         return phit_w_lds_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+    } else {
+      if (rows == -32)
+        return phit_w_lds_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
     }
     return hipErrorInvalidValue;
   }
