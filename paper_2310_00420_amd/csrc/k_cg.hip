@@ -103,24 +103,41 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
   const int c = alpha != nullptr ? colc[idx] : -1;
   const float* al = alpha + (int64_t)(c >= 0 ? c : 0) * D;
   // all four vectors are loaded before the first reduction so that the r and x loads are in
-  // flight while d.Ad is summed
+  // flight while d.Ad is summed.  With an even number of elements per thread, each thread
+  // takes pairs of consecutive elements (one 2-wide load or store per vector and pair);
+  // element e of a thread is d = el(e).
+  // (not for 16 FP64 elements per thread, where the pairs cost more registers than there are)
+  constexpr int P = EPT % 2 == 0 && !(sizeof(VT) == 8 && EPT >= 16) ? 2 : 1;
+  typedef typename VecOf<VT, P>::type vp;
+  auto el = [&](int e) __attribute__((always_inline)) {
+    return P * ((int)threadIdx.x + (e / P) * BS) + e % P;
+  };
   VT dv[EPT], av[EPT], rv[EPT], xv[EPT];
   double pd = 0.0;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int d = threadIdx.x + e * BS;
-    if (d < D) {
-      dv[e] = Dv[base + d];
-      av[e] = AD[base + d];
-      rv[e] = Rv[base + d];
-      xv[e] = X[base + d];
-      if (alpha != nullptr) {
-        const VT a = c >= 0 ? (VT)al[d] : (VT)0;
-        av[e] = __builtin_fma((VT)beta, av[e], a * dv[e]);
+  for (int e0 = 0; e0 < EPT; e0 += P) {
+    const int d = el(e0);
+    if (d < D) {   // D is a multiple of 16: a pair is in range with its first element
+      vp x4[4];
+      x4[0] = *(const vp*)(Dv + base + d);
+      x4[1] = *(const vp*)(AD + base + d);
+      x4[2] = *(const vp*)(Rv + base + d);
+      x4[3] = *(const vp*)(X + base + d);
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        VT dq, aq, rq, xq;
+        if constexpr (P == 1) { dq = x4[0]; aq = x4[1]; rq = x4[2]; xq = x4[3]; }
+        else { dq = x4[0][q]; aq = x4[1][q]; rq = x4[2][q]; xq = x4[3][q]; }
+        if (alpha != nullptr) {
+          const VT a = c >= 0 ? (VT)al[d + q] : (VT)0;
+          aq = __builtin_fma((VT)beta, aq, a * dq);
+        }
+        dv[e0 + q] = dq; av[e0 + q] = aq; rv[e0 + q] = rq; xv[e0 + q] = xq;
+        pd += (double)dq * (double)aq;
       }
-      pd += (double)dv[e] * (double)av[e];
     } else {
-      dv[e] = 0; av[e] = 0; rv[e] = 0; xv[e] = 0;
+#pragma unroll
+      for (int q = 0; q < P; ++q) { dv[e0 + q] = 0; av[e0 + q] = 0; rv[e0 + q] = 0; xv[e0 + q] = 0; }
     }
   }
   const double dAd = block_sum<BS>(pd, sh);
@@ -131,23 +148,29 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
   const double g = rr_old / dAd;
   const VT gv = (VT)g;
   double pr = 0.0;
+  auto store = [&](VT* v, int e0, auto value) __attribute__((always_inline)) {
+    vp o;
+    if constexpr (P == 1) o = value(0);
+    else { o[0] = value(0); o[1] = value(1); }
+    *(vp*)(v + base + el(e0)) = o;
+  };
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int d = threadIdx.x + e * BS;
-    if (d < D) {
-      X[base + d] = xv[e] + gv * dv[e];
-      rv[e] = rv[e] - gv * av[e];
-      pr += (double)rv[e] * (double)rv[e];
+  for (int e0 = 0; e0 < EPT; e0 += P) {
+    if (el(e0) < D) {
+      store(X, e0, [&](int q) { return xv[e0 + q] + gv * dv[e0 + q]; });
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        rv[e0 + q] = rv[e0 + q] - gv * av[e0 + q];
+        pr += (double)rv[e0 + q] * (double)rv[e0 + q];
+      }
     }
   }
   if (split) {
     // first half of a residual-replacement step: x and the recursive r only; the true
     // residual, xi, d and the stop decision follow in k_replace
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int d = threadIdx.x + e * BS;
-      if (d < D) Rv[base + d] = rv[e];
-    }
+    for (int e0 = 0; e0 < EPT; e0 += P)
+      if (el(e0) < D) store(Rv, e0, [&](int q) { return rv[e0 + q]; });
     if (threadIdx.x == 0) gam[(int64_t)u * T * Rp + idx] = g;
     return;
   }
@@ -155,14 +178,17 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
   const double x_ = rrn / rr_old;
   const VT xv_ = (VT)x_;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int d = threadIdx.x + e * BS;
+  for (int e0 = 0; e0 < EPT; e0 += P) {
+    const int d = el(e0);
     if (d < D) {
-      const VT dn = rv[e] + xv_ * dv[e];
-      Rv[base + d] = rv[e];
-      Dv[base + d] = dn;
-      if (d16_kind == 1) ((__bf16*)d16)[idx * d16_ld + d] = (__bf16)(float)dn;
-      else if (d16_kind == 2) ((_Float16*)d16)[idx * d16_ld + d] = (_Float16)(float)dn;
+      store(Rv, e0, [&](int q) { return rv[e0 + q]; });
+      store(Dv, e0, [&](int q) { return rv[e0 + q] + xv_ * dv[e0 + q]; });
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const VT dn = rv[e0 + q] + xv_ * dv[e0 + q];
+        if (d16_kind == 1) ((__bf16*)d16)[idx * d16_ld + d + q] = (__bf16)(float)dn;
+        else if (d16_kind == 2) ((_Float16*)d16)[idx * d16_ld + d + q] = (_Float16)(float)dn;
+      }
     }
   }
   if (threadIdx.x == 0) {
