@@ -13,7 +13,7 @@ cg        conjugate gradient, Alg. 1, with the stopping policy the paper leaves 
 slq       Lanczos tridiagonal from CG coefficients and Gauss quadrature, Eqs. (tridiag),
           (hutch-trace), (logdet-est), Sec. 3.2
 cofem     CoFEM E-step / M-step / EM driver, Alg. 2 with Eqs. (estep), (mstep), (diag-est),
-          (lin-sys)
+          (lin-sys); optional learned cluster weights (the mixture-weight M-step, Sec. 2)
 dense_em  exact EM with explicit covariance (Eqs. (estep), (mstep)), the baseline CoFEM replaces;
           used only to pin the CoFEM oracle on tiny inputs
 adjoint   dense FP64 reference for x = A(alpha, Phi)^-1 b and its gradients (the differentiation

@@ -20,6 +20,10 @@ M-step (Eq. (mstep)) with diag Sigma replaced by s:
 The paper does not discuss guards; since s is a Monte Carlo estimate the denominator can be
 non-positive.  Reading used here: a cluster with sum_t q_tc < 1e-300 keeps its old alpha; otherwise
 alpha_cd = Nq_c / den_cd when den_cd > Nq_c / alpha_max, else alpha_max.
+Learned cluster weights (optional): the model of Sec. 2 takes pi as known but notes that it can
+be learned as in finite-mixture EM.  That M-step maximises sum_tc q_tc log pi_c over the simplex,
+whose maximiser is pi_c = (1/T) sum_t q_tc; ``update_log_pi`` returns log pi_c (-inf for a cluster
+with no mass).
 Final step (Alg. 2): a_t = argmax_c q_tc (lowest c on ties), return mu_{t, a_t} from the last
 E-step.
 """
@@ -124,6 +128,14 @@ def mstep(mu, s, q, alpha_old, alpha_max=1e10):
     return new
 
 
+def update_log_pi(q):
+    """log pi_c = log((1/T) sum_t q_tc): the mixture-weight M-step when pi is learned (Sec. 2,
+    model of Eq. (cmtcs)).  A cluster whose responsibilities are all zero gets -inf."""
+    q = np.asarray(q, np.float64)
+    with np.errstate(divide="ignore"):
+        return np.log(q.sum(axis=0) / q.shape[0])
+
+
 def log_likelihood(ell, log_pi, const):
     """L-hat(theta) = (1/T) sum_t log sum_c pi_c exp(ell_tc / 2 + const_t) (Sec. 2)."""
     z = 0.5 * np.asarray(ell) + np.asarray(log_pi)[None, :] + np.asarray(const)[:, None]
@@ -131,20 +143,25 @@ def log_likelihood(ell, log_pi, const):
     return float(np.mean(m[:, 0] + np.log(np.exp(z - m).sum(axis=1))))
 
 
-def fit(Phi, y, beta, alpha0, log_pi, K, policy, n_em, seed=1, probes_fn=None, alpha_max=1e10):
-    """Alg. 2 end to end.  ``probes_fn(it)`` may supply explicit probes per EM iteration."""
+def fit(Phi, y, beta, alpha0, log_pi, K, policy, n_em, seed=1, probes_fn=None, alpha_max=1e10,
+        learn_pi=False):
+    """Alg. 2 end to end.  ``probes_fn(it)`` may supply explicit probes per EM iteration.  With
+    ``learn_pi`` each M-step also replaces log_pi by ``update_log_pi(q)``."""
     b = rhs(Phi, y, beta)
     const = log_norm_const(Phi, y, beta)
     alpha = np.asarray(alpha0, np.float64).copy()
+    log_pi = np.asarray(log_pi, np.float64).copy()
     hist = []
     out = None
     for it in range(n_em):
         pr = None if probes_fn is None else probes_fn(it)
         out = estep(Phi, b, beta, alpha, log_pi, K, policy, seed=seed, it=it, probes=pr)
         hist.append(dict(L=log_likelihood(out["ell"], log_pi, const), alpha=alpha.copy(),
-                         q=out["q"].copy(), ell=out["ell"].copy()))
+                         q=out["q"].copy(), ell=out["ell"].copy(), log_pi=log_pi.copy()))
         alpha = mstep(out["mu"], out["s"], out["q"], alpha, alpha_max)
+        if learn_pi:
+            log_pi = update_log_pi(out["q"])
     assign = np.argmax(out["q"], axis=1)
     recon = np.stack([out["mu"][t, assign[t]] for t in range(len(Phi))])
     return dict(alpha=alpha, q=out["q"], assign=assign, recon=recon, mu=out["mu"], s=out["s"],
-                history=hist)
+                log_pi=log_pi, history=hist)

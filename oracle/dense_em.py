@@ -10,7 +10,7 @@ oracle (with Hadamard probes and converged CG the two must agree to rounding).
 import numpy as np
 from scipy.linalg import cho_factor, cho_solve
 
-from .cofem import responsibilities, log_likelihood, log_norm_const, rhs
+from .cofem import responsibilities, log_likelihood, log_norm_const, rhs, update_log_pi
 
 
 def estep(Phi, b, beta, alpha):
@@ -40,16 +40,21 @@ def mstep(mu, var, q, alpha_old=None):
     return Nq[:, None] / den
 
 
-def fit(Phi, y, beta, alpha0, log_pi, n_em):
+def fit(Phi, y, beta, alpha0, log_pi, n_em, learn_pi=False):
+    """Exact EM; with ``learn_pi`` the M-step also updates the cluster weights."""
     b = rhs(Phi, y, beta)
     const = log_norm_const(Phi, y, beta)
     alpha = np.asarray(alpha0, np.float64).copy()
+    log_pi = np.asarray(log_pi, np.float64).copy()
     hist = []
     for _ in range(n_em):
         e = estep(Phi, b, beta, alpha)
         q = responsibilities(e["ell"], log_pi)
         hist.append(dict(L=log_likelihood(e["ell"], log_pi, const), alpha=alpha.copy(), q=q,
-                         ell=e["ell"].copy()))
+                         ell=e["ell"].copy(), log_pi=log_pi.copy()))
         alpha = mstep(e["mu"], e["var"], q, alpha)
+        if learn_pi:
+            log_pi = update_log_pi(q)
     assign = np.argmax(q, axis=1)
-    return dict(alpha=alpha, q=q, assign=assign, mu=e["mu"], var=e["var"], history=hist)
+    return dict(alpha=alpha, q=q, assign=assign, mu=e["mu"], var=e["var"], log_pi=log_pi,
+                history=hist)
