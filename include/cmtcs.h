@@ -178,6 +178,16 @@ cmtcs_status_t cmtcs_estep(cmtcs_handle_t h, const float* alpha, const double* l
 cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, const double* q,
                            const cmtcs_opts_t* opts, float* alpha_inout);
 
+/* Learned cluster weights: the model of Eq. (cmtcs) takes pi as known, and Sec. 2 notes that it
+ * can instead be learned as in finite-mixture EM.  That M-step is
+ *   log_pi_c = log((1/T) sum_t q_tc),
+ * the maximiser of sum_tc q_tc log pi_c over the simplex; a cluster whose responsibilities are all
+ * zero gets -inf (its q stays 0 in later E-steps).  Sums are FP64 in task order.
+ *   q [T][C] double (from cmtcs_estep); log_pi [C] double, written (it may be the log_pi array
+ *   that cmtcs_estep and a recorded cmtcs_em_iter read: the next call sees the new weights).
+ * Errors: CMTCS_E_INVALID for a NULL handle or array. */
+cmtcs_status_t cmtcs_mstep_pi(cmtcs_handle_t h, const double* q, double* log_pi);
+
 /* One EM iteration of Alg. 2: cmtcs_estep from alpha_inout (no stats) followed by cmtcs_mstep
  * into alpha_inout, with the same arguments, outputs and results as those two calls.  With
  * opts->graph = 1 (MATH_F64 and MATH_F32) the device work of the whole iteration -- CG start,

@@ -146,6 +146,15 @@ class Cmtcs:
                                            _ptr(alpha)))
         return alpha
 
+    def mstep_pi(self, q, log_pi):
+        """Learned cluster weights (the mixture-weight M-step the model of Sec. 2 allows):
+        log_pi_c = log((1/T) sum_t q_tc), in place on ``log_pi``; returns ``log_pi``."""
+        self._check_stream()
+        _need(q, torch.float64, (self.T, self.C), "q")
+        _need(log_pi, torch.float64, (self.C,), "log_pi")
+        _lib.check(_lib.load().cmtcs_mstep_pi(self._h, _ptr(q), _ptr(log_pi)))
+        return log_pi
+
     def em_iter(self, alpha, log_pi, K, out=None, fixed_iters=0, tol=1e-6, max_iters=200,
                 seed=1, em_iter=0, probes=None, alpha_max=1e10, graph=False):
         """One EM iteration (Alg. 2): E-step from ``alpha``, then the M-step into ``alpha`` (in
@@ -255,13 +264,16 @@ class Cmtcs:
 
 
 def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
-        alpha_max=1e10, probes_fn=None, callback=None, graph=False):
+        alpha_max=1e10, probes_fn=None, callback=None, graph=False, learn_pi=False):
     """CoFEM (Alg. 2): n_em iterations of E-step + M-step from alpha0, then a_t = argmax_c q_tc
     (lowest c on ties) and mu_{t, a_t} from the last E-step.  With ``graph`` each iteration is
     one replay of the recorded EM iteration (cmtcs_em_iter), on output buffers reused from one
     iteration to the next; ``callback(it, alpha, out)`` then sees alpha as the E-step used it
-    (a copy) and the outputs before the next iteration overwrites them."""
+    (a copy) and the outputs before the next iteration overwrites them.  With ``learn_pi`` each
+    M-step also updates the cluster weights (cmtcs_mstep_pi) on a copy of ``log_pi``, returned
+    as "log_pi"."""
     alpha = alpha0.clone()
+    log_pi = log_pi.clone() if learn_pi else log_pi
     out = None
     for it in range(n_em):
         pr = None if probes_fn is None else probes_fn(it)
@@ -272,16 +284,20 @@ def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, 
                                 alpha_max=alpha_max, graph=True)
             if callback is not None:
                 callback(it, before, out)
+            if learn_pi:
+                model.mstep_pi(out["q"], log_pi)
             continue
         out = model.estep(alpha, log_pi, K, fixed_iters=fixed_iters, tol=tol,
                           max_iters=max_iters, seed=seed, em_iter=it, probes=pr, graph=graph)
         if callback is not None:
             callback(it, alpha, out)
         model.mstep(out["mu"], out["s"], out["q"], alpha, alpha_max=alpha_max)
+        if learn_pi:
+            model.mstep_pi(out["q"], log_pi)
     assign = out["q"].cpu().numpy().argmax(axis=1)        # host: first maximum = lowest c
     recon = torch.stack([out["mu"][t, int(assign[t])] for t in range(model.T)])
     return dict(alpha=alpha, q=out["q"], assign=assign, recon=recon, mu=out["mu"], s=out["s"],
-                ell=out["ell"], logdet=out["logdet"])
+                ell=out["ell"], logdet=out["logdet"], log_pi=log_pi)
 
 
 class CGSolve(torch.autograd.Function):

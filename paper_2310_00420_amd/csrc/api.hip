@@ -861,6 +861,13 @@ cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, co
   return CMTCS_OK;
 }
 
+cmtcs_status_t cmtcs_mstep_pi(cmtcs_handle_t h, const double* q, double* log_pi) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  if (!q || !log_pi) return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  HIP_TRY(launch_update_pi(h->T, h->C, q, log_pi, h->st), "launch(mstep_pi)");
+  return CMTCS_OK;
+}
+
 cmtcs_status_t cmtcs_em_iter(cmtcs_handle_t h, float* alpha_inout, const double* log_pi,
                              const cmtcs_opts_t* opts, float* mu, float* s, double* logdet,
                              double* ell, double* q) {

@@ -303,5 +303,6 @@ hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
                        hipStream_t st);
 hipError_t launch_mstep(int T, int C, int D, const float* mu, const float* sdiag,
                         const double* q, double alpha_max, float* alpha, hipStream_t st);
+hipError_t launch_update_pi(int T, int C, const double* q, double* log_pi, hipStream_t st);
 
 }  // namespace cmtcs

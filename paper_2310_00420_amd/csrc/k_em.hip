@@ -97,6 +97,18 @@ __global__ __launch_bounds__(256) void k_mstep(const float* __restrict__ mu,
   alpha[(int64_t)c * D + d] = den > nq / alpha_max ? (float)(nq / den) : (float)alpha_max;
 }
 
+// log pi_c = log((1/T) sum_t q_tc): the mixture-weight M-step when the cluster weights are
+// learned rather than given (Sec. 2).  One thread per cluster, sum in task order; a cluster with
+// no mass gets -inf.
+__global__ __launch_bounds__(64) void k_update_pi(const double* __restrict__ q,
+                                                  double* __restrict__ log_pi, int T, int C) {
+  const int c = blockIdx.x * 64 + threadIdx.x;
+  if (c >= C) return;
+  double nq = 0.0;
+  for (int t = 0; t < T; ++t) nq += q[(int64_t)t * C + c];
+  log_pi[c] = log(nq / (double)T);
+}
+
 template <typename VT>
 hipError_t launch_rhs(const Geometry& g, const float* phi, const float* y, double beta, VT* b,
                       hipStream_t st) {
@@ -124,6 +136,11 @@ hipError_t launch_mstep(int T, int C, int D, const float* mu, const float* sdiag
                         const double* q, double alpha_max, float* alpha, hipStream_t st) {
   hipLaunchKernelGGL(k_mstep, dim3((D + 255) / 256, C), dim3(256), 0, st, mu, sdiag, q,
                      alpha_max, alpha, T, C, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_pi(int T, int C, const double* q, double* log_pi, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_pi, dim3((C + 63) / 64), dim3(64), 0, st, q, log_pi, T, C);
   return hipGetLastError();
 }
 

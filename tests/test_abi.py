@@ -23,7 +23,7 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for n in ("cmtcs_create", "cmtcs_destroy", "cmtcs_estep", "cmtcs_mstep", "cmtcs_em_iter",
-              "cmtcs_solve", "cmtcs_apply", "cmtcs_profile", "cmtcs_rhs", "cmtcs_grad", "cmtcs_tiles", "cmtcs_last_error",
+              "cmtcs_mstep_pi", "cmtcs_solve", "cmtcs_apply", "cmtcs_profile", "cmtcs_rhs", "cmtcs_grad", "cmtcs_tiles", "cmtcs_last_error",
               "cmtcs_version"):
         assert n in names
 
@@ -85,6 +85,7 @@ def test_null_arguments():
     assert lib.cmtcs_estep(None, None, None, ctypes.byref(o), None, None, None, None, None,
                            None) == _lib.CMTCS_E_INVALID
     assert lib.cmtcs_mstep(None, None, None, None, ctypes.byref(o), None) == _lib.CMTCS_E_INVALID
+    assert lib.cmtcs_mstep_pi(None, None, None) == _lib.CMTCS_E_INVALID
     assert lib.cmtcs_em_iter(None, None, None, ctypes.byref(o), None, None, None, None,
                              None) == _lib.CMTCS_E_INVALID
     assert lib.cmtcs_solve(None, None, 1, None, None, None, None, None, ctypes.byref(o),
