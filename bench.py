@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the short FP32 and bf16-precision runs of the same workload that "
                          "the default FP64 run reports under detail.forms")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of timing, compare single-task, multi-task and clustered "
+                         "multi-task CS over the support-difference fraction f (T=8 in two "
+                         "groups of 4, N=D/4, 5%% sparsity, sigma=0.05, 50 EM iterations, K=15, "
+                         "U=50) and print the errors as one JSON line")
+    ap.add_argument("--sweep-d", type=int, default=512)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 1 GiB device-to-device three times (a plain copy "
                          "kernel of known size, for scaling HBM byte counters)")
@@ -125,8 +131,36 @@ def cpu_baseline(w, ntasks):
                       % (tasks, cfg.K, cfg.tol, cfg.max_iters, rhs_iters, dt)}
 
 
+def run_sweep(a):
+    import torch
+    import synth
+    from paper_2310_00420_amd.experiments import compare_methods
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    D = a.sweep_d
+    rows = []
+    for f in (0.0, 0.25, 0.5, 0.75, 1.0):
+        w = synth.make(synth.Config("support-sweep", T=8, C=2, D=D, N=D // 4,
+                                    sparsity=max(1, round(0.05 * D)), groups=2, sigma=0.05,
+                                    support_diff=f))
+        r = compare_methods(torch.from_numpy(w.Phi).to(dev), w.row_off,
+                            torch.from_numpy(w.y).to(dev), w.z, w.beta, C=2)
+        grouped = bool(len(set(r["assign"][:4])) == 1 and len(set(r["assign"][4:])) == 1)
+        rows.append(dict(f=f, single=r["single"], multi=r["multi"], clustered=r["clustered"],
+                         clusters_found=bool(grouped and r["assign"][0] != r["assign"][4]),
+                         seconds={k: round(v, 3) for k, v in r["seconds"].items()}))
+        print("f=%.2f single %.4f multi %.4f clustered %.4f" % (f, r["single"], r["multi"],
+              r["clustered"]), file=sys.stderr, flush=True)
+    print(json.dumps(dict(experiment="support-difference sweep", D=D, N=D // 4, T=8,
+                          data="synthetic Gaussian Phi", rows=rows)), flush=True)
+
+
 def main():
     a = parse()
+    if a.sweep:
+        run_sweep(a)
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (tasks would shard "
               "across GPUs with one all-reduce of the M-step sums per EM iteration; not built). "

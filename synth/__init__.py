@@ -11,6 +11,9 @@ Recipe (all seeds fixed and recorded):
   * Phi_t has i.i.d. N(0, 1/N_t) entries, stored float32, row-major [N_t][D]; all tasks are
     stacked in one [sum N_t][D] array with row offsets;
   * y_t = Phi_t z_t + sigma * N(0, I), stored float32;  beta = 1 / sigma^2;  pi uniform;
+  * with ``support_diff`` = f >= 0 (two groups; the first experiment of Sec. 4): the groups share
+    round((1 - f) * sparsity) support entries and draw the rest disjointly, so f = 0 gives one
+    common support and f = 1 disjoint ones;
   * alpha^0 ~ Uniform(0, 1) i.i.d. per (c, d) (Alg. 2, initialisation), rounded to float32 so that
     every consumer sees identical values; zeros are redrawn.
 """
@@ -38,6 +41,7 @@ class Config:
     max_iters: int = 200
     n_em: int = 1
     sigma: float = 0.01
+    support_diff: float = -1.0   # >= 0: fraction f of the support that differs between 2 groups
 
 
 CONFIGS = {
@@ -111,7 +115,15 @@ def make(cfg, data_seed=DATA_SEED, init_seed=INIT_SEED, **over):
     row_off[1:] = np.cumsum(Ns)
     per = -(-T // cfg.groups)
     labels = np.minimum(np.arange(T) // per, cfg.groups - 1)
-    supports = [rng.choice(D, size=cfg.sparsity, replace=False) for _ in range(cfg.groups)]
+    if cfg.support_diff < 0:
+        supports = [rng.choice(D, size=cfg.sparsity, replace=False) for _ in range(cfg.groups)]
+    else:
+        assert cfg.groups == 2 and 0.0 <= cfg.support_diff <= 1.0 and 2 * cfg.sparsity <= D
+        n_sh = int(round((1.0 - cfg.support_diff) * cfg.sparsity))
+        pick = rng.choice(D, size=2 * cfg.sparsity - n_sh, replace=False)
+        own = cfg.sparsity - n_sh
+        supports = [np.concatenate([pick[:n_sh], pick[n_sh:n_sh + own]]),
+                    np.concatenate([pick[:n_sh], pick[n_sh + own:]])]
     Phi = np.empty((int(row_off[-1]), D), np.float32)
     y = np.empty(int(row_off[-1]), np.float32)
     z = np.zeros((T, D))
