@@ -58,11 +58,16 @@ def responsibilities(ell, log_pi):
     return np.exp(z - lse)
 
 
-def estep(Phi, b, beta, alpha, log_pi, K, policy, seed=1, it=0, probes=None, t_sel=None):
+def estep(Phi, b, beta, alpha, log_pi, K, policy, seed=1, it=0, probes=None, t_sel=None,
+          common_probes=False):
     """One CoFEM E-step (Alg. 2, inner loop) for the tasks in ``t_sel`` (default: all).
 
     Phi: list of N_t x D arrays; b: list of D vectors (from ``rhs``); alpha: C x D; log_pi: C.
     probes: optional array [T][C][K][D] of +-1 overriding the SplitMix64 probes.
+    common_probes: with generated probes, every cluster c of a task uses the probes drawn for
+    c = 0 (common random numbers across clusters; a variance-reduction variant, not in the
+    paper: each (t, c) estimator keeps its distribution, and the Monte Carlo errors of ell_tc
+    and ell_tc' become correlated, so their difference, which decides q_t, varies less).
     Returns a dict of FP64 arrays indexed [task-in-selection][c](...).
     """
     alpha = np.asarray(alpha, np.float64)
@@ -71,6 +76,8 @@ def estep(Phi, b, beta, alpha, log_pi, K, policy, seed=1, it=0, probes=None, t_s
     tasks = list(range(T)) if t_sel is None else list(t_sel)
     if probes is None:
         P_all = _probes.rademacher(seed, it, T, C, K, D, t_sel=tasks)
+        if common_probes:
+            P_all = np.repeat(P_all[:, :1], C, axis=1)
     else:
         P_all = np.asarray(probes, np.float64)[tasks]
     R = C * (K + 1)
@@ -144,7 +151,7 @@ def log_likelihood(ell, log_pi, const):
 
 
 def fit(Phi, y, beta, alpha0, log_pi, K, policy, n_em, seed=1, probes_fn=None, alpha_max=1e10,
-        learn_pi=False):
+        learn_pi=False, common_probes=False):
     """Alg. 2 end to end.  ``probes_fn(it)`` may supply explicit probes per EM iteration.  With
     ``learn_pi`` each M-step also replaces log_pi by ``update_log_pi(q)``."""
     b = rhs(Phi, y, beta)
@@ -155,7 +162,8 @@ def fit(Phi, y, beta, alpha0, log_pi, K, policy, n_em, seed=1, probes_fn=None, a
     out = None
     for it in range(n_em):
         pr = None if probes_fn is None else probes_fn(it)
-        out = estep(Phi, b, beta, alpha, log_pi, K, policy, seed=seed, it=it, probes=pr)
+        out = estep(Phi, b, beta, alpha, log_pi, K, policy, seed=seed, it=it, probes=pr,
+                    common_probes=common_probes)
         hist.append(dict(L=log_likelihood(out["ell"], log_pi, const), alpha=alpha.copy(),
                          q=out["q"].copy(), ell=out["ell"].copy(), log_pi=log_pi.copy()))
         alpha = mstep(out["mu"], out["s"], out["q"], alpha, alpha_max)
