@@ -124,6 +124,13 @@ typedef struct {
                                have stopped is skipped inside the kernels, and kernel timing by
                                cmtcs_profile is not available); 0 = launch step by step.
                                cmtcs_em_iter: 1 = record the whole EM iteration (see there) */
+  int32_t common_probes;    /* generated probes only (0 or 1): 1 = every cluster c of task t
+                               uses the probes of cluster 0, p(t,c,k) = p(t,0,k) (common random
+                               numbers across clusters; not in the paper).  The estimators of
+                               each (t, c) are unchanged in distribution, and the Monte Carlo
+                               errors of ell_tc and ell_tc' become correlated, so that their
+                               difference, which decides q_t, varies less.  0 = independent
+                               probes per (t, c) as in Alg. 2 */
 } cmtcs_opts_t;
 
 /* Optional per-right-hand-side outputs, device pointers, each may be NULL.  For cmtcs_estep

@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
                 ("fixed_iters", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("refine_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("em_iter", ctypes.c_uint64), ("probes", ctypes.c_void_p),
-                ("alpha_max", ctypes.c_double), ("graph", ctypes.c_int32)]
+                ("alpha_max", ctypes.c_double), ("graph", ctypes.c_int32),
+                ("common_probes", ctypes.c_int32)]
 
 
 class CgStats(ctypes.Structure):

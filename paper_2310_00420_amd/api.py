@@ -97,15 +97,18 @@ class Cmtcs:
 
     @staticmethod
     def _opts(K=0, fixed_iters=0, tol=1e-6, max_iters=200, seed=1, em_iter=0, probes=None,
-              alpha_max=1e10, refine_every=0, graph=False):
+              alpha_max=1e10, refine_every=0, graph=False, common_probes=False):
         return _lib.Opts(K=K, max_iters=max_iters, fixed_iters=fixed_iters, tol=tol,
                          refine_every=refine_every, seed=seed, em_iter=em_iter,
                          probes=None if probes is None else probes.data_ptr(),
-                         alpha_max=alpha_max, graph=int(bool(graph)))
+                         alpha_max=alpha_max, graph=int(bool(graph)),
+                         common_probes=int(bool(common_probes)))
 
     def estep(self, alpha, log_pi, K, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
-              em_iter=0, probes=None, stats=False, refine_every=0, graph=False):
-        """One E-step (Alg. 2 inner loop).  Returns a dict of device tensors."""
+              em_iter=0, probes=None, stats=False, refine_every=0, graph=False,
+              common_probes=False):
+        """One E-step (Alg. 2 inner loop).  Returns a dict of device tensors.  With
+        ``common_probes`` every cluster of a task uses the same generated probes."""
         self._check_stream()
         T, C, D, dev = self.T, self.C, self.D, self.device
         _need(alpha, torch.float32, (C, D), "alpha")
@@ -126,7 +129,8 @@ class Cmtcs:
             st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(),
                               out["ritz_min"].data_ptr(), out["ritz_max"].data_ptr())
         o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
-                       em_iter=em_iter, probes=probes, refine_every=refine_every, graph=graph)
+                       em_iter=em_iter, probes=probes, refine_every=refine_every, graph=graph,
+                       common_probes=common_probes)
         _lib.check(_lib.load().cmtcs_estep(
             self._h, _ptr(alpha), _ptr(log_pi), ctypes.byref(o), _ptr(out["mu"]), _ptr(out["s"]),
             _ptr(out["logdet"]), _ptr(out["ell"]), _ptr(out["q"]),
@@ -156,7 +160,8 @@ class Cmtcs:
         return log_pi
 
     def em_iter(self, alpha, log_pi, K, out=None, fixed_iters=0, tol=1e-6, max_iters=200,
-                seed=1, em_iter=0, probes=None, alpha_max=1e10, graph=False):
+                seed=1, em_iter=0, probes=None, alpha_max=1e10, graph=False,
+                common_probes=False):
         """One EM iteration (Alg. 2): E-step from ``alpha``, then the M-step into ``alpha`` (in
         place).  ``out`` (the dict a previous call returned) is reused for the outputs, so that
         with ``graph`` the recorded iteration replays on the same buffers."""
@@ -172,7 +177,8 @@ class Cmtcs:
                        ell=torch.empty(T, C, dtype=torch.float64, device=dev),
                        q=torch.empty(T, C, dtype=torch.float64, device=dev))
         o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
-                       em_iter=em_iter, probes=probes, alpha_max=alpha_max, graph=graph)
+                       em_iter=em_iter, probes=probes, alpha_max=alpha_max, graph=graph,
+                       common_probes=common_probes)
         _lib.check(_lib.load().cmtcs_em_iter(
             self._h, _ptr(alpha), _ptr(log_pi), ctypes.byref(o), _ptr(out["mu"]), _ptr(out["s"]),
             _ptr(out["logdet"]), _ptr(out["ell"]), _ptr(out["q"])))
@@ -264,14 +270,15 @@ class Cmtcs:
 
 
 def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
-        alpha_max=1e10, probes_fn=None, callback=None, graph=False, learn_pi=False):
+        alpha_max=1e10, probes_fn=None, callback=None, graph=False, learn_pi=False,
+        common_probes=False):
     """CoFEM (Alg. 2): n_em iterations of E-step + M-step from alpha0, then a_t = argmax_c q_tc
     (lowest c on ties) and mu_{t, a_t} from the last E-step.  With ``graph`` each iteration is
     one replay of the recorded EM iteration (cmtcs_em_iter), on output buffers reused from one
     iteration to the next; ``callback(it, alpha, out)`` then sees alpha as the E-step used it
     (a copy) and the outputs before the next iteration overwrites them.  With ``learn_pi`` each
     M-step also updates the cluster weights (cmtcs_mstep_pi) on a copy of ``log_pi``, returned
-    as "log_pi"."""
+    as "log_pi".  ``common_probes``: every cluster of a task uses the same generated probes."""
     alpha = alpha0.clone()
     log_pi = log_pi.clone() if learn_pi else log_pi
     out = None
@@ -281,14 +288,15 @@ def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, 
             before = alpha.clone() if callback is not None else None
             out = model.em_iter(alpha, log_pi, K, out=out, fixed_iters=fixed_iters, tol=tol,
                                 max_iters=max_iters, seed=seed, em_iter=it, probes=pr,
-                                alpha_max=alpha_max, graph=True)
+                                alpha_max=alpha_max, graph=True, common_probes=common_probes)
             if callback is not None:
                 callback(it, before, out)
             if learn_pi:
                 model.mstep_pi(out["q"], log_pi)
             continue
         out = model.estep(alpha, log_pi, K, fixed_iters=fixed_iters, tol=tol,
-                          max_iters=max_iters, seed=seed, em_iter=it, probes=pr, graph=graph)
+                          max_iters=max_iters, seed=seed, em_iter=it, probes=pr, graph=graph,
+                          common_probes=common_probes)
         if callback is not None:
             callback(it, alpha, out)
         model.mstep(out["mu"], out["s"], out["q"], alpha, alpha_max=alpha_max)

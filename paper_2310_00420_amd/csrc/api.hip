@@ -100,14 +100,14 @@ struct cmtcs_handle_s {
   hipGraphExec_t em_exec = nullptr;
   struct EmKey {
     const void* p[8];   // alpha, log_pi, mu, s, logdet, ell, q, probes
-    int K, steps, fixed, R, Rp, fwd_rows, adj_rows;
+    int K, steps, fixed, R, Rp, fwd_rows, adj_rows, crn;
     double tol, alpha_max;
     bool operator==(const EmKey& o) const {
       for (int i = 0; i < 8; ++i)
         if (p[i] != o.p[i]) return false;
       return K == o.K && steps == o.steps && fixed == o.fixed && R == o.R && Rp == o.Rp &&
-             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows && tol == o.tol &&
-             alpha_max == o.alpha_max;
+             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows && crn == o.crn &&
+             tol == o.tol && alpha_max == o.alpha_max;
     }
   } em_key{};
   // probe key of the current E-step, read by the kernels that draw probes (a device word, so
@@ -446,6 +446,7 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
+    src.crn = 0;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, 0.0, 0, st), "launch(cg_init)");
     HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
                              fwd_rows, st), "launch(phi_v)");
@@ -491,11 +492,12 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_set_key(key_d, key, st), "launch(set_key)");
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.keyp = key_d; src.probes = o.probes;
+    src.crn = o.common_probes;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
     if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
     else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
     if (rs != CMTCS_OK) return rs;
-    HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, mu, sd, st),
+    HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, o.common_probes, mu, sd, st),
             "launch(estep_finalize)");
     HIP_TRY(launch_sum_log_alpha(C, D, alpha, slog, st), "launch(sum_log_alpha)");
     HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, st),
@@ -524,12 +526,13 @@ struct cmtcs_handle_s {
     const int K = o.K;
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.keyp = key_d; src.probes = o.probes;
+    src.crn = o.common_probes;
     // the cluster map is rewritten here (other calls on the handle reuse its buffer)
     hipError_t e = launch_fill_colc(colc, T, g.R, g.Rp, K, nullptr, s);
     if (e == hipSuccess) e = launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, s);
     if (e == hipSuccess) e = cg_steps_all<VT>(g, alpha, steps, fixed, s);
     if (e == hipSuccess)
-      e = launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, mu, sd, s);
+      e = launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, o.common_probes, mu, sd, s);
     if (e == hipSuccess) e = launch_sum_log_alpha(C, D, alpha, slog, s);
     if (e == hipSuccess)
       e = launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, s);
@@ -563,7 +566,7 @@ struct cmtcs_handle_s {
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_set_key(key_d, probe_key(o.seed, o.em_iter), st), "launch(set_key)");
     const EmKey key{{alpha, log_pi, mu, sd, logdet, ell, q, o.probes}, K, steps, fixed, R, Rp,
-                    fwd_rows, adj_rows, fixed ? 0.0 : o.tol, o.alpha_max};
+                    fwd_rows, adj_rows, o.common_probes, fixed ? 0.0 : o.tol, o.alpha_max};
     if (em_exec == nullptr || !(key == em_key)) {
       if (em_exec) { (void)hipGraphExecDestroy(em_exec); em_exec = nullptr; }
       if (em_graph) { (void)hipGraphDestroy(em_graph); em_graph = nullptr; }
@@ -604,6 +607,7 @@ struct cmtcs_handle_s {
     if (rs != CMTCS_OK) return rs;
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
+    src.crn = 0;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
     if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
     else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
@@ -629,6 +633,8 @@ cmtcs_status_t check_opts(const cmtcs_handle_s* h, const cmtcs_opts_t* o, bool n
       return fail(CMTCS_E_INVALID, "max_iters must be in 1..handle max_iters");
     if (!(o->tol >= 0.0)) return fail(CMTCS_E_INVALID, "tol must be >= 0");
   }
+  if (o->common_probes != 0 && o->common_probes != 1)
+    return fail(CMTCS_E_INVALID, "common_probes must be 0 or 1");
   if (need_K) {
     if (o->K < 1 || o->K > h->max_K) return fail(CMTCS_E_INVALID, "K must be in 1..max_K");
     if ((int64_t)h->C * (o->K + 1) > h->max_rhs)

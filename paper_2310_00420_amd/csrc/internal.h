@@ -220,6 +220,8 @@ struct RhsSource {
   const uint64_t* keyp;     // kind 0: device word holding the probe key (read by the kernels,
                             // so that a recorded launch sequence can be replayed with a new key)
   const int8_t* probes;     // kind 0: optional explicit probes [T][C][K][D]
+  int crn;                  // kind 0, generated probes: 1 = every cluster of a task uses the
+                            // probes of cluster 0 (common random numbers)
 };
 template <typename VT>
 hipError_t launch_cg_init(const Geometry& g, const CgState& s, const RhsSource& src,
@@ -233,7 +235,8 @@ hipError_t launch_cg_update(const Geometry& g, const CgState& s, int u, int step
 hipError_t launch_set_key(uint64_t* keyp, uint64_t key, hipStream_t st);
 template <typename VT>
 hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, const uint64_t* keyp,
-                                 const int8_t* probes, float* mu, float* sdiag, hipStream_t st);
+                                 const int8_t* probes, int crn, float* mu, float* sdiag,
+                                 hipStream_t st);
 template <typename VT>
 hipError_t launch_solve_output(const Geometry& g, const CgState& s, void* X, double* gam_out,
                                double* xi_out, int steps, int* iters_out, uint8_t* status_out,

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
                                                 const VT* __restrict__ B, int K,
                                                 const uint64_t* __restrict__ keyp,
                                                 const int8_t* __restrict__ probes, double tol2,
-                                                int C, int R, int Rp, int D) {
+                                                int C, int R, int Rp, int D, int crn) {
   __shared__ double sh[BS / 64];
   const int col = blockIdx.x;
   const int t = col / Rp, j = col % Rp;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
       if (k == 0) v = b[(int64_t)t * D + d];
       else if (probes != nullptr)
         v = (VT)probes[(((int64_t)t * C + c) * K + (k - 1)) * D + d];
-      else v = (VT)probe_entry(key, t, c, k - 1, d, C, K, D);
+      else v = (VT)probe_entry(key, t, crn ? 0 : c, k - 1, d, C, K, D);
     } else {
       v = B[((int64_t)t * R + j) * D + d];
     }
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_estep_finalize(const VT* __restrict__ X
                                                         const int8_t* __restrict__ probes,
                                                         float* __restrict__ mu,
                                                         float* __restrict__ sdiag, int C, int Rp,
-                                                        int D) {
+                                                        int D, int crn) {
   const int tc = blockIdx.x;
   const int t = tc / C, c = tc % C;
   const int d = blockIdx.y * 256 + threadIdx.x;
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_estep_finalize(const VT* __restrict__ X
   for (int k = 0; k < K; ++k) {
     const double p = probes != nullptr
                          ? (double)probes[(((int64_t)t * C + c) * K + k) * D + d]
-                         : probe_entry(key, t, c, k, d, C, K, D);
+                         : probe_entry(key, t, crn ? 0 : c, k, d, C, K, D);
     acc += p * (double)X[base + (int64_t)(k + 1) * D];
   }
   sdiag[(int64_t)tc * D + d] = (float)(acc / (double)K);
@@ -362,7 +362,7 @@ static hipError_t init_one(const Geometry& g, const CgState& s, const RhsSource&
   hipLaunchKernelGGL((k_cg_init<VT, BS, EPT>), dim3(g.T * g.Rp), dim3(BS), 0, st, (VT*)s.X,
                      (VT*)s.Rv, (VT*)s.Dv, s.rr, s.thr, s.state, s.iters, s.act, src.kind,
                      (const VT*)src.b, (const VT*)src.B, src.K, src.keyp, src.probes, tol2, g.C,
-                     g.R, g.Rp, g.D);
+                     g.R, g.Rp, g.D, src.crn);
   return hipGetLastError();
 }
 
@@ -420,9 +420,10 @@ hipError_t launch_set_key(uint64_t* keyp, uint64_t key, hipStream_t st) {
 
 template <typename VT>
 hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, const uint64_t* keyp,
-                                 const int8_t* probes, float* mu, float* sdiag, hipStream_t st) {
+                                 const int8_t* probes, int crn, float* mu, float* sdiag,
+                                 hipStream_t st) {
   hipLaunchKernelGGL((k_estep_finalize<VT>), dim3(g.T * g.C, (g.D + 255) / 256), dim3(256), 0,
-                     st, (const VT*)s.X, K, keyp, probes, mu, sdiag, g.C, g.Rp, g.D);
+                     st, (const VT*)s.X, K, keyp, probes, mu, sdiag, g.C, g.Rp, g.D, crn);
   return hipGetLastError();
 }
 
@@ -527,10 +528,12 @@ template hipError_t launch_cg_update<float>(const Geometry&, const CgState&, int
                                             hipStream_t);
 template hipError_t launch_estep_finalize<double>(const Geometry&, const CgState&, int,
                                                   const uint64_t*,
-                                                  const int8_t*, float*, float*, hipStream_t);
+                                                  const int8_t*, int, float*, float*,
+                                                  hipStream_t);
 template hipError_t launch_estep_finalize<float>(const Geometry&, const CgState&, int,
                                                  const uint64_t*,
-                                                 const int8_t*, float*, float*, hipStream_t);
+                                                 const int8_t*, int, float*, float*,
+                                                 hipStream_t);
 template hipError_t launch_solve_output<double>(const Geometry&, const CgState&, void*, double*,
                                                 double*, int, int*, uint8_t*, hipStream_t);
 template hipError_t launch_solve_output<float>(const Geometry&, const CgState&, void*, double*,

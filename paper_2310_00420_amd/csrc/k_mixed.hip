@@ -365,7 +365,7 @@ __global__ __launch_bounds__(BS) void k_replace(const float* __restrict__ AX,
                                                 const uint64_t* __restrict__ keyp,
                                                 const int8_t* __restrict__ probes, int u,
                                                 int steps, int fixed, int T, int C, int R,
-                                                int Rp, int D) {
+                                                int Rp, int D, int crn) {
   __shared__ double sh[BS / 64];
   const int t = blockIdx.x / R, j = blockIdx.x % R;
   const int64_t idx = (int64_t)t * Rp + j;
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(BS) void k_replace(const float* __restrict__ AX,
     if (kind == 0) {
       if (k == 0) v = b[(int64_t)t * D + d];
       else if (probes != nullptr) v = (float)probes[(((int64_t)t * C + c) * K + (k - 1)) * D + d];
-      else v = (float)probe_entry(key, t, c, k - 1, d, C, K, D);
+      else v = (float)probe_entry(key, t, crn ? 0 : c, k - 1, d, C, K, D);
     } else {
       v = B[((int64_t)t * R + j) * D + d];
     }
@@ -470,7 +470,7 @@ static hipError_t replace_one(const Geometry& g, const CgState& s, const float* 
   hipLaunchKernelGGL((k_replace<BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, AX, (float*)s.Rv,
                      (float*)s.Dv, s.rr, s.thr, s.state, s.iters, s.xi, s.act, src.kind,
                      (const float*)src.b, (const float*)src.B, src.K, src.keyp, src.probes, u,
-                     steps, fixed, g.T, g.C, g.R, g.Rp, g.D);
+                     steps, fixed, g.T, g.C, g.R, g.Rp, g.D, src.crn);
   return hipGetLastError();
 }
 
