@@ -167,7 +167,8 @@ cmtcs_status_t cmtcs_destroy(cmtcs_handle_t h);
  * SplitMix64 output mix(key + (i+1) G), i = ((t C + c) K + k) ceil(D/64) + m, the key is
  * mix(seed + (em_iter+1) G), G = 0x9E3779B97F4A7C15, and mix is SplitMix64's finaliser
  * (Steele, Lea & Flood, OOPSLA 2014).  Probes are fresh per EM iteration, task and cluster
- * (Alg. 2).  A probe whose tridiagonal has a non-positive eigenvalue is left out of the
+ * (Alg. 2); with opts->common_probes = 1, c is taken as 0 in i, so the clusters of a task
+ * share their probes.  A probe whose tridiagonal has a non-positive eigenvalue is left out of the
  * average of Eq. (logdet-est).  The tridiagonals are held in LDS up to a budget of 64 KB per
  * block of four probes (runs of up to 4096 CG steps), otherwise in a workspace sized at create
  * from max_iters; the environment variable CMTCS_SLQ_LDS_BYTES at create lowers that budget
@@ -200,9 +201,9 @@ cmtcs_status_t cmtcs_mstep_pi(cmtcs_handle_t h, const double* q, double* log_pi)
  * opts->graph = 1 (MATH_F64 and MATH_F32) the device work of the whole iteration -- CG start,
  * all CG steps (as in the graph mode of cmtcs_estep), diagonal estimate, log-determinant,
  * responsibilities and M-step -- is recorded once as a HIP graph and replayed by later calls
- * with the same shape (K), step policy, tol, alpha_max and the same eight array pointers
- * (alpha_inout, log_pi, mu, s, logdet, ell, q, opts->probes); opts->seed and opts->em_iter may
- * change between calls (the probe key is a device word set before each replay).  Other calls
+ * with the same shape (K), step policy, tol, alpha_max, common_probes and the same eight
+ * array pointers (alpha_inout, log_pi, mu, s, logdet, ell, q, opts->probes); opts->seed and
+ * opts->em_iter may change between calls (the probe key is a device word set before each replay).  Other calls
  * on the handle between iterations are allowed.  MATH_MIXED, or graph = 0, launches step by
  * step.  Errors as cmtcs_estep and cmtcs_mstep. */
 cmtcs_status_t cmtcs_em_iter(cmtcs_handle_t h, float* alpha_inout, const double* log_pi,
