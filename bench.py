@@ -146,12 +146,16 @@ def run_sweep(a):
                                     support_diff=f))
         r = compare_methods(torch.from_numpy(w.Phi).to(dev), w.row_off,
                             torch.from_numpy(w.y).to(dev), w.z, w.beta, C=2)
-        grouped = bool(len(set(r["assign"][:4])) == 1 and len(set(r["assign"][4:])) == 1)
+        def found(a):
+            return bool(len(set(a[:4])) == 1 and len(set(a[4:])) == 1 and a[0] != a[4])
         rows.append(dict(f=f, single=r["single"], multi=r["multi"], clustered=r["clustered"],
-                         clusters_found=bool(grouped and r["assign"][0] != r["assign"][4]),
+                         clusters_found=found(r["assign"]),
+                         clustered_common_probes=r["clustered_common"],
+                         clusters_found_common_probes=found(r["assign_common"]),
                          seconds={k: round(v, 3) for k, v in r["seconds"].items()}))
-        print("f=%.2f single %.4f multi %.4f clustered %.4f" % (f, r["single"], r["multi"],
-              r["clustered"]), file=sys.stderr, flush=True)
+        print("f=%.2f single %.4f multi %.4f clustered %.4f (common probes %.4f)"
+              % (f, r["single"], r["multi"], r["clustered"], r["clustered_common"]),
+              file=sys.stderr, flush=True)
     print(json.dumps(dict(experiment="support-difference sweep", D=D, N=D // 4, T=8,
                           data="synthetic Gaussian Phi", rows=rows)), flush=True)
 

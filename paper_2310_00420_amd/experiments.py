@@ -28,13 +28,13 @@ def _alpha0(C, D, seed):
     return a
 
 
-def _fit(phi, row_off, y, beta, C, alpha0, n_em, K, steps, seed, math):
+def _fit(phi, row_off, y, beta, C, alpha0, n_em, K, steps, seed, math, common_probes=False):
     dev = phi.device
     m = Cmtcs(phi, row_off, y, beta, C, math=math, max_iters=steps, max_K=K)
     try:
         log_pi = torch.full((C,), -np.log(C), dtype=torch.float64, device=dev)
         out = fit(m, torch.tensor(alpha0[:C], device=dev), log_pi, K, n_em, fixed_iters=steps,
-                  max_iters=steps, seed=seed)
+                  max_iters=steps, seed=seed, common_probes=common_probes)
         return out["recon"].double().cpu().numpy(), out["assign"]
     finally:
         m.close()
@@ -46,7 +46,9 @@ def compare_methods(phi, row_off, y, z, beta, C=2, n_em=50, K=15, steps=50, seed
 
     phi: [sum N_t][D] float32 device tensor; row_off: T+1 host prefix sums; y: [sum N_t] float32
     device tensor; z: [T][D] true signals (host).  Returns a dict with "single", "multi",
-    "clustered" errors, the clustered fit's assignments and the wall time of each method."""
+    "clustered" errors, the clustered fit's assignments and the wall time of each method, and
+    "clustered_common", "assign_common": the clustered fit with probes shared by the clusters
+    of a task (common random numbers; not in the paper)."""
     row_off = np.asarray(row_off, np.int64)
     T, D = len(row_off) - 1, int(phi.shape[1])
     z = np.asarray(z, np.float64)
@@ -74,5 +76,12 @@ def compare_methods(phi, row_off, y, z, beta, C=2, n_em=50, K=15, steps=50, seed
     times["clustered"] = time.perf_counter() - t0
     res["clustered"] = err(mu)
     res["assign"] = np.asarray(assign)
+
+    t0 = time.perf_counter()
+    mu, assign = _fit(phi, row_off, y, beta, C, a0, n_em, K, steps, seed, math,
+                      common_probes=True)
+    times["clustered_common"] = time.perf_counter() - t0
+    res["clustered_common"] = err(mu)
+    res["assign_common"] = np.asarray(assign)
     res["seconds"] = times
     return res
