@@ -166,7 +166,7 @@ def main():
         run_sweep(a)
         return
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (tasks would shard "
+        print("bench.py measures one GPU: the library has no multi-GPU path (tasks would shard "
               "across GPUs with one all-reduce of the M-step sums per EM iteration; not built). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
