@@ -102,3 +102,14 @@ def test_error_raises_from_python():
     with pytest.raises(_lib.CmtcsError) as e:
         _lib.check(_lib.load().cmtcs_create(None, None, None))
     assert e.value.code == _lib.CMTCS_E_INVALID
+
+
+def test_comparison_initial_alpha_follows_the_workload_recipe():
+    """The support-difference comparison draws alpha^0 as the synthetic workloads do (Alg. 2
+    initialisation, U(0, 1) per (c, d), float32), so its fits start where the oracle's would."""
+    import synth
+    from paper_2310_00420_amd.experiments import _alpha0
+    for C, D in ((1, 512), (2, 512), (3, 77)):
+        a = _alpha0(C, D, synth.INIT_SEED)
+        assert a.dtype == np.float32
+        assert np.array_equal(a.astype(np.float64), synth.draw_alpha0(C, D, synth.INIT_SEED))
