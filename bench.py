@@ -9,8 +9,16 @@ device memory before timing starts.
 Printed (one JSON line): CG right-hand-side iterations per second over the timed EM iterations
 (value), the EM iteration time (ms_per_step), the roofline position of the dominant kernel
 (timed with HIP events on the library's stream) and the FP64 oracle's rate on a bounded
-sample on the host CPU.  The default FP64 run also times two EM iterations each of the plain
-FP32 form and the bf16 precision form (detail.forms, with the latter's speedup over FP32).
+sample on the host CPU.  The default FP64 run also reports:
+  detail.async    the same EM iterations without kernel timing (the library's asynchronous
+                  path: every CG step enqueued, no host waits);
+  detail.forms    the plain FP32 form and the bf16 / fp16 precision forms on the same workload:
+                  speed, and the error of their first E-step against the FP64 one from the same
+                  alpha and probes, with whether it meets the form's bar (1e-5 FP32, 1e-3
+                  16-bit); a speedup over FP32 is quoted only for a form that meets its bar;
+  detail.forms_well_conditioned  the same at beta = 1, alpha in (1, 2), where the bars are met;
+  detail.configs  the plain FP32 configuration (T=32, D=1024) and the ragged batching
+                  configuration (T=256, D=2048) timed the same way.
 """
 
 import argparse
@@ -53,28 +61,39 @@ def parse():
                          "groups of 4, N=D/4, 5%% sparsity, sigma=0.05, 50 EM iterations, K=15, "
                          "U=50) and print the errors as one JSON line")
     ap.add_argument("--sweep-d", type=int, default=512)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the short runs of the plain-FP32 and batching configurations that "
+                         "the default FP64 run reports under detail.configs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 1 GiB device-to-device three times (a plain copy "
                          "kernel of known size, for scaling HBM byte counters)")
     return ap.parse_args()
 
 
-def time_form(Cmtcs, torch, w, dev, math, phi16, refine_every, warmup, steps):
+def host(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def time_form(Cmtcs, torch, w, dev, math, phi16, refine_every, warmup, steps, alpha0=None):
     """EM iterations of the same workload in another arithmetic form, on a handle of its own:
-    (ms per EM iteration, CG RHS-iterations per second)."""
+    (ms per EM iteration, CG RHS-iterations per second, host copy of the first E-step's
+    outputs -- EM iteration 0 from alpha0)."""
     cfg = w.cfg
     m = Cmtcs(torch.from_numpy(w.Phi).to(dev), w.row_off, torch.from_numpy(w.y).to(dev), w.beta,
               cfg.C, math=math, max_iters=cfg.max_iters, max_K=cfg.K, phi16=phi16)
-    alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
+    alpha = torch.tensor(w.alpha0 if alpha0 is None else alpha0, dtype=torch.float32, device=dev)
     log_pi = torch.tensor(w.log_pi, device=dev)
     kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1,
               refine_every=refine_every if math == "mixed" else 0)
     iters = []
+    first = None
     for it in range(warmup + steps):
         if it == warmup:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         out = m.estep(alpha, log_pi, cfg.K, em_iter=it, stats=True, **kw)
+        if it == 0:
+            first = host(out)
         m.mstep(out["mu"], out["s"], out["q"], alpha)
         if it >= warmup:
             iters.append(out["iters"])
@@ -82,7 +101,44 @@ def time_form(Cmtcs, torch, w, dev, math, phi16, refine_every, warmup, steps):
     dt = time.perf_counter() - t0
     rhs = sum(int(i.sum().item()) for i in iters)
     m.close()
-    return 1e3 * dt / steps, rhs / dt
+    return 1e3 * dt / steps, rhs / dt, first
+
+
+def form_error(got, ref, bar):
+    """Error of one E-step against another from the same alpha and probes: largest relative
+    vector-norm error of mu and s over (t, c), relative error of nu-bar and ell, agreement of
+    the argmax of q; and whether all four are within `bar` with the same argmax."""
+    def cols(a, r):
+        a = a.astype(np.float64); r = r.astype(np.float64)
+        return float(np.max(np.linalg.norm(a - r, axis=-1) / np.linalg.norm(r, axis=-1)))
+    e = {"mu": cols(got["mu"], ref["mu"]), "s": cols(got["s"], ref["s"]),
+         "nu": float(np.max(np.abs(got["logdet"] - ref["logdet"]) / np.abs(ref["logdet"]))),
+         "ell": float(np.max(np.abs(got["ell"] - ref["ell"])
+                             / np.maximum(np.abs(ref["ell"]), np.abs(ref["logdet"])))),
+         "argmax_agree": float(np.mean(got["q"].argmax(1) == ref["q"].argmax(1)))}
+    e = {k: (round(v, 6) if k == "argmax_agree" else float("%.3g" % v)) for k, v in e.items()}
+    e["bar"] = bar
+    e["meets_bar"] = bool(all(e[k] <= bar for k in ("mu", "s", "nu", "ell"))
+                          and e["argmax_agree"] == 1.0)
+    return e
+
+
+def forms_block(Cmtcs, torch, w, dev, refine_every, ref_first, f64_ms, alpha0=None):
+    """FP32 and the two precision forms against the FP64 E-step `ref_first` (same alpha, same
+    probes); a form's speedup over FP32 is given only when both meet their bars."""
+    res = {"f64": {"ms_per_step": round(f64_ms, 2)}}
+    for name, math, kind, bar in (("f32", "f32", "bf16", 1e-5), ("mixed_bf16", "mixed", "bf16", 1e-3),
+                                  ("mixed_f16", "mixed", "f16", 1e-3)):
+        ms, v, first = time_form(Cmtcs, torch, w, dev, math, kind, refine_every, 1, 2, alpha0)
+        res[name] = {"ms_per_step": round(ms, 2), "value": v,
+                     "error_vs_f64": form_error(first, ref_first, bar)}
+        if math == "mixed":
+            res[name]["refine_every"] = refine_every
+    for name in ("mixed_bf16", "mixed_f16"):
+        if res[name]["error_vs_f64"]["meets_bar"] and res["f32"]["error_vs_f64"]["meets_bar"]:
+            res[name]["speedup_over_f32"] = round(res["f32"]["ms_per_step"]
+                                                  / res[name]["ms_per_step"], 3)
+    return res
 
 
 def measured_traffic(kernel, workload, math):
@@ -105,12 +161,23 @@ def cpu_baseline(w, ntasks):
     """The FP64 oracle on a bounded sample: `ntasks` tasks (spread over the true clusters), one
     full E-step with the workload's CG policy."""
     from oracle import cofem, cg as ocg
+    blas = "unknown BLAS"
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()
-                       if i.get("user_api") == "blas"] or [1])
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        threads = max([i.get("num_threads", 1) for i in info] or [1])
+        if info:
+            blas = "%s %s" % (info[0].get("internal_api", "?"), info[0].get("version", "?"))
     except Exception:
         threads = os.cpu_count()
+    cpu = "unknown CPU"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     cfg = w.cfg
     tasks = [int(v) for v in np.linspace(0, cfg.T - 1, ntasks).round()]
     pol = ocg.CGPolicy(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters)
@@ -126,9 +193,10 @@ def cpu_baseline(w, ntasks):
     rhs_iters = int(ref["iters"].sum())
     return {"value": rhs_iters / dt, "unit": "RHS-iters/s", "cores": int(threads),
             "kind": "oracle",
+            "cpu": cpu, "blas": blas,
             "sample": "tasks %s of the workload, one E-step (K=%d, tol %g, <=%d CG steps), "
-                      "%d RHS-iterations in %.1f s; FP64 numpy/OpenBLAS"
-                      % (tasks, cfg.K, cfg.tol, cfg.max_iters, rhs_iters, dt)}
+                      "%d RHS-iterations in %.1f s; FP64 numpy on %s, %d threads"
+                      % (tasks, cfg.K, cfg.tol, cfg.max_iters, rhs_iters, dt, blas, threads)}
 
 
 def run_sweep(a):
@@ -160,6 +228,111 @@ def run_sweep(a):
                           data="synthetic Gaussian Phi", rows=rows)), flush=True)
 
 
+def roofline(m, w, math, config, prof, iters):
+    """Roofline position of the dominant product over the profiled EM iterations (HIP-event
+    kernel time on the library's stream, algorithmic work of the RHS-iterations executed)."""
+    cfg = w.cfg
+    ns = np.diff(w.row_off).astype(np.float64)
+    name = max(("phi_v", "phit_w"), key=lambda k: prof[k][0])
+    tot_ms, launches = prof[name]
+    if math == "mixed":
+        # HBM-bound: algorithmic bytes = the 16-bit Phi stream plus one pass over the vectors,
+        # for every step each task is still active (task-steps = its longest column)
+        R = cfg.C * (cfg.K + 1)
+        task_steps = sum(i.max(dim=1).values.double().cpu().numpy() for i in iters)
+        if name == "phi_v":    # Phi16 N D, V16 R D, W16 R N (2-byte elements)
+            per_task = 2.0 * (ns * cfg.D + R * cfg.D + R * ns)
+        else:                  # PhiT16 D N, W16 R N, V and A V in FP32: 8 R D
+            per_task = 2.0 * (ns * cfg.D + R * ns) + 8.0 * R * cfg.D
+        nbytes = float((task_steps * per_task).sum())
+        achieved = nbytes / (tot_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_GBPS, 4), "traffic": None,
+                "kernel": name + "16", "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
+                "bytes_per_launch": nbytes / max(launches, 1)}
+    # algorithmic flops = 2 N_t D per RHS-iteration per product (rows weight ragged tasks)
+    row_iters = float(sum((i.double().sum(dim=1).cpu().numpy() * ns).sum() for i in iters))
+    flops = 2.0 * cfg.D * row_iters
+    achieved = flops / (tot_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[math]
+    trows = m.tiles()[0 if name == "phi_v" else 1]
+    vt = "double" if math == "f64" else "float"
+    kname = "k_%s%s<%s, %d>" % (name, "_lds" if trows < 0 else "", vt, abs(trows) // 16)
+    return {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(kname, config, math),
+            "kernel": kname, "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
+            "flop_per_launch": flops / max(launches, 1)}
+
+
+def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup, steps,
+                 unprofiled=False):
+    """Times `steps` EM iterations (E-step + M-step, K probes, the workload's CG policy) after
+    `warmup` untimed ones, with HIP-event kernel timing on the library's stream; optionally the
+    same iterations again without kernel timing.  Returns the measurements and the host copy of
+    the first E-step (EM iteration 0 from alpha^0)."""
+    cfg = w.cfg
+    m = Cmtcs(torch.from_numpy(w.Phi).to(dev), w.row_off, torch.from_numpy(w.y).to(dev), w.beta,
+              cfg.C, math=math, max_iters=cfg.max_iters, max_K=cfg.K, phi16=phi16)
+    alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
+    log_pi = torch.tensor(w.log_pi, device=dev)
+    kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1,
+              refine_every=refine_every if math == "mixed" else 0)
+    first = None
+
+    def em_iteration(it):
+        out = m.estep(alpha, log_pi, cfg.K, em_iter=it, stats=True, **kw)
+        m.mstep(out["mu"], out["s"], out["q"], alpha)
+        return out
+
+    for it in range(warmup):
+        out = em_iteration(it)
+        if it == 0:
+            first = host(out)
+    torch.cuda.synchronize()
+    m.profile(True)
+    iters = []
+    t0 = time.perf_counter()
+    for it in range(warmup, warmup + steps):
+        out = em_iteration(it)
+        iters.append(out["iters"])
+        if first is None:   # no warm-up: the first timed E-step is EM iteration 0
+            first = host(out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = m.profile(False)
+    rhs_iters = int(sum(int(i.sum().item()) for i in iters))
+    res = {"value": rhs_iters / dt, "ms_per_step": 1e3 * dt / steps,
+           "roofline": roofline(m, w, math, config, prof, iters),
+           "rhs_iters_per_em_iter": rhs_iters / steps,
+           "max_cg_steps": int(max(int(i.max().item()) for i in iters)),
+           "tile_rows": m.tiles(),
+           "kernel_ms_per_em_iter": {k: round(v[0] / steps, 3) for k, v in prof.items()},
+           "launches_per_em_iter": {k: v[1] / steps for k, v in prof.items()}}
+    if unprofiled:
+        # the same EM iterations from the same alpha^0, without kernel timing: every CG step is
+        # enqueued at once and the host never waits inside an E-step
+        alpha.copy_(torch.tensor(w.alpha0, dtype=torch.float32, device=dev))
+        for it in range(warmup):
+            em_iteration(it)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for it in range(warmup, warmup + steps):
+            out2 = em_iteration(it)
+        torch.cuda.synchronize()
+        adt = time.perf_counter() - t0
+        res["async"] = {"ms_per_step": 1e3 * adt / steps, "value": rhs_iters / adt,
+                        "same_q_as_profiled": bool(torch.equal(out2["q"], out["q"]))}
+    res["_first"] = first
+    res["_model"] = (m, alpha, log_pi)
+    return res
+
+
+def workload_name(cfg):
+    return ("CoFEM EM iteration (E-step + M-step), T=%d C=%d D=%d N=%s K=%d, CG tol %g, "
+            "<=%d steps" % (cfg.T, cfg.C, cfg.D, cfg.N, cfg.K, cfg.tol, cfg.max_iters))
+
+
 def main():
     a = parse()
     if a.sweep:
@@ -179,92 +352,30 @@ def main():
     w = synth.make(a.config)
     cfg = w.cfg
     rows = int(w.row_off[-1])
-    phi = torch.from_numpy(w.Phi).to(dev)
-    y = torch.from_numpy(w.y).to(dev)
-    m = Cmtcs(phi, w.row_off, y, w.beta, cfg.C, math=a.math, max_iters=cfg.max_iters,
-              max_K=cfg.K, phi16=a.phi16)
-    alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
-    log_pi = torch.tensor(w.log_pi, device=dev)
-    kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1,
-              refine_every=a.refine_every if a.math == "mixed" else 0)
-
-    def em_iteration(it):
-        out = m.estep(alpha, log_pi, cfg.K, em_iter=it, stats=True, **kw)
-        m.mstep(out["mu"], out["s"], out["q"], alpha)
-        return out
-
-    for it in range(a.warmup):
-        em_iteration(it)
-    torch.cuda.synchronize()
-    m.profile(True)
-    iters = []
-    t0 = time.perf_counter()
-    for it in range(a.warmup, a.warmup + a.steps):
-        out = em_iteration(it)
-        iters.append(out["iters"])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = m.profile(False)
-    rhs_iters = int(sum(int(i.sum().item()) for i in iters))
-    max_steps = int(max(int(i.max().item()) for i in iters))
-    # RHS-iterations weighted by the rows of their task (ragged N_t)
-    ns = np.diff(w.row_off).astype(np.float64)
-    row_iters = float(sum((i.double().sum(dim=1).cpu().numpy() * ns).sum() for i in iters))
-
-    # roofline of the dominant kernel
-    N = rows // cfg.T
-    name = max(("phi_v", "phit_w"), key=lambda k: prof[k][0])
-    tot_ms, launches = prof[name]
-    if a.math == "mixed":
-        # HBM-bound: algorithmic bytes = the 16-bit Phi stream plus one pass over the vectors,
-        # for every step each task is still active (task-steps = its longest column)
-        R = cfg.C * (cfg.K + 1)
-        task_steps = sum(i.max(dim=1).values.double().cpu().numpy() for i in iters)
-        if name == "phi_v":    # Phi16 N D, V16 R D, W16 R N (2-byte elements)
-            per_task = 2.0 * (ns * cfg.D + R * cfg.D + R * ns)
-        else:                  # PhiT16 D N, W16 R N, V and A V in FP32: 8 R D
-            per_task = 2.0 * (ns * cfg.D + R * ns) + 8.0 * R * cfg.D
-        nbytes = float((task_steps * per_task).sum())
-        achieved = nbytes / (tot_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_GBPS, 4), "traffic": None,
-                "kernel": name + "16", "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
-                "bytes_per_launch": nbytes / max(launches, 1)}
-    else:
-        # algorithmic flops = 2 N_t D per RHS-iteration per product
-        flops = 2.0 * cfg.D * row_iters
-        achieved = flops / (tot_ms * 1e-3) / 1e12
-        peak = PEAK_TFLOPS[a.math]
-        trows = m.tiles()[0 if name == "phi_v" else 1]
-        vt = "double" if a.math == "f64" else "float"
-        kname = "k_%s%s<%s, %d>" % (name, "_lds" if trows < 0 else "", vt, abs(trows) // 16)
-        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(kname, a.config, a.math),
-                "kernel": kname, "avg_launch_us": round(1e3 * tot_ms / max(launches, 1), 2),
-                "flop_per_launch": flops / max(launches, 1)}
+    main_run = a.math == "f64" and a.config == "prec"
+    r = run_workload(torch, Cmtcs, w, dev, a.config, a.math, a.phi16, a.refine_every, a.warmup,
+                     a.steps, unprofiled=main_run and not a.no_forms)
+    m, alpha, log_pi = r.pop("_model")
+    first = r.pop("_first")
     res = {
         "metric": "CG RHS-iters/sec + EM iter time, D=4096 T=64 C=4 K=32; MFMA/HBM roofline %",
-        "value": rhs_iters / dt, "unit": "RHS-iters/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps, "higher_is_better": True,
+        "value": r["value"], "unit": "RHS-iters/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": a.math if a.math != "mixed" else a.phi16 + "+f32",
         "data": "synthetic: Phi_t iid N(0,1/N) stored fp32, %d true clusters with %d-sparse "
                 "shared supports, sigma %g, seeds data %d / init %d / probes 1"
                 % (cfg.groups, cfg.sparsity, cfg.sigma, synth.DATA_SEED, synth.INIT_SEED),
-        "config": {"workload": "CoFEM EM iteration (E-step + M-step), T=%d C=%d D=%d N=%s K=%d, "
-                               "CG tol %g, <=%d steps" % (cfg.T, cfg.C, cfg.D, cfg.N, cfg.K,
-                                                          cfg.tol, cfg.max_iters),
+        "config": {"workload": workload_name(cfg),
                    "T": cfg.T, "C": cfg.C, "D": cfg.D, "N": cfg.N, "rows": rows, "K": cfg.K,
                    "math": a.math if a.math != "mixed" else
                    "mixed(%s, true residual every %d)" % (a.phi16, a.refine_every)},
-        "roofline": roof,
-        "detail": {"rhs_iters_per_em_iter": rhs_iters / a.steps, "max_cg_steps": max_steps,
-                   "tile_rows": m.tiles(),
-                   "kernel_ms_per_em_iter": {k: round(v[0] / a.steps, 3)
-                                             for k, v in prof.items()},
-                   "launches_per_em_iter": {k: v[1] / a.steps for k, v in prof.items()}},
+        "roofline": r["roofline"],
+        "detail": {k: r[k] for k in ("rhs_iters_per_em_iter", "max_cg_steps", "tile_rows",
+                                     "kernel_ms_per_em_iter", "launches_per_em_iter")},
     }
+    if "async" in r:
+        res["detail"]["async"] = r["async"]
     if a.graph and a.math != "mixed":
         # the same EM iterations, each one replay of the recorded iteration (cmtcs_em_iter):
         # bit-identical results, so the same RHS-iteration count
@@ -280,19 +391,33 @@ def main():
             gout = m.em_iter(alpha, log_pi, cfg.K, out=gout, em_iter=it, **gkw)
         torch.cuda.synchronize()
         gdt = time.perf_counter() - t0
-        res["detail"]["graph"] = {
-            "ms_per_step": 1e3 * gdt / a.steps, "value": rhs_iters / gdt,
-            "same_q_as_direct": bool(torch.equal(gout["q"], out["q"]))}
-    if not a.no_forms and a.math == "f64" and a.config == "prec":
-        # the plain FP32 form and the precision form (bf16 Phi, FP32 true-residual replacement
-        # every refine_every steps) on the same workload: the latter's speedup over the former
-        f32_ms, f32_v = time_form(Cmtcs, torch, w, dev, "f32", "bf16", a.refine_every, 1, 2)
-        mx_ms, mx_v = time_form(Cmtcs, torch, w, dev, "mixed", "bf16", a.refine_every, 1, 2)
-        res["detail"]["forms"] = {
-            "f32": {"ms_per_step": round(f32_ms, 2), "value": f32_v},
-            "mixed_bf16": {"ms_per_step": round(mx_ms, 2), "value": mx_v,
-                           "refine_every": a.refine_every},
-            "speedup_mixed_over_f32": round(f32_ms / mx_ms, 3)}
+        res["detail"]["graph"] = {"ms_per_step": 1e3 * gdt / a.steps,
+                                  "value": r["rhs_iters_per_em_iter"] * a.steps / gdt}
+    m.close()
+    if main_run and not a.no_forms:
+        res["detail"]["forms"] = forms_block(Cmtcs, torch, w, dev, a.refine_every, first,
+                                             r["ms_per_step"])
+        print("forms done", file=sys.stderr, flush=True)
+        # the same shape with beta = 1 and alpha in (1, 2), where every form can meet its bar
+        wc = synth.make(a.config, sigma=1.0)
+        rc = run_workload(torch, Cmtcs, wc, dev, a.config, "f64", a.phi16, a.refine_every, 1, 2)
+        rc.pop("_model")[0].close()
+        res["detail"]["forms_well_conditioned"] = {
+            "workload": "as above with beta = 1, alpha^0 + 1",
+            **forms_block(Cmtcs, torch, wc, dev, a.refine_every, rc.pop("_first"),
+                          rc["ms_per_step"], alpha0=wc.alpha0 + 1.0)}
+        print("well-conditioned forms done", file=sys.stderr, flush=True)
+    if main_run and not a.no_configs:
+        configs = {}
+        for name, math in (("fp32", "f32"), ("batch", "f32"), ("batch", "f64")):
+            wk = synth.make(name)
+            rk = run_workload(torch, Cmtcs, wk, dev, name, math, a.phi16, a.refine_every, 1, 2)
+            rk.pop("_model")[0].close()
+            rk.pop("_first")
+            configs["%s_%s" % (name, math)] = {"workload": workload_name(wk.cfg), "math": math,
+                                               **rk}
+            print("config %s %s done" % (name, math), file=sys.stderr, flush=True)
+        res["detail"]["configs"] = configs
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -303,7 +428,6 @@ def main():
         res["detail"]["copy_calibration_bytes"] = 4 << 28
     if not a.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, a.cpu_tasks)
-    m.close()
     print(json.dumps(res))
 
 

@@ -22,7 +22,12 @@
  *    dense, row-major, without padding, in the element type stated at each argument.
  *  - Work is enqueued on the stream given to cmtcs_create and is asynchronous: outputs are
  *    valid once that stream has been synchronised.  The library never allocates device memory
- *    after cmtcs_create returns.
+ *    after cmtcs_create returns.  A call does not wait for the stream, with two exceptions: the
+ *    first call with a new number of column slots per task (or after a change of tile shapes)
+ *    copies the tile tables and, unless the autotuner is off, times candidate kernels, and waits
+ *    for that; and cmtcs_profile reads its timings.  A CG loop always enqueues its whole step
+ *    budget (max_iters or fixed_iters steps): every kernel of a step whose right-hand sides
+ *    have all stopped returns at once on the device, so no host check is needed.
  *  - Every function returns a cmtcs_status_t; on anything but CMTCS_OK, cmtcs_last_error()
  *    returns a message for the calling thread.  Argument errors are detected on the host before
  *    any work is enqueued, and then no output is written.  No C++ exception crosses the ABI.
@@ -69,7 +74,12 @@ typedef enum { CMTCS_MATH_F64 = 0, CMTCS_MATH_F32 = 1, CMTCS_MATH_MIXED = 2 } cm
 enum {
   CMTCS_CG_CONVERGED = 0,   /* tolerance met, the fixed step count done, or r = 0 exactly   */
   CMTCS_CG_MAX_ITER = 1,    /* tolerance mode: max_iters steps without meeting tol          */
-  CMTCS_CG_BREAKDOWN = 2    /* d.Ad <= 0 or a non-finite scalar; the solve stopped before it */
+  CMTCS_CG_BREAKDOWN = 2,   /* d.Ad <= 0 or a non-finite scalar; the solve stopped before it */
+  CMTCS_CG_NONPOS_RITZ = 3  /* cmtcs_estep probe columns only: the probe's tridiagonal
+                               (Eq. (tridiag)) was not certified positive definite (or has
+                               non-finite entries, or the solve took no step), so the probe was
+                               left out of the average of Eq. (logdet-est); replaces the CG
+                               outcome of that column                                       */
 };
 
 /* Problem data: fixed for the lifetime of a handle.  The library reads phi and y in place (it
@@ -142,6 +152,9 @@ typedef struct {
   double* ritz_min;         /* cmtcs_estep only, [T][C][K]: smallest eigenvalue of the
                                probe's tridiagonal (Eq. (tridiag)); NaN if it took 0 steps  */
   double* ritz_max;         /* cmtcs_estep only, [T][C][K]: largest eigenvalue              */
+  int32_t* k_eff;           /* cmtcs_estep only, [T][C]: probes that entered nu-bar (K unless
+                               some were left out, see CMTCS_CG_NONPOS_RITZ); 0 makes nu-bar,
+                               ell and the q of that task NaN                              */
 } cmtcs_cg_stats_t;
 
 /* Creates a handle for one problem on `stream` (a hipStream_t; NULL = the null stream) and
@@ -181,7 +194,10 @@ cmtcs_status_t cmtcs_estep(cmtcs_handle_t h, const float* alpha, const double* l
  *   alpha_cd = Nq_c / den_cd,  Nq_c = sum_t q_tc,  den_cd = sum_t q_tc (mu_tcd^2 + s_tcd).
  * The paper states no guards; s is a Monte Carlo estimate, so den can be <= 0.  Applied here:
  * a cluster with Nq_c < 1e-300 keeps its alpha; otherwise alpha_cd = Nq_c / den_cd when
- * den_cd > Nq_c / alpha_max, else alpha_max.  Sums are FP64 in task order.
+ * den_cd > Nq_c / alpha_max, else alpha_max.  Sums are FP64 in task order.  A task whose q_tc
+ * is not finite (its E-step had K_eff = 0, see cmtcs_cg_stats_t) is left out of cluster c's
+ * sums, and an entry whose den_cd is not finite (a non-finite mu or s) keeps its alpha_cd, so
+ * that one failed task cannot overwrite the whole model.
  *   mu, s [T][C][D] float; q [T][C] double; alpha_inout [C][D] float, updated in place. */
 cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, const double* q,
                            const cmtcs_opts_t* opts, float* alpha_inout);
@@ -256,7 +272,9 @@ cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_t
 
 /* Kernel timing for measurement: while enabled, each CG step's two operator products and its
  * vector update are bracketed by HIP events on the handle's stream and their durations are
- * summed.  enable = 1 clears the sums and turns timing on; enable = 0 turns it off; any other
+ * summed.  While enabled, the step-by-step CG loop waits for the events every 8 steps and then
+ * also stops enqueueing steps once every right-hand side has stopped (the timings then cover
+ * the steps that did work).  enable = 1 clears the sums and turns timing on; enable = 0 turns it off; any other
  * value leaves the state unchanged.  When non-NULL, the HOST arrays receive the sums so far
  * (after the stream has drained): totals_ms[3] in milliseconds and counts[3] in launches, in
  * the order {Phi V product, Phi^T W product, CG update}. */

@@ -19,7 +19,9 @@ M-step (Eq. (mstep)) with diag Sigma replaced by s:
   alpha_cd = sum_t q_tc / sum_t q_tc (mu_tcd^2 + s_tcd).
 The paper does not discuss guards; since s is a Monte Carlo estimate the denominator can be
 non-positive.  Reading used here: a cluster with sum_t q_tc < 1e-300 keeps its old alpha; otherwise
-alpha_cd = Nq_c / den_cd when den_cd > Nq_c / alpha_max, else alpha_max.
+alpha_cd = Nq_c / den_cd when den_cd > Nq_c / alpha_max, else alpha_max.  Tasks whose q_tc is not
+finite are left out of cluster c's sums, and an entry whose den_cd is not finite keeps its old
+alpha_cd (a failed task must not overwrite the model).
 Learned cluster weights (optional): the model of Sec. 2 takes pi as known but notes that it can
 be learned as in finite-mixture EM.  That M-step maximises sum_tc q_tc log pi_c over the simplex,
 whose maximiser is pi_c = (1/T) sum_t q_tc; ``update_log_pi`` returns log pi_c (-inf for a cluster
@@ -124,14 +126,17 @@ def mstep(mu, s, q, alpha_old, alpha_max=1e10):
     """alpha update of Eq. (mstep) with the guards described in the module docstring."""
     mu = np.asarray(mu, np.float64); s = np.asarray(s, np.float64); q = np.asarray(q, np.float64)
     alpha_old = np.asarray(alpha_old, np.float64)
-    Nq = q.sum(axis=0)                                              # C
-    den = np.einsum("tc,tcd->cd", q, mu * mu + s)                   # C x D
     new = alpha_old.copy()
     for c in range(alpha_old.shape[0]):
-        if Nq[c] < 1e-300:
+        use = np.isfinite(q[:, c])                                  # tasks entering the sums
+        Nq = q[use, c].sum()
+        den = q[use, c] @ (mu[use, c] ** 2 + s[use, c])             # D
+        if Nq < 1e-300:
             continue
-        floor = Nq[c] / alpha_max
-        new[c] = np.where(den[c] > floor, Nq[c] / np.where(den[c] > floor, den[c], 1.0), alpha_max)
+        floor = Nq / alpha_max
+        with np.errstate(invalid="ignore"):
+            upd = np.where(den > floor, Nq / np.where(den > floor, den, 1.0), alpha_max)
+        new[c] = np.where(np.isfinite(den), upd, alpha_old[c])
     return new
 
 

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libcmtcs.so")
 CMTCS_OK, CMTCS_E_INVALID, CMTCS_E_HIP, CMTCS_E_NOMEM, CMTCS_E_UNSUPPORTED = range(5)
 CMTCS_F32, CMTCS_BF16, CMTCS_F16 = range(3)
 CMTCS_MATH_F64, CMTCS_MATH_F32, CMTCS_MATH_MIXED = range(3)
-CMTCS_CG_CONVERGED, CMTCS_CG_MAX_ITER, CMTCS_CG_BREAKDOWN = range(3)
+CMTCS_CG_CONVERGED, CMTCS_CG_MAX_ITER, CMTCS_CG_BREAKDOWN, CMTCS_CG_NONPOS_RITZ = range(4)
 
 STATUS_NAMES = {0: "CMTCS_OK", 1: "CMTCS_E_INVALID", 2: "CMTCS_E_HIP", 3: "CMTCS_E_NOMEM",
                 4: "CMTCS_E_UNSUPPORTED"}
@@ -40,7 +40,8 @@ class Opts(ctypes.Structure):
 
 class CgStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_void_p), ("status", ctypes.c_void_p),
-                ("ritz_min", ctypes.c_void_p), ("ritz_max", ctypes.c_void_p)]
+                ("ritz_min", ctypes.c_void_p), ("ritz_max", ctypes.c_void_p),
+                ("k_eff", ctypes.c_void_p)]
 
 
 _lib = None

@@ -126,8 +126,10 @@ class Cmtcs:
             out["status"] = torch.empty(T, R, dtype=torch.uint8, device=dev)
             out["ritz_min"] = torch.empty(T, C, K, dtype=torch.float64, device=dev)
             out["ritz_max"] = torch.empty(T, C, K, dtype=torch.float64, device=dev)
+            out["k_eff"] = torch.empty(T, C, dtype=torch.int32, device=dev)
             st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(),
-                              out["ritz_min"].data_ptr(), out["ritz_max"].data_ptr())
+                              out["ritz_min"].data_ptr(), out["ritz_max"].data_ptr(),
+                              out["k_eff"].data_ptr())
         o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
                        em_iter=em_iter, probes=probes, refine_every=refine_every, graph=graph,
                        common_probes=common_probes)
@@ -204,7 +206,7 @@ class Cmtcs:
         if stats:
             out["iters"] = torch.empty(T, R, dtype=torch.int32, device=self.device)
             out["status"] = torch.empty(T, R, dtype=torch.uint8, device=self.device)
-            st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(), None, None)
+            st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(), None, None, None)
         o = self._opts(fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, graph=graph)
         _lib.check(_lib.load().cmtcs_solve(
             self._h, _ptr(alpha), R, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(B),

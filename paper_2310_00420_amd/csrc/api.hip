@@ -34,8 +34,7 @@ cmtcs_status_t hip_fail(hipError_t e, const char* what) {
 
 int round16(int x) { return (x + 15) / 16 * 16; }
 
-// Steps between host checks of the per-step active counts (early exit of the host loop once
-// every right-hand side has stopped).
+// Profiled steps whose HIP events are harvested together (cmtcs_profile).
 constexpr int kCheckEvery = 8;
 
 }  // namespace
@@ -71,7 +70,8 @@ struct cmtcs_handle_s {
   double *tau = nullptr, *rmin = nullptr,
          *rmax = nullptr, *slog = nullptr;
   uint8_t* ok = nullptr;
-  int* act_host = nullptr;   // pinned
+  int* keff = nullptr;       // [T][C] probes that entered nu-bar
+  int* act_host = nullptr;   // pinned; read while profiling only
 
   // mixed precision (CMTCS_MATH_MIXED)
   void* phi16 = nullptr;                 // 16-bit copy of Phi, [rows][D]
@@ -353,7 +353,6 @@ struct cmtcs_handle_s {
     return prepare(g.Rp);
   }
 
-  // Runs CG steps until every right-hand side has stopped or `steps` steps are done.
   // 16-bit products of one step (MATH_MIXED); which = 1: Phi V16, 2: Phi^T W16 (+ beta and
   // alpha V when alpha is given; the CG loop passes none and the update adds them).
   hipError_t mixed_product(const Geometry& g16, const float* alpha, const int* act_u,
@@ -374,6 +373,8 @@ struct cmtcs_handle_s {
     return launch_round16<_Float16>((const float*)Dv, D, D16, ld16(D), rows, D, st);
   }
 
+  // Enqueues all `steps` CG steps without waiting: the kernels of a step return at once for
+  // tasks (products) and columns (update) that have stopped.
   template <typename VT>
   cmtcs_status_t run_cg(const Geometry& g, const float* alpha, int steps, int fixed,
                         const RhsSource& src, int refine_every) {
@@ -417,19 +418,24 @@ struct cmtcs_handle_s {
         HIP_TRY(launch_replace(g, s, (const float*)AD, src, u, steps, fixed, st),
                 "launch(replace)");
       }
-      if (e4) {
-        HIP_TRY(hipEventRecord(e4[3], st), "hipEventRecord");
-        if (++ev_pending == kCheckEvery) HIP_TRY(harvest(), "profile events");
-      }
       // the update wrote the 16-bit direction itself, except on replacement steps
       if (replace) HIP_TRY(round_direction(g), "launch(round16)");
-      if ((u + 1) % kCheckEvery == 0 && u + 1 < steps) {
-        HIP_TRY(hipMemcpyAsync(act_host, act + (size_t)(u + 1) * T, sizeof(int) * T,
-                               hipMemcpyDeviceToHost, st), "hipMemcpyAsync(active counts)");
-        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(active counts)");
-        bool any = false;
-        for (int t = 0; t < T; ++t) any = any || act_host[t] != 0;
-        if (!any) break;
+      if (e4) {
+        HIP_TRY(hipEventRecord(e4[3], st), "hipEventRecord");
+        if (++ev_pending == kCheckEvery) {
+          // while profiling, the host waits here for the timings anyway; it also reads the
+          // active counts and stops enqueueing once every column has stopped, so that the
+          // timings hold the steps that did work and not the trailing empty launches
+          HIP_TRY(harvest(), "profile events");
+          if (u + 1 < steps) {
+            HIP_TRY(hipMemcpyAsync(act_host, act + (size_t)(u + 1) * T, sizeof(int) * T,
+                                   hipMemcpyDeviceToHost, st), "hipMemcpyAsync(active counts)");
+            HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(active counts)");
+            bool any = false;
+            for (int t = 0; t < T; ++t) any = any || act_host[t] != 0;
+            if (!any) break;
+          }
+        }
       }
     }
     if (prof_on) HIP_TRY(harvest(), "profile events");
@@ -502,10 +508,12 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_sum_log_alpha(C, D, alpha, slog, st), "launch(sum_log_alpha)");
     HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, st),
             "launch(slq)");
-    HIP_TRY(launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, st),
+    HIP_TRY(launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q,
+                            keff, st),
             "launch(resp)");
     if (stats != nullptr) {
-      HIP_TRY(launch_stats_estep(g, cg(), stats->iters, stats->status, st), "launch(stats)");
+      HIP_TRY(launch_stats_estep(g, cg(), K, ok, keff, stats->iters, stats->status, stats->k_eff,
+                                 st), "launch(stats)");
       const size_t P = (size_t)T * C * K;
       if (stats->ritz_min != nullptr)
         HIP_TRY(hipMemcpyAsync(stats->ritz_min, rmin, sizeof(double) * P,
@@ -537,7 +545,8 @@ struct cmtcs_handle_s {
     if (e == hipSuccess)
       e = launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, s);
     if (e == hipSuccess)
-      e = launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, s);
+      e = launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, keff,
+                          s);
     if (e == hipSuccess) e = launch_mstep(T, C, D, mu, sd, q, o.alpha_max, alpha, s);
     return e;
   }
@@ -771,6 +780,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->rmin, sizeof(double) * P);
   A(&h->rmax, sizeof(double) * P);
   A(&h->ok, P);
+  A(&h->keff, sizeof(int) * T * C);
   A(&h->slog, sizeof(double) * C);
   if (h->math == CMTCS_MATH_MIXED) {
     size_t np32_sum = 0, f16_max = 0;

@@ -253,8 +253,12 @@ hipError_t launch_grads(const Geometry& g, int R, const VT* XL, const VT* W, con
                         const int* colc, double beta, double y_coef, float* dalpha,
                         float* dphi, int64_t rows, hipStream_t st);
 hipError_t launch_zero_i32(int* p, long n, hipStream_t st);
-hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iters_out,
-                              uint8_t* status_out, hipStream_t st);
+// Per-right-hand-side statistics of an E-step: iters and status ([T][R]; probe columns whose
+// tridiagonal was not certified positive definite, ok[p] = 0, get CMTCS_CG_NONPOS_RITZ) and the
+// number of probes K_eff of each (t, c) that entered nu ([T][C]).  Each output may be null.
+hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int K, const uint8_t* ok,
+                              const int* keff, int32_t* iters_out, uint8_t* status_out,
+                              int32_t* keff_out, hipStream_t st);
 
 // Launchers (k_slq.hip).
 // steps: the largest number of CG steps any probe took (bounds the tridiagonal size).
@@ -303,7 +307,7 @@ template <typename VT>
 hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
                        const double* tau, const uint8_t* ok, const double* slog,
                        const double* log_pi, double* logdet, double* ell, double* q,
-                       hipStream_t st);
+                       int* keff, hipStream_t st);
 hipError_t launch_mstep(int T, int C, int D, const float* mu, const float* sdiag,
                         const double* q, double alpha_max, float* alpha, hipStream_t st);
 hipError_t launch_update_pi(int T, int C, const double* q, double* log_pi, hipStream_t st);

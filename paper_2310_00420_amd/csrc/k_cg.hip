@@ -6,6 +6,8 @@
 // reductions of a CG step (d.Ad and the new r.r) finish inside the workgroup and the whole
 // vector update of Alg. 1 (gamma, x, r, xi, d) is a single kernel.  Scalars are FP64 and the
 // reduction order is fixed, so results are identical run to run.
+#include <algorithm>
+
 #include "internal.h"
 #include "../../include/cmtcs.h"
 
@@ -451,12 +453,38 @@ hipError_t launch_solve_output(const Geometry& g, const CgState& s, void* X, dou
   return e;
 }
 
-hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int32_t* iters_out,
-                              uint8_t* status_out, hipStream_t st) {
-  if (iters_out == nullptr && status_out == nullptr) return hipSuccess;
-  const int64_t total = (int64_t)g.T * g.R;
-  hipLaunchKernelGGL(k_stats_out, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                     s.iters, s.state, iters_out, status_out, g.T, g.R, g.Rp);
+// E-step statistics: k = j % (K+1) >= 1 marks probe columns, whose status becomes
+// CMTCS_CG_NONPOS_RITZ where the log-determinant kernel left the probe out (ok = 0).
+__global__ __launch_bounds__(256) void k_stats_estep(const int* __restrict__ iters,
+                                                     const uint8_t* __restrict__ state,
+                                                     const uint8_t* __restrict__ ok,
+                                                     const int* __restrict__ keff,
+                                                     int32_t* __restrict__ iout,
+                                                     uint8_t* __restrict__ sout,
+                                                     int32_t* __restrict__ kout, int T, int C,
+                                                     int K, int R, int Rp) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (kout != nullptr && i < (int64_t)T * C) kout[i] = keff[i];
+  if (i >= (int64_t)T * R) return;
+  const int t = (int)(i / R), j = (int)(i % R);
+  const int64_t idx = (int64_t)t * Rp + j;
+  if (iout != nullptr) iout[i] = iters[idx];
+  if (sout != nullptr) {
+    const int c = j / (K + 1), k = j % (K + 1);
+    uint8_t v = state[idx];
+    if (k > 0 && !ok[((int64_t)t * C + c) * K + (k - 1)]) v = CMTCS_CG_NONPOS_RITZ;
+    sout[i] = v;
+  }
+}
+
+hipError_t launch_stats_estep(const Geometry& g, const CgState& s, int K, const uint8_t* ok,
+                              const int* keff, int32_t* iters_out, uint8_t* status_out,
+                              int32_t* keff_out, hipStream_t st) {
+  if (iters_out == nullptr && status_out == nullptr && keff_out == nullptr) return hipSuccess;
+  const int64_t total = std::max<int64_t>((int64_t)g.T * g.R, (int64_t)g.T * g.C);
+  hipLaunchKernelGGL(k_stats_estep, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     s.iters, s.state, ok, keff, iters_out, status_out, keff_out, g.T, g.C, K,
+                     g.R, g.Rp);
   return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ __global__ __launch_bounds__(256) void k_resp(const VT* __restrict__ X, const VT
                                               const double* __restrict__ log_pi,
                                               double* __restrict__ logdet,
                                               double* __restrict__ ell, double* __restrict__ q,
-                                              int C, int K, int Rp, int D) {
+                                              int* __restrict__ keff_out, int C, int K, int Rp,
+                                              int D) {
   __shared__ double sh[4];
   const int t = blockIdx.x;
   const VT* bt = b + (int64_t)t * D;
@@ -60,6 +61,7 @@ __global__ __launch_bounds__(256) void k_resp(const VT* __restrict__ X, const VT
         if (ok[p]) { st += tau[p]; ++keff; }
       }
       const double nu = keff > 0 ? -st / (double)keff : NAN;
+      keff_out[(int64_t)t * C + c] = keff;
       logdet[(int64_t)t * C + c] = nu;
       ell[(int64_t)t * C + c] = nu + slog[c] + dot;
     }
@@ -78,6 +80,9 @@ __global__ __launch_bounds__(256) void k_resp(const VT* __restrict__ X, const VT
 }
 
 // alpha_cd = Nq_c / den_cd with the guards stated in the ABI header; one thread per (c, d).
+// A task whose q_tc is not finite (e.g. every probe of (t, c) excluded from nu, so that q_t is
+// NaN) is left out of cluster c's sums; a denominator that is still not finite (a non-finite mu
+// or s entry) keeps the old alpha_cd.
 __global__ __launch_bounds__(256) void k_mstep(const float* __restrict__ mu,
                                                const float* __restrict__ sdiag,
                                                const double* __restrict__ q, double alpha_max,
@@ -88,12 +93,13 @@ __global__ __launch_bounds__(256) void k_mstep(const float* __restrict__ mu,
   double nq = 0.0, den = 0.0;
   for (int t = 0; t < T; ++t) {
     const double w = q[(int64_t)t * C + c];
+    if (!isfinite(w)) continue;
     const int64_t i = ((int64_t)t * C + c) * D + d;
     const double m = (double)mu[i];
     nq += w;
     den += w * (m * m + (double)sdiag[i]);
   }
-  if (nq < 1e-300) return;
+  if (nq < 1e-300 || !isfinite(den)) return;
   alpha[(int64_t)c * D + d] = den > nq / alpha_max ? (float)(nq / den) : (float)alpha_max;
 }
 
@@ -126,9 +132,9 @@ template <typename VT>
 hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
                        const double* tau, const uint8_t* ok, const double* slog,
                        const double* log_pi, double* logdet, double* ell, double* q,
-                       hipStream_t st) {
+                       int* keff, hipStream_t st) {
   hipLaunchKernelGGL((k_resp<VT>), dim3(g.T), dim3(256), 0, st, (const VT*)s.X, b, tau, ok, slog,
-                     log_pi, logdet, ell, q, g.C, K, g.Rp, g.D);
+                     log_pi, logdet, ell, q, keff, g.C, K, g.Rp, g.D);
   return hipGetLastError();
 }
 
@@ -150,9 +156,11 @@ template hipError_t launch_rhs<float>(const Geometry&, const float*, const float
                                       float*, hipStream_t);
 template hipError_t launch_resp<double>(const Geometry&, const CgState&, int, const double*,
                                         const double*, const uint8_t*, const double*,
-                                        const double*, double*, double*, double*, hipStream_t);
+                                        const double*, double*, double*, double*, int*,
+                                        hipStream_t);
 template hipError_t launch_resp<float>(const Geometry&, const CgState&, int, const float*,
                                        const double*, const uint8_t*, const double*,
-                                       const double*, double*, double*, double*, hipStream_t);
+                                       const double*, double*, double*, double*, int*,
+                                       hipStream_t);
 
 }  // namespace cmtcs

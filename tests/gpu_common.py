@@ -43,14 +43,22 @@ def rel_max(a, b):
 
 def estep_errors(got, ref):
     """Per-(t, c) errors of one E-step result against another (both as numpy dicts with the
-    oracle's keys mu, s, nu, ell, q): relative vector norms for mu and s, relative values for
-    nu, and for ell relative to max(|ell|, |nu|) (ell itself can be ~0, e.g. for a task without
+    oracle's keys mu, s, nu, ell, q): relative vector norms for mu and s, and their largest
+    entry error relative to the largest entry (mu_inf, s_inf), relative values for nu, and for
+    ell relative to max(|ell|, |nu|) (ell itself can be ~0, e.g. for a task without
     measurements, where nu = -sum log alpha exactly)."""
     def cols(a, b):
         a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
         return np.linalg.norm(a - b, axis=-1) / np.maximum(np.linalg.norm(b, axis=-1), 1e-300)
+
+    def elems(a, b):
+        # largest entry error relative to the largest entry: a localised error (one wrong tile)
+        # is not diluted by the vector length as in the norm ratio
+        a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+        return np.max(np.abs(a - b), axis=-1) / np.maximum(np.max(np.abs(b), axis=-1), 1e-300)
     ell_scale = np.maximum(np.abs(ref["ell"]), np.abs(ref["nu"]))
     return dict(mu=cols(got["mu"], ref["mu"]), s=cols(got["s"], ref["s"]),
+                mu_inf=elems(got["mu"], ref["mu"]), s_inf=elems(got["s"], ref["s"]),
                 logdet=np.abs(got["nu"] - ref["nu"]) / np.abs(ref["nu"]),
                 ell=np.abs(got["ell"] - ref["ell"]) / ell_scale)
 
@@ -72,3 +80,10 @@ def compare_estep(gpu, ref, tasks):
                argmax_equal=bool(np.all((g["q"][t].argmax(1) == ref["q"].argmax(1))[decided])),
                undecided_tasks=int((~decided).sum()), per=per)
     return out
+
+
+def kappa_hat(gpu, tasks):
+    """Largest ratio of the extreme Ritz values of the probe tridiagonals (stats ritz_min and
+    ritz_max) over the given tasks: a lower bound on the condition number of A."""
+    t = np.asarray(tasks)
+    return float(np.nanmax(gpu["ritz_max"].cpu().numpy()[t] / gpu["ritz_min"].cpu().numpy()[t]))

@@ -22,7 +22,9 @@ from scipy.linalg import eigvalsh_tridiagonal
 import synth
 from oracle import cofem, cg as ocg, probes as oprobes, slq
 from gpu_common import (DEV, device_model, alpha_dev, log_pi_dev, compare_estep, estep_errors,
-                        rel_cols)
+                        rel_cols, kappa_hat)
+from paper_2310_00420_amd._lib import CMTCS_CG_BREAKDOWN as BREAKDOWN, \
+    CMTCS_CG_NONPOS_RITZ as NONPOS_RITZ
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +68,10 @@ def _run(w, tasks, math="f64", probes=None, seed=1, it=0, alpha=None, K=None, sp
     ref = cofem.estep(w.phi_list(), b, w.beta, alpha, w.log_pi, K, _policy(cfg), seed=seed,
                       it=it, probes=probes, t_sel=tasks)
     err = compare_estep(g, ref, tasks)
+    err["kappa_hat"] = kappa_hat(g, tasks)
+    # every probe entered the log-determinant average (no non-positive Ritz value)
+    assert (g["k_eff"].cpu().numpy() == K).all()
+    assert not (g["status"].cpu().numpy() == NONPOS_RITZ).any()
     it_g = g["iters"].cpu().numpy()[np.asarray(tasks)]
     it_o = ref["iters"].reshape(len(tasks), -1)
     err["iters_maxdiff"] = int(np.max(np.abs(it_g - it_o)))
@@ -87,9 +93,12 @@ def _run(w, tasks, math="f64", probes=None, seed=1, it=0, alpha=None, K=None, sp
     return err, g, ref, sp
 
 
+METRICS = ("mu", "s", "mu_inf", "s_inf", "logdet", "ell")
+
+
 def _assert(err, spread):
     """Every (t, c) entry within max(1e-5, 4 x the oracle's self-spread of that entry)."""
-    for k in ("mu", "s", "logdet", "ell"):
+    for k in METRICS:
         assert err["bar_ratio"][k] <= 1.0, (k, err["bar_ratio"], err[k])
     assert err["argmax_equal"], err
 
@@ -289,3 +298,127 @@ def test_slq_workspace_form_matches_lds_form(monkeypatch):
         m.close()
     for k in ("logdet", "ell", "q", "ritz_min", "ritz_max", "iters"):
         assert torch.equal(out[0][k], out[1][k]), k
+
+
+# ------------------------------------------------------------------------------------------
+# Fixed bars where the answer is unique: converged CG on well-conditioned systems.
+
+def _assert_fixed(err):
+    for k in METRICS:
+        assert err[k] <= TOL, (k, err[k])
+    assert err["argmax_equal"], err
+
+
+def _batch_geometry():
+    """The batching configuration's geometry (T=256, N_t ~ U{128..2048}, D=2048, C=8, K=32)
+    with beta = 1 and alpha in (1, 2): condition numbers ~10, so CG converges to tol 1e-10 and
+    the solutions are unique up to rounding."""
+    w = synth.make("batch", sigma=1.0, tol=1e-10, max_iters=400)
+    ns = np.diff(w.row_off)
+    order = np.argsort(ns, kind="stable")
+    tasks = sorted({int(order[0]), int(order[len(order) // 2]), int(order[-1])})
+    return w, tasks
+
+
+@pytest.mark.parametrize("math", ["f64", "f32"])
+def test_estep_batch_geometry_converged(math):
+    """All 67,584 right-hand sides of the ragged batching geometry in one solve, FP64 and FP32;
+    the oracle checks the smallest, the median and the largest task at the fixed 1e-5 bar, with
+    no allowance for the oracle's own spread (it is ~1e-12 here)."""
+    w, tasks = _batch_geometry()
+    err, g, ref, sp = _run(w, tasks, math=math, alpha=w.alpha0 + 1.0, spread=False)
+    print("N_t of the sampled tasks:", [int(n) for n in np.diff(w.row_off)[tasks]])
+    _assert_fixed(err)
+    assert (g["status"].cpu().numpy() == 0).all()
+
+
+def test_estep_f32_well_conditioned_fp32_shape():
+    """The plain FP32 path at the FP32 configuration's shape (T=32, C=4, D=1024, N=256, K=32)
+    with beta = 1 and alpha in (1, 2): every sampled task within the fixed 1e-5 bar."""
+    w = synth.make("fp32", sigma=1.0)
+    err, g, ref, sp = _run(w, [0, 9, 18, 31], math="f32", alpha=w.alpha0 + 1.0, spread=False)
+    _assert_fixed(err)
+
+
+# ------------------------------------------------------------------------------------------
+# The plain FP32 path at the configurations' own conditioning (beta = 1e4, alpha ~ U(0, 1)).
+# A rounded operator departs from the FP64 result by ~kappa u (tests/test_precision_emulation.py
+# shows this for the arithmetic alone), so FP32 cannot meet 1e-5 there.  Checked here: the
+# device's departure is the one FP32 arithmetic itself causes -- within 5x of the CPU model of
+# the FP32 form (tests/emulate.py) on the same inputs and probes -- and the 1e-5 bar, which is
+# expected to fail (strict xfail).
+
+_F32_CACHE = {}
+
+
+def _f32_config(name):
+    if name in _F32_CACHE:
+        return _F32_CACHE[name]
+    import emulate
+    w = synth.make(name)
+    if name == "fp32":
+        tasks = [0, 9, 18, 31]
+    else:
+        ns = np.diff(w.row_off)
+        order = np.argsort(ns, kind="stable")
+        tasks = sorted([int(order[0]), int(order[1]), int(order[len(order) // 2])])
+    err, g, ref, sp = _run(w, tasks, math="f32", spread=False)
+    emu = emulate.errors(emulate.estep(w, tasks, w.alpha0, w.cfg.K, emulate.policy_of(w.cfg),
+                                       prod="f32", vec="f32"),
+                         dict(mu=ref["mu"], s=ref["s"], nu=ref["nu"]))
+    print("%s FP32: device mu %.2e s %.2e nu %.2e ell %.2e | CPU model of FP32 mu %.2e s %.2e "
+          "nu %.2e | kappa-hat %.2e" % (name, err["mu"], err["s"], err["logdet"], err["ell"],
+                                        emu["mu"], emu["s"], emu["nu"], err["kappa_hat"]))
+    _F32_CACHE[name] = (err, emu)
+    return err, emu
+
+
+@pytest.mark.parametrize("name", ["fp32", "batch"])
+def test_estep_f32_config_departure_is_fp32_rounding(name):
+    err, emu = _f32_config(name)
+    for k, ke in (("mu", "mu"), ("s", "s"), ("logdet", "nu")):
+        assert err[k] <= 5 * emu[ke] + TOL, (k, err[k], emu[ke])
+    assert err["argmax_equal"], err
+
+
+@pytest.mark.xfail(strict=True, reason="FP32 rounding at the configuration's conditioning "
+                   "(kappa ~1e8) moves mu by ~1e-1, far above 1e-5; see "
+                   "tests/test_precision_emulation.py")
+def test_estep_f32_fp32_config_meets_1e5():
+    err, emu = _f32_config("fp32")
+    _assert_fixed(err)
+
+
+# ------------------------------------------------------------------------------------------
+# The tiny configuration as specified for the plain method: 20 EM iterations of Alg. 2 against
+# exact dense EM.  Hadamard probes (K = D = 64 columns of a Sylvester-Hadamard matrix, passed
+# explicitly) make the diagonal and log-determinant estimators exact when CG converges, so
+# CoFEM's trajectory is dense EM's (Eqs. (estep), (mstep)).
+
+def test_em_trajectory_tiny_hadamard_equals_dense_em():
+    from oracle import dense_em
+    from paper_2310_00420_amd import fit
+    w = synth.make("tiny")
+    D, C, n_em = w.cfg.D, w.cfg.C, 20
+    H = synth.hadamard(6)
+    pr = torch.tensor(np.broadcast_to(H[None, None], (w.T, C, D, D)).astype(np.int8), device=DEV)
+    m = device_model(w, K=D, max_iters=10 * D)
+    hist = []
+
+    def keep(it, alpha, out):
+        hist.append((alpha.cpu().numpy().astype(np.float64), out["ell"].cpu().numpy(),
+                     out["q"].cpu().numpy()))
+
+    out = fit(m, alpha_dev(w.alpha0), log_pi_dev(w.log_pi), D, n_em, tol=1e-13,
+              max_iters=10 * D, probes_fn=lambda it: pr, callback=keep)
+    ref = dense_em.fit(w.phi_list(), w.y_list(), w.beta, w.alpha0, w.log_pi, n_em)
+    const = cofem.log_norm_const(w.phi_list(), w.y_list(), w.beta)
+    worst_a = worst_L = 0.0
+    for (a, ell, q), hr in zip(hist, ref["history"]):
+        L = cofem.log_likelihood(ell, w.log_pi, const)
+        worst_L = max(worst_L, abs(L - hr["L"]) / abs(hr["L"]))
+        worst_a = max(worst_a, np.max(np.abs(1 / a - 1 / hr["alpha"])) / np.max(1 / hr["alpha"]))
+    print("\n20 EM iterations, Hadamard probes vs dense EM: 1/alpha %.2e, L %.2e"
+          % (worst_a, worst_L))
+    assert worst_a <= 1e-6 and worst_L <= 1e-7
+    assert np.array_equal(out["assign"], ref["assign"])

@@ -14,8 +14,10 @@ the FP32 Phi) every m steps.
   iterate then drifts: the same happens in an FP64 numpy emulation of the method.)
 * At the configurations' beta = 1e4 the rounding error of a 16-bit product, ~beta ||Phi||^2
   u16 ~ 1e2, exceeds the small eigenvalues of A (alpha ~ U(0, 1)) by orders of magnitude, so no
-  refinement period restores 1e-3 there; that error is measured and printed here (and by the
-  benchmark), not asserted.
+  refinement period restores 1e-3 there (tests/test_precision_emulation.py shows it for the
+  arithmetic alone, and that FP32 products fail too).  The 1e-3 bar is asserted at the precision
+  configuration and expected to fail (strict xfail); the same shape with beta = 1 and alpha in
+  (1, 2) must meet it.
 """
 
 import numpy as np
@@ -93,25 +95,46 @@ def test_mixed_estep_well_conditioned(kind):
     assert err["argmax_equal"]
 
 
-@pytest.mark.parametrize("kind", ["bf16", "f16"])
-def test_mixed_estep_precision_config_error(kind):
-    """Precision configuration shape (T=64, C=4, D=4096, N=1024, K=32, tol 1e-6, <= 200 steps,
-    replacement every 10 steps): the whole batch on the device, errors against the oracle on two
-    tasks printed; asserted are only finite outputs and normalised responsibilities."""
-    w = synth.make("prec")
+def _prec_run(kind, w, alpha, tasks):
     m = _model(w, kind, w.cfg.K, w.cfg.max_iters)
-    g = m.estep(alpha_dev(w.alpha0), log_pi_dev(w.log_pi), w.cfg.K, tol=w.cfg.tol,
+    g = m.estep(alpha_dev(alpha), log_pi_dev(w.log_pi), w.cfg.K, tol=w.cfg.tol,
                 max_iters=w.cfg.max_iters, refine_every=10, stats=True)
     torch.cuda.synchronize()
     for k in ("mu", "s", "logdet", "ell", "q"):
         assert torch.isfinite(g[k]).all(), k
-    q = g["q"].cpu().numpy()
-    assert np.all(np.abs(q.sum(1) - 1) < 1e-12)
-    tasks = [0, 40]
     b = cofem.rhs(w.phi_list(), w.y_list(), w.beta)
-    ref = cofem.estep(w.phi_list(), b, w.beta, w.alpha0, w.log_pi, w.cfg.K,
+    ref = cofem.estep(w.phi_list(), b, w.beta, alpha, w.log_pi, w.cfg.K,
                       ocg.CGPolicy(tol=w.cfg.tol, max_iters=w.cfg.max_iters), seed=1, it=0,
                       t_sel=tasks)
     err = compare_estep(g, ref, tasks)
-    print("\n%s precision config vs FP64 oracle (tasks %s): %s" % (
-        kind, tasks, {k: v for k, v in err.items() if k != "per"}))
+    print("\n%s %s vs FP64 oracle (tasks %s): %s; iters max %d" % (
+        kind, w.cfg.name, tasks, {k: v for k, v in err.items() if k != "per"},
+        int(g["iters"].max())))
+    m.close()
+    return err
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_mixed_estep_precision_shape_well_conditioned(kind):
+    """The precision configuration's shape (T=64, C=4, D=4096, N=1024, K=32, tol 1e-6, <= 200
+    steps, replacement every 10 steps) with beta = 1 and alpha in (1, 2): the whole batch on
+    the device within 1e-3 of the oracle on two tasks, with the same argmax."""
+    w = synth.make("prec", sigma=1.0)
+    err = _prec_run(kind, w, w.alpha0 + 1.0, [0, 40])
+    for k in ("mu", "s", "logdet", "ell"):
+        assert err[k] <= 1e-3, (k, err[k])
+    assert err["argmax_equal"]
+
+
+@pytest.mark.xfail(strict=True, reason="at beta = 1e4 and alpha ~ U(0, 1) a 16-bit product's "
+                   "rounding exceeds the small eigenvalues of A; no form below FP64 holds mu "
+                   "to 1e-3 (tests/test_precision_emulation.py)")
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_mixed_estep_precision_config_meets_1e3(kind):
+    """The precision configuration itself (beta = 1e4, alpha^0 ~ U(0, 1)), the whole batch on
+    the device, the 1e-3 bar on two tasks."""
+    w = synth.make("prec")
+    err = _prec_run(kind, w, w.alpha0, [0, 40])
+    for k in ("mu", "s", "logdet", "ell"):
+        assert err[k] <= 1e-3, (k, err[k])
+    assert err["argmax_equal"]

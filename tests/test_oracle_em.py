@@ -164,6 +164,26 @@ def test_mstep_guards():
     assert np.array_equal(a[1], old[1])
 
 
+def test_mstep_skips_failed_tasks():
+    """A task whose q is NaN (all of its probes left out of nu-bar) drops out of the sums: the
+    result equals the M-step over the other tasks; a non-finite mu entry keeps its old alpha."""
+    rng = np.random.default_rng(3)
+    mu = rng.standard_normal((4, 2, 5)); s = rng.random((4, 2, 5))
+    q = rng.random((4, 2)); q /= q.sum(1, keepdims=True)
+    old = np.full((2, 5), 3.0)
+    bad = q.copy(); bad[2] = np.nan
+    a = cofem.mstep(mu, s, bad, old)
+    keep = [0, 1, 3]
+    ref = cofem.mstep(mu[keep], s[keep], q[keep], old)
+    assert np.array_equal(a, ref)
+    # closed form of the kept tasks: alpha_cd = sum_t q / sum_t q (mu^2 + s)
+    assert np.allclose(a, q[keep].sum(0)[:, None]
+                       / np.einsum("tc,tcd->cd", q[keep], mu[keep] ** 2 + s[keep]), rtol=1e-14)
+    mu2 = mu.copy(); mu2[1, 0, 3] = np.inf
+    a2 = cofem.mstep(mu2, s, q, old)
+    assert a2[0, 3] == 3.0 and np.array_equal(np.delete(a2[0], 3), np.delete(cofem.mstep(mu, s, q, old)[0], 3))
+
+
 def test_responsibilities_are_bayes_posterior(tiny):
     """q_tc = pi_c N(y_t; 0, S_c) / sum_c' pi_c' N(y_t; 0, S_c') with S_c the marginal covariance,
     and L-hat = mean_t log sum_c pi_c N(y_t; 0, S_c), evaluated with scipy's Gaussian density."""
