@@ -82,6 +82,18 @@ enum {
                                outcome of that column                                       */
 };
 
+/* Sensing operator of a problem.
+ *  CMTCS_OP_DENSE: Phi_t is a dense N_t x D float matrix (the configurations' Gaussian sensing).
+ *  CMTCS_OP_PARTIAL_FOURIER: Phi_t = Omega_t F, the sensing of the experiments of Sec. 4: F is
+ *      the unitary D x D DFT, F[k][d] = exp(-2 pi i k d / D) / sqrt(D), and Omega_t keeps the
+ *      N_t rows (frequencies) listed in freq.  The complex measurements enter the real model
+ *      stacked as [Re y_t; Im y_t] against [Re(Omega_t F); Im(Omega_t F)], with noise precision
+ *      beta on each part, so that A = beta Re(F^H Omega_t^T Omega_t F) + diag(alpha_c) and
+ *      b_t = beta Re(F^H Omega_t^T y_t); A is applied with FFTs in O(D log D) (Sec. 3.3), and
+ *      each right-hand side's whole CG solve runs in one workgroup.  Requires MATH_F64 and D a
+ *      power of two, 64..4096.  A frequency listed twice counts twice (its row appears twice). */
+typedef enum { CMTCS_OP_DENSE = 0, CMTCS_OP_PARTIAL_FOURIER = 1 } cmtcs_operator_t;
+
 /* Problem data: fixed for the lifetime of a handle.  The library reads phi and y in place (it
  * does not copy them), so they must stay valid and unchanged until destroy. */
 typedef struct {
@@ -96,11 +108,13 @@ typedef struct {
                                (slots = max_rhs rounded up to whole 16-column fragments, or to
                                whole 144-column groups past 144) must each stay below 4 GiB,
                                else CMTCS_E_UNSUPPORTED                                     */
-  const void* phi;          /* device [row_off[T]][D] float: the stacked Phi_t              */
+  const void* phi;          /* device [row_off[T]][D] float: the stacked Phi_t (OP_DENSE;
+                               ignored for OP_PARTIAL_FOURIER)                              */
   cmtcs_dtype_t phi_dtype;  /* F32 for MATH_F64 / MATH_F32; for MATH_MIXED the 16-bit type
                                (BF16 or F16) the library stores Phi in                      */
   const float* phi_f32;     /* reserved, must be NULL                                       */
-  const float* y;           /* device [row_off[T]] measurements, stacked like Phi           */
+  const float* y;           /* device measurements, stacked like Phi: [row_off[T]] (OP_DENSE)
+                               or [row_off[T]][2] (re, im) pairs (OP_PARTIAL_FOURIER)       */
   double beta;              /* noise precision, > 0                                         */
   cmtcs_math_t math;        /* arithmetic, see cmtcs_math_t                                 */
   int32_t max_rhs;          /* largest number of right-hand sides per task any later call
@@ -108,6 +122,10 @@ typedef struct {
                                cmtcs_solve                                                   */
   int32_t max_iters;        /* largest CG step count any later call uses (1..4096)          */
   int32_t max_K;            /* largest probe count any later cmtcs_estep uses (>= 0)        */
+  cmtcs_operator_t op;      /* sensing operator (zero: OP_DENSE)                            */
+  const int32_t* freq;      /* OP_PARTIAL_FOURIER: device [row_off[T]] selected frequencies
+                               of each task, each in 0..D-1 (checked at create:
+                               CMTCS_E_INVALID otherwise); OP_DENSE: ignored               */
 } cmtcs_problem_t;
 
 /* Options of one call.  CG stopping (the paper runs CG "until convergence" in Alg. 1 and for
@@ -159,7 +177,10 @@ typedef struct {
 
 /* Creates a handle for one problem on `stream` (a hipStream_t; NULL = the null stream) and
  * the current HIP device.  Allocates the whole workspace for the sizes in *prob and computes
- * b_t = beta Phi_t^T y_t once (Eq. (lin-sys)), since b does not depend on alpha.
+ * b_t = beta Phi_t^T y_t once (Eq. (lin-sys)), since b does not depend on alpha.  For
+ * OP_PARTIAL_FOURIER problems cmtcs_estep, cmtcs_em_iter (always step by step), cmtcs_solve,
+ * cmtcs_apply, cmtcs_rhs and the M-steps are available; cmtcs_grad returns
+ * CMTCS_E_UNSUPPORTED.
  * On success *out receives the handle; on failure *out is set to NULL. */
 cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* prob, void* stream);
 
@@ -274,8 +295,10 @@ cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_t
  * vector update are bracketed by HIP events on the handle's stream and their durations are
  * summed.  While enabled, the step-by-step CG loop waits for the events every 8 steps and then
  * also stops enqueueing steps once every right-hand side has stopped (the timings then cover
- * the steps that did work).  enable = 1 clears the sums and turns timing on; enable = 0 turns it off; any other
- * value leaves the state unchanged.  When non-NULL, the HOST arrays receive the sums so far
+ * the steps that did work).  For OP_PARTIAL_FOURIER problems, whose CG solves are one
+ * kernel each, that kernel's duration is summed in the third slot and the first two stay 0.
+ * enable = 1 clears the sums and turns timing on; enable = 0 turns it off; any other value
+ * leaves the state unchanged.  When non-NULL, the HOST arrays receive the sums so far
  * (after the stream has drained): totals_ms[3] in milliseconds and counts[3] in launches, in
  * the order {Phi V product, Phi^T W product, CG update}. */
 cmtcs_status_t cmtcs_profile(cmtcs_handle_t h, int32_t enable, double* totals_ms,

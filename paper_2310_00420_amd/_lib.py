@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "libcmtcs.so")
 CMTCS_OK, CMTCS_E_INVALID, CMTCS_E_HIP, CMTCS_E_NOMEM, CMTCS_E_UNSUPPORTED = range(5)
 CMTCS_F32, CMTCS_BF16, CMTCS_F16 = range(3)
 CMTCS_MATH_F64, CMTCS_MATH_F32, CMTCS_MATH_MIXED = range(3)
+CMTCS_OP_DENSE, CMTCS_OP_PARTIAL_FOURIER = range(2)
 CMTCS_CG_CONVERGED, CMTCS_CG_MAX_ITER, CMTCS_CG_BREAKDOWN, CMTCS_CG_NONPOS_RITZ = range(4)
 
 STATUS_NAMES = {0: "CMTCS_OK", 1: "CMTCS_E_INVALID", 2: "CMTCS_E_HIP", 3: "CMTCS_E_NOMEM",
@@ -26,7 +27,7 @@ class Problem(ctypes.Structure):
                 ("phi_f32", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("beta", ctypes.c_double), ("math", ctypes.c_int),
                 ("max_rhs", ctypes.c_int32), ("max_iters", ctypes.c_int32),
-                ("max_K", ctypes.c_int32)]
+                ("max_K", ctypes.c_int32), ("op", ctypes.c_int), ("freq", ctypes.c_void_p)]
 
 
 class Opts(ctypes.Structure):

@@ -46,39 +46,60 @@ class Cmtcs:
     phi: [sum N_t][D] float32 device tensor (stacked Phi_t); row_off: T+1 prefix sums of N_t
     (host sequence); y: [sum N_t] float32 device tensor.  math: "f64", "f32" or "mixed"; with
     "mixed" the library stores Phi in ``phi16`` ("bf16" or "f16").
+
+    Partial-Fourier sensing (Sec. 4; ``partial_fourier``): phi is None, ``freq`` is the
+    [sum N_t] int32 device tensor of selected frequencies, y the [sum N_t][2] float32 (re, im)
+    measurements, D the signal length; FP64 only.
     """
 
     def __init__(self, phi, row_off, y, beta, C, math="f64", max_rhs=None, max_iters=200,
-                 max_K=32, phi16="bf16"):
+                 max_K=32, phi16="bf16", freq=None, D=None):
         lib = _lib.load()
         self.row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
         self.T = len(self.row_off) - 1
-        self.D = int(phi.shape[1])
         self.C = int(C)
         rows = int(self.row_off[-1])
-        _need(phi, torch.float32, (rows, self.D), "phi")
-        _need(y, torch.float32, (rows,), "y")
+        self.fourier = freq is not None
+        if self.fourier:
+            if phi is not None:
+                raise ValueError("partial-Fourier problems take no phi")
+            self.D = int(D)
+            _need(freq, torch.int32, (rows,), "freq")
+            _need(y, torch.float32, (rows, 2), "y")
+        else:
+            self.D = int(phi.shape[1])
+            _need(phi, torch.float32, (rows, self.D), "phi")
+            _need(y, torch.float32, (rows,), "y")
         self.math = math
         self.vdtype = torch.float64 if math == "f64" else torch.float32
         dtype = _lib.CMTCS_F32
         if math == "mixed":
             dtype = {"bf16": _lib.CMTCS_BF16, "f16": _lib.CMTCS_F16}[phi16]
-        self.phi, self.y = phi, y
+        self.phi, self.y, self.freq = phi, y, freq
         self.max_K = int(max_K)
         self.max_iters = int(max_iters)
         self.max_rhs = int(max_rhs if max_rhs is not None else self.C * (self.max_K + 1))
         self.beta = float(beta)
-        self.device = phi.device
+        self.device = y.device
         self._roff = self.row_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
-        p = _lib.Problem(T=self.T, C=self.C, D=self.D, row_off=self._roff, phi=phi.data_ptr(),
+        p = _lib.Problem(T=self.T, C=self.C, D=self.D, row_off=self._roff,
+                         phi=None if phi is None else phi.data_ptr(),
                          phi_dtype=dtype, phi_f32=None, y=y.data_ptr(), beta=self.beta,
                          math=MATH[math], max_rhs=self.max_rhs, max_iters=self.max_iters,
-                         max_K=self.max_K)
+                         max_K=self.max_K,
+                         op=_lib.CMTCS_OP_PARTIAL_FOURIER if self.fourier else _lib.CMTCS_OP_DENSE,
+                         freq=None if freq is None else freq.data_ptr())
         h = ctypes.c_void_p()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         _lib.check(lib.cmtcs_create(ctypes.byref(h), ctypes.byref(p), ctypes.c_void_p(stream)))
         self._h = h
         self._stream = stream
+
+    @classmethod
+    def partial_fourier(cls, freq, row_off, yc, D, beta, C, **kw):
+        """A partial-Fourier problem: Phi_t = Omega_t F (the rows ``freq`` of the unitary DFT),
+        complex measurements ``yc`` as [sum N_t][2] (re, im) float32 pairs."""
+        return cls(None, row_off, yc, beta, C, freq=freq, D=D, **kw)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

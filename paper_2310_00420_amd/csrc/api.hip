@@ -43,6 +43,12 @@ struct cmtcs_handle_s {
   int T = 0, C = 0, D = 0;
   double beta = 0.0;
   cmtcs_math_t math = CMTCS_MATH_F64;
+  // partial-Fourier sensing: frequencies, multiplier counts m_k + m_{-k} per task, and a
+  // counter of out-of-range frequencies found at create
+  bool fourier = false;
+  const int* freq = nullptr;
+  int* hcount = nullptr;
+  int* bad_freq = nullptr;
   int max_rhs = 0, max_iters = 0, max_K = 0, Rp_max = 0;
   size_t vbytes = 8;
   std::vector<int64_t> row_off;
@@ -225,6 +231,24 @@ struct cmtcs_handle_s {
   }
 
   bool mixed() const { return math == CMTCS_MATH_MIXED; }
+
+  // The whole CG solve of a partial-Fourier problem: one kernel (timed in the third profiling
+  // slot while profiling is on).
+  cmtcs_status_t run_fourier(const Geometry& g, const float* alpha, int mode,
+                             const RhsSource& src, double tol, int steps, int fixed) {
+    const CgState s = cg_loop(alpha);
+    hipEvent_t* e4 = prof_on ? ev[ev_pending] : nullptr;
+    if (e4) {
+      for (int k = 0; k < 3; ++k) HIP_TRY(hipEventRecord(e4[k], st), "hipEventRecord");
+    }
+    HIP_TRY(launch_fourier_cg(g, s, hcount, mode, src, tol, steps, fixed, st),
+            "launch(fourier_cg)");
+    if (e4) {
+      HIP_TRY(hipEventRecord(e4[3], st), "hipEventRecord");
+      if (++ev_pending == kCheckEvery) HIP_TRY(harvest(), "profile events");
+    }
+    return CMTCS_OK;
+  }
 
   CgState cg() const {
     CgState s;
@@ -446,6 +470,18 @@ struct cmtcs_handle_s {
   cmtcs_status_t apply(const float* alpha, int R, const int32_t* col_cluster, const void* V,
                        void* AV) {
     const int Rp = col_slots(R);
+    if (fourier) {
+      const Geometry g = geom(R, Rp);
+      HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
+      RhsSource src;
+      src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.keyp = nullptr;
+      src.probes = nullptr; src.crn = 0;
+      cmtcs_status_t rs = run_fourier(g, alpha, 1, src, 0.0, 0, 1);
+      if (rs != CMTCS_OK) return rs;
+      HIP_TRY(launch_solve_output<VT>(g, cg(), AV, nullptr, nullptr, 0, nullptr, nullptr, st),
+              "launch(copy out)");
+      return CMTCS_OK;
+    }
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(R, Rp);
@@ -486,22 +522,27 @@ struct cmtcs_handle_s {
                        float* mu, float* sd, double* logdet, double* ell, double* q,
                        cmtcs_cg_stats_t* stats) {
     const int K = o.K, R = C * (K + 1), Rp = col_slots(R);
-    cmtcs_status_t rs = prepare(Rp);
+    cmtcs_status_t rs = fourier ? CMTCS_OK : prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(R, Rp);
     const uint64_t key = probe_key(o.seed, o.em_iter);
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, K, nullptr, st), "launch(fill_colc)");
-    rs = tune<VT>(g, alpha);
+    if (!fourier) rs = tune<VT>(g, alpha);
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_set_key(key_d, key, st), "launch(set_key)");
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.keyp = key_d; src.probes = o.probes;
     src.crn = o.common_probes;
-    HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
-    if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
-    else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
+    if (fourier) {
+      rs = run_fourier(g, alpha, 0, src, fixed ? 0.0 : o.tol, steps, fixed);
+    } else {
+      HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st),
+              "launch(cg_init)");
+      if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
+      else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
+    }
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_estep_finalize<VT>(g, cg(), K, key_d, o.probes, o.common_probes, mu, sd, st),
             "launch(estep_finalize)");
@@ -558,7 +599,7 @@ struct cmtcs_handle_s {
   template <typename VT>
   cmtcs_status_t em_iter(float* alpha, const double* log_pi, const cmtcs_opts_t& o, float* mu,
                          float* sd, double* logdet, double* ell, double* q) {
-    if (!o.graph || mixed()) {
+    if (!o.graph || mixed() || fourier) {
       cmtcs_status_t rs = estep<VT>(alpha, log_pi, o, mu, sd, logdet, ell, q, nullptr);
       if (rs != CMTCS_OK) return rs;
       HIP_TRY(launch_mstep(T, C, D, mu, sd, q, o.alpha_max, alpha, st), "launch(mstep)");
@@ -606,20 +647,25 @@ struct cmtcs_handle_s {
                        void* Xout, double* gout, double* xout, const cmtcs_opts_t& o,
                        cmtcs_cg_stats_t* stats) {
     const int Rp = col_slots(R);
-    cmtcs_status_t rs = prepare(Rp);
+    cmtcs_status_t rs = fourier ? CMTCS_OK : prepare(Rp);
     if (rs != CMTCS_OK) return rs;
     const Geometry g = geom(R, Rp);
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
-    rs = tune<VT>(g, alpha);
+    if (!fourier) rs = tune<VT>(g, alpha);
     if (rs != CMTCS_OK) return rs;
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
     src.crn = 0;
-    HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st), "launch(cg_init)");
-    if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
-    else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
+    if (fourier) {
+      rs = run_fourier(g, alpha, 0, src, fixed ? 0.0 : o.tol, steps, fixed);
+    } else {
+      HIP_TRY(launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, st),
+              "launch(cg_init)");
+      if (o.graph && !mixed()) rs = run_cg_graph<VT>(g, alpha, steps, fixed);
+      else rs = run_cg<VT>(g, alpha, steps, fixed, src, o.refine_every);
+    }
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_solve_output<VT>(g, cg(), Xout, gout, xout, steps,
                                     stats ? stats->iters : nullptr,
@@ -669,8 +715,19 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
     if (p->row_off[t + 1] < p->row_off[t])
       return fail(CMTCS_E_INVALID, "row_off must be non-decreasing");
   const int64_t rows = p->row_off[p->T];
-  if (rows > 0 && (p->phi == nullptr || p->y == nullptr))
+  if (p->op != CMTCS_OP_DENSE && p->op != CMTCS_OP_PARTIAL_FOURIER)
+    return fail(CMTCS_E_INVALID, "unknown sensing operator");
+  const bool fourier = p->op == CMTCS_OP_PARTIAL_FOURIER;
+  if (fourier) {
+    if (rows > 0 && (p->freq == nullptr || p->y == nullptr))
+      return fail(CMTCS_E_INVALID, "freq and y must be non-NULL");
+    if (p->math != CMTCS_MATH_F64)
+      return fail(CMTCS_E_UNSUPPORTED, "partial-Fourier problems run in MATH_F64 only");
+    if (p->D < 64 || p->D > 4096 || (p->D & (p->D - 1)) != 0)
+      return fail(CMTCS_E_UNSUPPORTED, "partial-Fourier problems need D a power of two, 64..4096");
+  } else if (rows > 0 && (p->phi == nullptr || p->y == nullptr)) {
     return fail(CMTCS_E_INVALID, "phi and y must be non-NULL");
+  }
   if (!(p->beta > 0.0)) return fail(CMTCS_E_INVALID, "beta must be > 0");
   if (p->max_rhs < 1) return fail(CMTCS_E_INVALID, "max_rhs must be >= 1");
   if (p->max_iters < 1 || p->max_iters > 4096)
@@ -684,13 +741,13 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
     if (p->phi_dtype != CMTCS_BF16 && p->phi_dtype != CMTCS_F16)
       return fail(CMTCS_E_INVALID, "MATH_MIXED needs phi_dtype BF16 or F16");
     if (p->D % 32 != 0) return fail(CMTCS_E_INVALID, "MATH_MIXED needs D a multiple of 32");
-  } else if (p->phi_dtype != CMTCS_F32) {
+  } else if (p->phi_dtype != CMTCS_F32 && !fourier) {
     return fail(CMTCS_E_INVALID, "MATH_F64 and MATH_F32 take phi_dtype F32");
   }
   for (int t = 0; t < p->T; ++t)
     if (p->row_off[t + 1] - p->row_off[t] > (1 << 30))
       return fail(CMTCS_E_INVALID, "N_t too large");
-  {
+  if (!fourier) {
     // the operator products address each task's blocks with 32-bit byte offsets
     const int64_t lim = int64_t(1) << 32, slots = col_slots(p->max_rhs);
     if (slots * p->D * 8 >= lim)
@@ -714,6 +771,8 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   h->phi_dtype = p->phi_dtype;
   h->phi = (const float*)p->phi;
   h->y = p->y;
+  h->fourier = fourier;
+  h->freq = p->freq;
   h->st = (hipStream_t)stream;
 
   const size_t T = h->T, C = h->C, D = h->D, Rpm = h->Rp_max, it = h->max_iters;
@@ -760,8 +819,15 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   };
   A(&h->row_off_d, sizeof(int64_t) * (T + 1));
   A(&h->w_off_d, sizeof(int64_t) * (T + 1));
-  A(&h->X, vec); A(&h->Rv, vec); A(&h->Dv, vec); A(&h->AD, vec);
-  A(&h->W, Rpm * np_sum * h->vbytes);
+  A(&h->X, vec);
+  if (fourier) {
+    // the CG state lives in the solve kernel; the multiplier counts per task
+    A(&h->hcount, sizeof(int) * T * D);
+    A(&h->bad_freq, sizeof(int));
+  } else {
+    A(&h->Rv, vec); A(&h->Dv, vec); A(&h->AD, vec);
+    A(&h->W, Rpm * np_sum * h->vbytes);
+  }
   A(&h->b, T * D * h->vbytes);
   A(&h->rr, sizeof(double) * T * Rpm);
   A(&h->thr, sizeof(double) * T * Rpm);
@@ -771,8 +837,10 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->xi, sizeof(double) * it * T * Rpm);
   A(&h->act, sizeof(int) * (it + 1) * T);
   A(&h->colc, sizeof(int) * T * (Rpm + (size_t)h->max_rhs));   // [T][Rp] + map staging
-  A(&h->fwd_tiles, sizeof(int4) * fwd_max);
-  A(&h->adj_tiles, sizeof(int4) * adj_max);
+  if (!fourier) {
+    A(&h->fwd_tiles, sizeof(int4) * fwd_max);
+    A(&h->adj_tiles, sizeof(int4) * adj_max);
+  }
   // SLQ tridiagonals of runs too long for LDS
   A(&h->slq_ws, std::max<size_t>(16, slq_workspace_bytes((long)P, (int)it, h->slq_lds)));
   A(&h->key_d, sizeof(uint64_t));
@@ -806,15 +874,25 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   }
   e = hipMemcpyAsync(h->row_off_d, h->row_off.data(), sizeof(int64_t) * (T + 1),
                      hipMemcpyHostToDevice, h->st);
+  int bad = 0;
   if (e == hipSuccess) {
     const Geometry g = h->geom(1, 16);
-    if (f64) e = launch_rhs<double>(g, h->phi, h->y, h->beta, (double*)h->b, h->st);
+    if (fourier)
+      e = launch_fourier_setup(g, h->freq, h->y, h->beta, (double*)h->b, h->hcount, h->bad_freq,
+                               h->st);
+    else if (f64) e = launch_rhs<double>(g, h->phi, h->y, h->beta, (double*)h->b, h->st);
     else e = launch_rhs<float>(g, h->phi, h->y, h->beta, (float*)h->b, h->st);
   }
+  if (e == hipSuccess && fourier)
+    e = hipMemcpyAsync(&bad, h->bad_freq, sizeof(int), hipMemcpyDeviceToHost, h->st);
   if (e == hipSuccess) e = hipStreamSynchronize(h->st);
   if (e != hipSuccess) {
     delete h;
     return hip_fail(e, "cmtcs_create");
+  }
+  if (bad != 0) {
+    delete h;
+    return fail(CMTCS_E_INVALID, "freq entries must be in 0..D-1");
   }
   if (h->math == CMTCS_MATH_MIXED) {
     // 16-bit tables and offsets, then the transposed 16-bit copy of Phi
@@ -931,6 +1009,8 @@ cmtcs_status_t cmtcs_grad(cmtcs_handle_t h, int32_t R_per_task, const int32_t* c
   if (R_per_task < 1 || 2 * (int64_t)R_per_task > h->max_rhs)
     return fail(CMTCS_E_INVALID, "R_per_task must be in 1..max_rhs/2");
   if (!col_cluster || !X || !Lam) return fail(CMTCS_E_INVALID, "a required argument is NULL");
+  if (h->fourier)
+    return fail(CMTCS_E_UNSUPPORTED, "cmtcs_grad is not available for partial-Fourier problems");
   for (int64_t i = 0; i < (int64_t)h->T * R_per_task; ++i)
     if (col_cluster[i] < 0 || col_cluster[i] >= h->C)
       return fail(CMTCS_E_INVALID, "col_cluster entries must be in 0..C-1");

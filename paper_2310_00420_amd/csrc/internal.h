@@ -298,6 +298,17 @@ constexpr int kRows16 = 64;   // output rows per wave tile of the 16-bit product
 // 4.3 TB/s for 64-row tiles at an 8 KB pitch, 6.1 TB/s at 8 KB + 128 B, like a linear stream).
 __host__ __device__ constexpr int64_t ld16(int64_t n) { return (n + 127) / 128 * 128 + 64; }
 
+// Launchers (k_fourier.hip): partial-Fourier problems (D a power of two, 64..4096, FP64).
+// mode 0: the whole CG solve of every column (two columns per workgroup), writing X, the
+// gamma/xi histories, iters and state of s; mode 1: X = A B for the columns of src.B (kind 1).
+hipError_t launch_fourier_cg(const Geometry& g, const CgState& s, const int* hcount, int mode,
+                             const RhsSource& src, double tol, int steps, int fixed,
+                             hipStream_t st);
+// b = beta Re(F^H Omega^T y) per task and hcount[t][k] = m_k + m_{-k}; frequencies outside
+// [0, D) are counted in *bad.
+hipError_t launch_fourier_setup(const Geometry& g, const int* freq, const float* yc, double beta,
+                                double* b, int* hcount, int* bad, hipStream_t st);
+
 // Launchers (k_em.hip).
 template <typename VT>
 hipError_t launch_rhs(const Geometry& g, const float* phi, const float* y, double beta, VT* b,

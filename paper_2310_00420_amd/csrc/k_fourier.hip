@@ -1,0 +1,416 @@
+// Partial-Fourier sensing (Sec. 4: Phi_t = Omega_t F, F the unitary D x D DFT, Omega_t a subset
+// of its rows; real model through the stacking [Re; Im]), where applying A costs O(D log D)
+// (Sec. 3.3):
+//     A v = beta Re(F^H Omega^T Omega F v) + alpha (.) v = beta F^H diag(h) F v + alpha (.) v,
+// with h_k = (m_k + m_{-k}) / 2 and m_k the number of times frequency k is selected: for a real
+// v the real part averages each frequency with its mirror image, so A maps real vectors to real
+// vectors through one complex transform pair with a real, symmetric multiplier.
+//
+// The whole CG solve of a right-hand side (Alg. 1) runs in one workgroup: the column lives in
+// registers, the transforms in LDS, and nothing but the step sizes gamma_u, xi_u (for the
+// log-determinant, Eq. (tridiag)) and the final solution goes to HBM.  A workgroup solves two
+// columns of the same task at once: since h is real and symmetric, F^H diag(h) F applied to
+// v1 + i v2 gives the two real results as the real and imaginary parts, so one complex FFT pair
+// serves both.  The transform is the Stockham autosort FFT (radix 4, one radix-2 stage when
+// log2 D is odd), in place in LDS: each stage reads its butterfly inputs, waits, then writes.
+// Twiddles come from a table of cos(2 pi i / D), i <= D/4, built by each workgroup in LDS.
+#include <algorithm>
+
+#include "internal.h"
+#include "../../include/cmtcs.h"
+
+namespace cmtcs {
+
+namespace {
+
+// exp(-2 pi i m / N) (forward) or its conjugate (inverse), 0 <= m < N, from the quarter-wave
+// cosine table c[i] = cos(2 pi i / N), i = 0..N/4 (sin(2 pi i / N) = c[N/4 - i]).
+template <bool INV>
+__device__ inline d2 root(int m, int N, const double* c) {
+  const int q4 = N >> 2;
+  const int quad = m / q4, i = m - quad * q4;
+  const double cs = c[i], sn = c[q4 - i];
+  double re, im;   // cos(theta), -sin(theta) for theta = 2 pi m / N
+  switch (quad) {
+    case 0: re = cs; im = -sn; break;
+    case 1: re = -sn; im = -cs; break;
+    case 2: re = -cs; im = sn; break;
+    default: re = sn; im = cs; break;
+  }
+  return d2{re, INV ? -im : im};
+}
+
+__device__ inline d2 cmul(d2 a, d2 b) {
+  return d2{__builtin_fma(a[0], b[0], -a[1] * b[1]), __builtin_fma(a[0], b[1], a[1] * b[0])};
+}
+
+// One Stockham stage of radix R (2 or 4) over N points: butterfly j (0 <= j < N/R) reads
+// x[j + r N/R], multiplies input r by the twiddle w^(r k) (k = j mod Ns, w = exp(-2 pi i /
+// (R Ns))), transforms the R values and writes them to (j / Ns) R Ns + k + r Ns.  Ns is the
+// length of the sub-transforms already done.  Every thread of the block must call it.
+template <int R, bool INV, int BS, int N>
+__device__ inline void fft_stage(d2* buf, const double* ctab, int Ns) {
+  constexpr int NBF = N / R;                       // butterflies
+  constexpr int PER = NBF >= BS ? NBF / BS : 1;    // per thread
+  d2 v[PER][R];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = (int)threadIdx.x + i * BS;
+    if (j < NBF) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = buf[j + r * NBF];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int j = (int)threadIdx.x + i * BS;
+    if (j < NBF) {
+      const int k = j & (Ns - 1);
+      const int step = N / (R * Ns);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], root<INV>(r * k * step, N, ctab));
+      d2 u[R];
+      if constexpr (R == 2) {
+        u[0] = v[i][0] + v[i][1];
+        u[1] = v[i][0] - v[i][1];
+      } else {
+        const d2 a0 = v[i][0] + v[i][2], a1 = v[i][0] - v[i][2];
+        const d2 a2 = v[i][1] + v[i][3], a3 = v[i][1] - v[i][3];
+        // -i a3 (forward) or +i a3 (inverse)
+        const d2 ma3 = INV ? d2{-a3[1], a3[0]} : d2{a3[1], -a3[0]};
+        u[0] = a0 + a2;
+        u[1] = a1 + ma3;
+        u[2] = a0 - a2;
+        u[3] = a1 - ma3;
+      }
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[base + r * Ns] = u[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Unnormalised DFT of the N points in buf (forward: exp(-2 pi i k d / N); inverse: conjugate).
+template <bool INV, int BS, int LOGN>
+__device__ inline void fft(d2* buf, const double* ctab) {
+  constexpr int N = 1 << LOGN;
+  int Ns = 1;
+  if constexpr (LOGN & 1) {
+    fft_stage<2, INV, BS, N>(buf, ctab, Ns);
+    Ns = 2;
+  }
+  // a runtime loop over the radix-4 stages: unrolled, the address arithmetic of every stage is
+  // invariant across CG steps and would be kept in registers
+#pragma unroll 1
+  for (; Ns < N; Ns *= 4) fft_stage<4, INV, BS, N>(buf, ctab, Ns);
+}
+
+// Sums of two values over the block in a fixed order; every thread receives both.
+template <int BS>
+__device__ inline d2 block_sum2(double a, double b, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { sh[2 * w] = a; sh[2 * w + 1] = b; }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < BS / 64; ++i) { sa += sh[2 * i]; sb += sh[2 * i + 1]; }
+  return d2{sa, sb};
+}
+
+}  // namespace
+
+// Threads per workgroup for length 2^LOGN: a quarter of the length (one radix-4 butterfly per
+// thread and stage), at least one wave and at most 512, so that a wave may hold 256 registers
+// (two columns of 2^LOGN / 512 elements in x, r, d and A d, plus the butterflies in flight).
+template <int LOGN>
+constexpr int fourier_bs() {
+  return std::max(64, std::min(512, (1 << LOGN) / 4));
+}
+
+// Workgroup (t, pair p): columns j = 2p and 2p + 1 of task t.
+//   mode 0: CG (Alg. 1) from x = 0 on the right-hand sides (kind 0: the E-step's mean system and
+//           probes; kind 1: B), recording gamma_u, xi_u, the step count and the outcome, and
+//           writing x to X;
+//   mode 1: one application of A to B's columns, written to X.
+template <int LOGN>
+__global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
+    double* __restrict__ X, double* __restrict__ gam, double* __restrict__ xi,
+    int* __restrict__ iters, uint8_t* __restrict__ state, const int* __restrict__ hcount,
+    const float* __restrict__ alpha, const int* __restrict__ colc, int mode, int kind,
+    const double* __restrict__ b, const double* __restrict__ B, int K,
+    const uint64_t* __restrict__ keyp, const int8_t* __restrict__ probes, int crn, double beta,
+    double tol2, int steps, int fixed, int T, int C, int R, int Rp) {
+  constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>(), E = N / BS;
+  extern __shared__ double lds[];
+  d2* buf = reinterpret_cast<d2*>(lds);           // N complex points
+  double* ctab = lds + 2 * N;                      // N/4 + 1 cosines (N/4 + 2 slots)
+  double* red = ctab + (N / 4 + 2);                // 2 BS/64 partial sums
+  d2* xs = reinterpret_cast<d2*>(red + 2 * (BS / 64));   // x of both columns, N pairs
+  const int tid = threadIdx.x;
+  const int pairs = Rp / 2;
+  const int t = blockIdx.x / pairs, p = blockIdx.x % pairs;
+  const int j0 = 2 * p;
+  for (int i = tid; i <= N / 4; i += BS) ctab[i] = cospi(2.0 * (double)i / (double)N);
+
+  // the two columns: right-hand sides, diagonal terms, multipliers
+  // r and d of both columns stay in registers, x in LDS (each thread its own elements); alpha
+  // of each column's cluster and the multiplier counts are re-read (from cache) where used
+  double rv[2][E], dv[2][E];
+  const float* alc[2];
+  const int* hct = hcount + (int64_t)t * N;
+  bool live[2];
+  uint64_t key = 0;
+  if (kind == 0 && probes == nullptr) key = *keyp;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int j = j0 + q;
+    live[q] = j < R;
+    const int64_t idx = (int64_t)t * Rp + j;
+    const int c = live[q] ? colc[idx] : 0;
+    alc[q] = alpha + (int64_t)c * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int d = tid + e * BS;
+      double v = 0.0;
+      if (live[q]) {
+        if (kind == 0) {
+          const int cc = j / (K + 1), k = j % (K + 1);
+          if (k == 0) v = b[(int64_t)t * N + d];
+          else if (probes != nullptr)
+            v = (double)probes[(((int64_t)t * C + cc) * K + (k - 1)) * N + d];
+          else v = probe_entry(key, t, crn ? 0 : cc, k - 1, d, C, K, N);
+        } else {
+          v = B[((int64_t)t * R + j) * N + d];
+        }
+      }
+      rv[q][e] = v;
+      dv[q][e] = v;
+    }
+  }
+  const double hscale = 0.5 * beta / (double)N;   // h = count / 2, beta, the pair's 1/N
+
+  // beta Phi^T Phi d for both columns (zero for a stopped one), left in buf as (column 0,
+  // column 1) pairs in natural order; A d = that + alpha (.) d is formed where it is read
+  auto apply = [&](const bool* on) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      buf[tid + e * BS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
+    __syncthreads();
+    fft<false, BS, LOGN>(buf, ctab);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      buf[tid + e * BS] = buf[tid + e * BS] * (hscale * (double)hct[tid + e * BS]);
+    __syncthreads();
+    fft<true, BS, LOGN>(buf, ctab);
+  };
+  auto ad_of = [&](int q, int e) __attribute__((always_inline)) {
+    return __builtin_fma(live[q] ? (double)alc[q][tid + e * BS] : 0.0, dv[q][e],
+                         buf[tid + e * BS][q]);
+  };
+
+  if (mode == 1) {
+    __syncthreads();   // the cosine table
+    apply(live);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      if (live[q]) {
+        const int64_t base = ((int64_t)t * Rp + j0 + q) * N;
+#pragma unroll
+        for (int e = 0; e < E; ++e) X[base + tid + e * BS] = ad_of(q, e);
+      }
+    return;
+  }
+
+  double pr0 = 0.0, pr1 = 0.0;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    xs[tid + e * BS] = d2{0.0, 0.0};
+    pr0 += rv[0][e] * rv[0][e];
+    pr1 += rv[1][e] * rv[1][e];
+  }
+  const d2 r0 = block_sum2<BS>(pr0, pr1, red);   // its barriers also publish the table
+  double rr[2] = {r0[0], r0[1]}, thr[2];
+  bool act[2];
+  uint8_t st[2];
+  int its[2] = {0, 0};
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    thr[q] = tol2 * rr[q];
+    if (!isfinite(rr[q])) st[q] = CMTCS_CG_BREAKDOWN;
+    else if (rr[q] > 0.0) st[q] = kActive;
+    else st[q] = CMTCS_CG_CONVERGED;   // b = 0: x = 0 is exact
+    act[q] = live[q] && st[q] == kActive;
+  }
+  const int64_t ncol = (int64_t)T * Rp;
+  for (int u = 0; u < steps && (act[0] || act[1]); ++u) {
+    apply(act);
+    double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      p0 += dv[0][e] * ad_of(0, e);
+      p1 += dv[1][e] * ad_of(1, e);
+    }
+    const d2 dAd = block_sum2<BS>(p0, p1, red);
+    double g[2] = {0.0, 0.0};
+    bool upd[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      upd[q] = act[q];
+      if (act[q] && (!(dAd[q] > 0.0) || !isfinite(dAd[q]))) {
+        st[q] = CMTCS_CG_BREAKDOWN;   // stop before this step
+        act[q] = false;
+        upd[q] = false;
+      }
+      if (upd[q]) g[q] = rr[q] / dAd[q];
+    }
+    p0 = 0.0;
+    p1 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      d2 x2 = xs[tid + e * BS];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (upd[q]) {
+          x2[q] = __builtin_fma(g[q], dv[q][e], x2[q]);
+          rv[q][e] = __builtin_fma(-g[q], ad_of(q, e), rv[q][e]);
+        }
+      xs[tid + e * BS] = x2;
+      p0 += rv[0][e] * rv[0][e];
+      p1 += rv[1][e] * rv[1][e];
+    }
+    const d2 rrn = block_sum2<BS>(p0, p1, red);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (!upd[q]) continue;
+      const double x_ = rrn[q] / rr[q];
+#pragma unroll
+      for (int e = 0; e < E; ++e) dv[q][e] = __builtin_fma(x_, dv[q][e], rv[q][e]);
+      const int64_t idx = (int64_t)t * Rp + j0 + q;
+      if (tid == 0) {
+        gam[(int64_t)u * ncol + idx] = g[q];
+        xi[(int64_t)u * ncol + idx] = x_;
+      }
+      rr[q] = rrn[q];
+      its[q] = u + 1;
+      if (!isfinite(rrn[q])) st[q] = CMTCS_CG_BREAKDOWN;
+      else if (rrn[q] == 0.0 || (fixed == 0 && rrn[q] <= thr[q])) st[q] = CMTCS_CG_CONVERGED;
+      else if (u + 1 >= steps) st[q] = fixed ? CMTCS_CG_CONVERGED : CMTCS_CG_MAX_ITER;
+      act[q] = st[q] == kActive;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    if (!live[q]) continue;
+    const int64_t idx = (int64_t)t * Rp + j0 + q;
+    const int64_t base = idx * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) X[base + tid + e * BS] = xs[tid + e * BS][q];
+    if (tid == 0) {
+      iters[idx] = its[q];
+      // a column still active here ran out of steps (steps = 0)
+      state[idx] = st[q] == kActive ? (fixed ? CMTCS_CG_CONVERGED : CMTCS_CG_MAX_ITER) : st[q];
+    }
+  }
+}
+
+// b_t[d] = beta Re(F^H Omega_t^T y_t)[d] = beta / sqrt(D) sum_n (Re y_n cos(2 pi k_n d / D)
+//          - Im y_n sin(2 pi k_n d / D)), the angle reduced exactly: (k_n d) mod D.
+__global__ __launch_bounds__(256) void k_fourier_rhs(const int* __restrict__ freq,
+                                                     const float* __restrict__ yc,
+                                                     const int64_t* __restrict__ row_off,
+                                                     double beta, double* __restrict__ b,
+                                                     int D) {
+  const int t = blockIdx.x;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  double acc = 0.0;
+  for (int64_t n = row_off[t]; n < row_off[t + 1]; ++n) {
+    const int k = freq[n];
+    if (k < 0 || k >= D) continue;   // rejected at create
+    const int64_t m = ((int64_t)k * d) & (D - 1);
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)D, &sn, &cs);
+    acc += (double)yc[2 * n] * cs - (double)yc[2 * n + 1] * sn;
+  }
+  b[(int64_t)t * D + d] = beta * acc / sqrt((double)D);
+}
+
+// hcount[t][k] = m_k + m_{-k}: selections of frequency k and of its mirror (D - k) mod D.
+// Frequencies outside [0, D) are counted in *bad and otherwise ignored.
+__global__ __launch_bounds__(256) void k_fourier_hcount(const int* __restrict__ freq,
+                                                        const int64_t* __restrict__ row_off,
+                                                        int* __restrict__ hcount,
+                                                        int* __restrict__ bad, int T, int D) {
+  const int t = blockIdx.x;
+  for (int64_t n = row_off[t] + threadIdx.x; n < row_off[t + 1]; n += 256) {
+    const int k = freq[n];
+    if (k < 0 || k >= D) {
+      atomicAdd(bad, 1);
+      continue;
+    }
+    atomicAdd(&hcount[(int64_t)t * D + k], 1);
+    atomicAdd(&hcount[(int64_t)t * D + ((D - k) & (D - 1))], 1);
+  }
+}
+
+template <int LOGN>
+static hipError_t fourier_one(const Geometry& g, const CgState& s, const int* hcount, int mode,
+                              const RhsSource& src, double tol2, int steps, int fixed,
+                              hipStream_t st) {
+  constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>();
+  // N complex points, the cosine table (padded to an even count, so that x stays 16-byte
+  // aligned), the reduction slots, x of both columns
+  const size_t lds = sizeof(double) * (2 * N + N / 4 + 2 + 2 * (BS / 64) + 2 * N);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_fourier_cg<LOGN>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_fourier_cg<LOGN>, dim3((unsigned)(g.T * (g.Rp / 2))), dim3(BS), lds, st,
+                     (double*)s.X, s.gam, s.xi, s.iters, s.state, hcount, s.alpha, s.colc, mode,
+                     src.kind, (const double*)src.b, (const double*)src.B, src.K, src.keyp,
+                     src.probes, src.crn, s.beta, tol2, steps, fixed, g.T, g.C, g.R, g.Rp);
+  return hipGetLastError();
+}
+
+hipError_t launch_fourier_cg(const Geometry& g, const CgState& s, const int* hcount, int mode,
+                             const RhsSource& src, double tol, int steps, int fixed,
+                             hipStream_t st) {
+  const double tol2 = tol * tol;
+  switch (g.D) {
+    case 64: return fourier_one<6>(g, s, hcount, mode, src, tol2, steps, fixed, st);
+    case 128: return fourier_one<7>(g, s, hcount, mode, src, tol2, steps, fixed, st);
+    case 256: return fourier_one<8>(g, s, hcount, mode, src, tol2, steps, fixed, st);
+    case 512: return fourier_one<9>(g, s, hcount, mode, src, tol2, steps, fixed, st);
+    case 1024: return fourier_one<10>(g, s, hcount, mode, src, tol2, steps, fixed, st);
+    case 2048: return fourier_one<11>(g, s, hcount, mode, src, tol2, steps, fixed, st);
+    case 4096: return fourier_one<12>(g, s, hcount, mode, src, tol2, steps, fixed, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fourier_setup(const Geometry& g, const int* freq, const float* yc, double beta,
+                                double* b, int* hcount, int* bad, hipStream_t st) {
+  hipError_t e = hipMemsetAsync(hcount, 0, sizeof(int) * (size_t)g.T * g.D, st);
+  if (e == hipSuccess) e = hipMemsetAsync(bad, 0, sizeof(int), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fourier_hcount, dim3(g.T), dim3(256), 0, st, freq, g.row_off, hcount, bad,
+                     g.T, g.D);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fourier_rhs, dim3(g.T, (g.D + 255) / 256), dim3(256), 0, st, freq, yc,
+                     g.row_off, beta, b, g.D);
+  return hipGetLastError();
+}
+
+}  // namespace cmtcs

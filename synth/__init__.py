@@ -146,3 +146,76 @@ def hadamard(m):
     for _ in range(m):
         H = np.block([[H, H], [H, -H]])
     return H
+
+
+# ------------------------------------------------------------------------------------------
+# Partial-Fourier sensing (the experiments of Sec. 4): Phi_t = Omega_t F with F the unitary D x D
+# DFT and Omega_t a random subset of N_t = D/4 of its rows; the complex measurements are
+# y_t = Omega_t F z_t + sigma (e1 + i e2), e1, e2 ~ N(0, I), stored as float32 (re, im) pairs;
+# the real model sees them stacked as [Re y_t; Im y_t] against [Re(Omega_t F); Im(Omega_t F)].
+# Signals, clusters and alpha^0 follow the same recipe as above; sigma = 0.05 as in Sec. 4 and
+# 5% of the entries of each signal are non-zero.
+
+FOURIER_CONFIGS = {
+    # small case for parity tests
+    "fourier-small": Config("fourier-small", T=4, C=2, D=256, N=64, sparsity=13, groups=2, K=16,
+                            sigma=0.05),
+    # the metric's task, cluster, probe and length sizes with the paper's sensing
+    "fourier": Config("fourier", T=64, C=4, D=4096, N=1024, sparsity=205, groups=4, K=32,
+                      sigma=0.05),
+}
+
+
+@dataclass
+class FourierWorkload:
+    cfg: Config
+    freq: np.ndarray           # [sum N_t] int32 selected frequencies, task t in row_off[t]:[t+1]
+    row_off: np.ndarray        # [T+1] int64 prefix sums of N_t (complex measurements)
+    yc: np.ndarray             # [sum N_t][2] float32 (re, im) measurements
+    z: np.ndarray              # [T][D] float64 true signals
+    labels: np.ndarray
+    alpha0: np.ndarray
+    beta: float
+    log_pi: np.ndarray
+
+    @property
+    def T(self):
+        return self.cfg.T
+
+    def freq_t(self, t):
+        return self.freq[self.row_off[t]:self.row_off[t + 1]]
+
+    def yc_t(self, t):
+        v = self.yc[self.row_off[t]:self.row_off[t + 1]].astype(np.float64)
+        return v[:, 0] + 1j * v[:, 1]
+
+
+def make_fourier(cfg, data_seed=DATA_SEED, init_seed=INIT_SEED, **over):
+    if isinstance(cfg, str):
+        cfg = FOURIER_CONFIGS[cfg]
+    if over:
+        cfg = Config(**{**cfg.__dict__, **over})
+    rng = np.random.default_rng(data_seed)
+    T, D = cfg.T, cfg.D
+    Ns = np.full(T, int(cfg.N)) if not isinstance(cfg.N, (list, tuple)) else np.asarray(cfg.N)
+    row_off = np.zeros(T + 1, np.int64)
+    row_off[1:] = np.cumsum(Ns)
+    per = -(-T // cfg.groups)
+    labels = np.minimum(np.arange(T) // per, cfg.groups - 1)
+    supports = [rng.choice(D, size=cfg.sparsity, replace=False) for _ in range(cfg.groups)]
+    freq = np.empty(int(row_off[-1]), np.int32)
+    yc = np.empty((int(row_off[-1]), 2), np.float32)
+    z = np.zeros((T, D))
+    for t in range(T):
+        n = int(Ns[t])
+        f = np.sort(rng.choice(D, size=n, replace=False))
+        z[t, supports[labels[t]]] = rng.standard_normal(cfg.sparsity)
+        Fz = np.fft.fft(z[t], norm="ortho")[f]
+        noise = cfg.sigma * (rng.standard_normal(n) + 1j * rng.standard_normal(n))
+        v = Fz + noise
+        freq[row_off[t]:row_off[t + 1]] = f
+        yc[row_off[t]:row_off[t + 1], 0] = v.real
+        yc[row_off[t]:row_off[t + 1], 1] = v.imag
+    return FourierWorkload(cfg=cfg, freq=freq, row_off=row_off, yc=yc, z=z, labels=labels,
+                           alpha0=draw_alpha0(cfg.C, D, init_seed), beta=1.0 / cfg.sigma ** 2,
+                           log_pi=np.full(cfg.C, -np.log(cfg.C)))
