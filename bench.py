@@ -18,7 +18,9 @@ sample on the host CPU.  The default FP64 run also reports:
                   16-bit); a speedup over FP32 is quoted only for a form that meets its bar;
   detail.forms_well_conditioned  the same at beta = 1, alpha in (1, 2), where the bars are met;
   detail.configs  the plain FP32 configuration (T=32, D=1024) and the ragged batching
-                  configuration (T=256, D=2048) timed the same way.
+                  configuration (T=256, D=2048) timed the same way;
+  detail.fourier  the paper's own sensing (Sec. 4): partial-Fourier Phi_t with T=64, C=4,
+                  D=4096, N=1024 frequencies, K=32, sigma 0.05.
 """
 
 import argparse
@@ -266,7 +268,7 @@ def roofline(m, w, math, config, prof, iters):
 
 
 def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup, steps,
-                 unprofiled=False):
+                 unprofiled=False, alpha0=None):
     """Times `steps` EM iterations (E-step + M-step, K probes, the workload's CG policy) after
     `warmup` untimed ones, with HIP-event kernel timing on the library's stream; optionally the
     same iterations again without kernel timing.  Returns the measurements and the host copy of
@@ -274,7 +276,8 @@ def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup
     cfg = w.cfg
     m = Cmtcs(torch.from_numpy(w.Phi).to(dev), w.row_off, torch.from_numpy(w.y).to(dev), w.beta,
               cfg.C, math=math, max_iters=cfg.max_iters, max_K=cfg.K, phi16=phi16)
-    alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
+    a0 = w.alpha0 if alpha0 is None else alpha0
+    alpha = torch.tensor(a0, dtype=torch.float32, device=dev)
     log_pi = torch.tensor(w.log_pi, device=dev)
     kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1,
               refine_every=refine_every if math == "mixed" else 0)
@@ -312,7 +315,7 @@ def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup
     if unprofiled:
         # the same EM iterations from the same alpha^0, without kernel timing: every CG step is
         # enqueued at once and the host never waits inside an E-step
-        alpha.copy_(torch.tensor(w.alpha0, dtype=torch.float32, device=dev))
+        alpha.copy_(torch.tensor(a0, dtype=torch.float32, device=dev))
         for it in range(warmup):
             em_iteration(it)
         torch.cuda.synchronize()
@@ -326,6 +329,58 @@ def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup
     res["_first"] = first
     res["_model"] = (m, alpha, log_pi)
     return res
+
+
+FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
+
+
+def run_fourier_workload(torch, Cmtcs, name, dev, warmup, steps):
+    """EM iterations on a partial-Fourier workload (Sec. 4 sensing): the whole CG solve of two
+    columns per workgroup in one kernel.  Roofline: FP64 arithmetic of the transforms, counted
+    as 5 N log2 N per complex FFT of N = D points (two per step of a column pair, i.e. one per
+    RHS-iteration), against the FP64 vector peak."""
+    import synth
+    w = synth.make_fourier(name)
+    cfg = w.cfg
+    m = Cmtcs.partial_fourier(torch.tensor(w.freq, device=dev), w.row_off,
+                              torch.tensor(w.yc, device=dev), cfg.D, w.beta, cfg.C,
+                              max_iters=cfg.max_iters, max_K=cfg.K)
+    alpha = torch.tensor(w.alpha0, dtype=torch.float32, device=dev)
+    log_pi = torch.tensor(w.log_pi, device=dev)
+    kw = dict(tol=cfg.tol, max_iters=cfg.max_iters, seed=1)
+    for it in range(warmup):
+        out = m.estep(alpha, log_pi, cfg.K, em_iter=it, **kw)
+        m.mstep(out["mu"], out["s"], out["q"], alpha)
+    torch.cuda.synchronize()
+    m.profile(True)
+    iters = []
+    t0 = time.perf_counter()
+    for it in range(warmup, warmup + steps):
+        out = m.estep(alpha, log_pi, cfg.K, em_iter=it, stats=True, **kw)
+        m.mstep(out["mu"], out["s"], out["q"], alpha)
+        iters.append(out["iters"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = m.profile(False)
+    m.close()
+    rhs = int(sum(int(i.sum().item()) for i in iters))
+    ms, launches = prof["cg_update"]
+    N = cfg.D
+    flops = 5.0 * N * np.log2(N) * rhs
+    achieved = flops / (ms * 1e-3) / 1e12
+    return {"workload": "partial-Fourier CoFEM EM iteration, T=%d C=%d D=%d N=%d frequencies "
+                        "(2N real measurements), K=%d, sigma %g, CG tol %g, <=%d steps"
+                        % (cfg.T, cfg.C, cfg.D, cfg.N, cfg.K, cfg.sigma, cfg.tol, cfg.max_iters),
+            "math": "f64", "value": rhs / dt, "unit": "RHS-iters/s", "ms_per_step": 1e3 * dt / steps,
+            "rhs_iters_per_em_iter": rhs / steps,
+            "max_cg_steps": int(max(int(i.max().item()) for i in iters)),
+            "solve_kernel_ms_per_em_iter": round(ms / steps, 3),
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                         "peak": FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / FP64_VECTOR_TFLOPS, 4), "traffic": None,
+                         "kernel": "k_fourier_cg<%d>" % int(np.log2(N)),
+                         "avg_launch_us": round(1e3 * ms / max(launches, 1), 2),
+                         "flop_per_launch": flops / max(launches, 1)}}
 
 
 def workload_name(cfg):
@@ -349,6 +404,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.config.startswith("fourier"):
+        # the partial-Fourier workload alone (for profiling its solve kernel)
+        r = run_fourier_workload(torch, Cmtcs, a.config, dev, a.warmup, a.steps)
+        print(json.dumps(r))
+        return
     w = synth.make(a.config)
     cfg = w.cfg
     rows = int(w.row_off[-1])
@@ -400,7 +460,8 @@ def main():
         print("forms done", file=sys.stderr, flush=True)
         # the same shape with beta = 1 and alpha in (1, 2), where every form can meet its bar
         wc = synth.make(a.config, sigma=1.0)
-        rc = run_workload(torch, Cmtcs, wc, dev, a.config, "f64", a.phi16, a.refine_every, 1, 2)
+        rc = run_workload(torch, Cmtcs, wc, dev, a.config, "f64", a.phi16, a.refine_every, 1, 2,
+                          alpha0=wc.alpha0 + 1.0)
         rc.pop("_model")[0].close()
         res["detail"]["forms_well_conditioned"] = {
             "workload": "as above with beta = 1, alpha^0 + 1",
@@ -408,6 +469,8 @@ def main():
                           rc["ms_per_step"], alpha0=wc.alpha0 + 1.0)}
         print("well-conditioned forms done", file=sys.stderr, flush=True)
     if main_run and not a.no_configs:
+        res["detail"]["fourier"] = run_fourier_workload(torch, Cmtcs, "fourier", dev, 1, 2)
+        print("fourier done", file=sys.stderr, flush=True)
         configs = {}
         for name, math in (("fp32", "f32"), ("batch", "f32"), ("batch", "f64")):
             wk = synth.make(name)

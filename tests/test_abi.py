@@ -76,6 +76,17 @@ def test_create_rejects_bad_problems(over, frag):
     assert frag in lib.cmtcs_last_error().decode()
 
 
+@pytest.mark.parametrize("over,frag", [
+    (dict(op=7), "unknown sensing operator"),
+    (dict(op=_lib.CMTCS_OP_PARTIAL_FOURIER, freq=1, math=_lib.CMTCS_MATH_F32), "MATH_F64"),
+    (dict(op=_lib.CMTCS_OP_PARTIAL_FOURIER, freq=1, D=48), "power of two"),
+    (dict(op=_lib.CMTCS_OP_PARTIAL_FOURIER, freq=1, D=8192), "power of two"),
+    (dict(op=_lib.CMTCS_OP_PARTIAL_FOURIER, freq=None, D=64), "freq and y"),
+])
+def test_create_rejects_bad_fourier_problems(over, frag):
+    test_create_rejects_bad_problems(over, frag)
+
+
 def test_null_arguments():
     lib = _lib.load()
     assert lib.cmtcs_create(None, None, None) == _lib.CMTCS_E_INVALID
