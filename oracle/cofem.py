@@ -61,7 +61,7 @@ def responsibilities(ell, log_pi):
 
 
 def estep(Phi, b, beta, alpha, log_pi, K, policy, seed=1, it=0, probes=None, t_sel=None,
-          common_probes=False):
+          common_probes=False, precond=None):
     """One CoFEM E-step (Alg. 2, inner loop) for the tasks in ``t_sel`` (default: all).
 
     Phi: list of N_t x D arrays; b: list of D vectors (from ``rhs``); alpha: C x D; log_pi: C.
@@ -70,6 +70,13 @@ def estep(Phi, b, beta, alpha, log_pi, K, policy, seed=1, it=0, probes=None, t_s
     c = 0 (common random numbers across clusters; a variance-reduction variant, not in the
     paper: each (t, c) estimator keeps its distribution, and the Monte Carlo errors of ell_tc
     and ell_tc' become correlated, so their difference, which decides q_t, varies less).
+    precond="jacobi" (not in the paper): CG preconditioned by M = diag(A_tc) (cg.pcg), with the
+    estimators adjusted so that one solve per probe still serves both: the probe right-hand side
+    is M^1/2 p, so that the preconditioned run is CG on A-hat = M^-1/2 A M^-1/2 started at p and
+    its Lanczos quadrature (Eqs. (tridiag), (hutch-trace)) estimates p^T log(A-hat) p; then
+        log det Sigma = -(sum_d log M_dd + log det A-hat)  ->  nu-bar = -(sum log M + mean tau),
+        s = M^-1/2 (.) (1/K) sum_k p_k (.) A^-1 M^1/2 p_k,
+    unbiased for diag Sigma since E[p_d (A^-1 M^1/2 p)_d] = (A^-1)_dd M_dd^1/2.
     Returns a dict of FP64 arrays indexed [task-in-selection][c](...).
     """
     alpha = np.asarray(alpha, np.float64)
@@ -95,15 +102,25 @@ def estep(Phi, b, beta, alpha, log_pi, K, policy, seed=1, it=0, probes=None, t_s
     alpha_col = np.repeat(alpha, K + 1, axis=0).T                     # D x R
     for a, t in enumerate(tasks):
         Pt = np.asarray(Phi[t], np.float64)
+        if precond == "jacobi":
+            mdiag = beta * (Pt * Pt).sum(axis=0)[:, None] + alpha.T     # D x C: diag(A_tc)
+        elif precond is not None:
+            raise ValueError("precond must be None or 'jacobi'")
         B = np.zeros((D, R))
         for c in range(C):
             B[:, c * (K + 1)] = b[t]
-            B[:, c * (K + 1) + 1:(c + 1) * (K + 1)] = P_all[a, c].T
+            pr = P_all[a, c].T
+            if precond == "jacobi":
+                pr = np.sqrt(mdiag[:, c:c + 1]) * pr
+            B[:, c * (K + 1) + 1:(c + 1) * (K + 1)] = pr
 
         def apply_A(V, cols, Pt=Pt):
             return beta * (Pt.T @ (Pt @ V)) + alpha_col[:, cols] * V
 
-        X, g, x, it_, st = _cg.cg(apply_A, B, policy)
+        if precond == "jacobi":
+            X, g, x, it_, st = _cg.pcg(apply_A, B, policy, np.repeat(mdiag, K + 1, axis=1))
+        else:
+            X, g, x, it_, st = _cg.cg(apply_A, B, policy)
         gam[a], xis[a] = g, x
         for c in range(C):
             j0 = c * (K + 1)
@@ -114,6 +131,9 @@ def estep(Phi, b, beta, alpha, log_pi, K, policy, seed=1, it=0, probes=None, t_s
                 j = j0 + 1 + k
                 taus[a, c, k] = _slq.quadrature_log(g[j], x[j], float(pk[k] @ pk[k]))
             nu[a, c] = _slq.logdet_estimate(taus[a, c])
+            if precond == "jacobi":
+                s[a, c] /= np.sqrt(mdiag[:, c])
+                nu[a, c] -= np.log(mdiag[:, c]).sum()
             ell[a, c] = nu[a, c] + sum_log_alpha[c] + float(b[t] @ mu[a, c])
             iters[a, c] = it_[j0:j0 + K + 1]
             status[a, c] = st[j0:j0 + K + 1]
@@ -156,7 +176,7 @@ def log_likelihood(ell, log_pi, const):
 
 
 def fit(Phi, y, beta, alpha0, log_pi, K, policy, n_em, seed=1, probes_fn=None, alpha_max=1e10,
-        learn_pi=False, common_probes=False):
+        learn_pi=False, common_probes=False, precond=None):
     """Alg. 2 end to end.  ``probes_fn(it)`` may supply explicit probes per EM iteration.  With
     ``learn_pi`` each M-step also replaces log_pi by ``update_log_pi(q)``."""
     b = rhs(Phi, y, beta)
@@ -168,7 +188,7 @@ def fit(Phi, y, beta, alpha0, log_pi, K, policy, n_em, seed=1, probes_fn=None, a
     for it in range(n_em):
         pr = None if probes_fn is None else probes_fn(it)
         out = estep(Phi, b, beta, alpha, log_pi, K, policy, seed=seed, it=it, probes=pr,
-                    common_probes=common_probes)
+                    common_probes=common_probes, precond=precond)
         hist.append(dict(L=log_likelihood(out["ell"], log_pi, const), alpha=alpha.copy(),
                          q=out["q"].copy(), ell=out["ell"].copy(), log_pi=log_pi.copy()))
         alpha = mstep(out["mu"], out["s"], out["q"], alpha, alpha_max)
