@@ -291,6 +291,26 @@ cmtcs_status_t cmtcs_grad(cmtcs_handle_t h, int32_t R_per_task, const int32_t* c
 cmtcs_status_t cmtcs_apply(cmtcs_handle_t h, const float* alpha, int32_t R_per_task,
                            const int32_t* col_cluster, const void* V, void* AV);
 
+/* The operator of cmtcs_apply without a handle, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ *   AV[t][j] = beta Phi_t^T (Phi_t V[t][j]) + alpha_{col_cluster[t][j]} (.) V[t][j],
+ * the same matrix-core products, with the default tile shapes (no autotuning).  It allocates
+ * nothing: its tile tables, padded copies of V and A V and the intermediate Phi V live in one
+ * statically sized device array of 64 MiB per GPU (held by each GPU the library runs on until
+ * the process ends), and a problem needing more returns CMTCS_E_INVALID (the message gives the
+ * bytes needed).  Every call on a GPU uses that GPU's one array: calls that overlap on one GPU
+ * (from several threads or streams) race and must be serialised by the caller.  The call copies
+ * its small tables to the device and waits for the stream before launching the products, which
+ * then run asynchronously on `stream`.
+ *   prob        a dense problem (op OP_DENSE, math MATH_F64 or MATH_F32, phi_dtype F32); its
+ *               phi, row_off, beta, T, C and D are used, nothing else
+ *   alpha       [C][D] float;  R_per_task >= 1;  col_cluster HOST [T][R_per_task] in 0..C-1
+ *   V, AV       [T][R_per_task][D], double for MATH_F64, float for MATH_F32
+ *   stream      a hipStream_t (NULL = the null stream) */
+cmtcs_status_t cmtcs_apply_noalloc(const cmtcs_problem_t* prob, const float* alpha,
+                                   int32_t R_per_task, const int32_t* col_cluster, const void* V,
+                                   void* AV, void* stream);
+
 /* Kernel timing for measurement: while enabled, each CG step's two operator products and its
  * vector update are bracketed by HIP events on the handle's stream and their durations are
  * summed.  While enabled, the step-by-step CG loop waits for the events every 8 steps and then

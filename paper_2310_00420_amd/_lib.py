@@ -82,6 +82,9 @@ def load():
     lib.cmtcs_grad.restype = st
     lib.cmtcs_apply.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp, vp]
     lib.cmtcs_apply.restype = st
+    lib.cmtcs_apply_noalloc.argtypes = [ctypes.POINTER(Problem), vp, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), vp, vp, vp]
+    lib.cmtcs_apply_noalloc.restype = st
     lib.cmtcs_profile.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
     lib.cmtcs_profile.restype = st

@@ -292,6 +292,31 @@ class Cmtcs:
         return {k: (ms[i], n[i]) for i, k in enumerate(names)}
 
 
+def apply_noalloc(phi, row_off, beta, C, alpha, V, col_cluster, math="f64"):
+    """A V (the operator of Eq. (lin-sys)) through cmtcs_apply_noalloc: no handle, no device
+    allocation inside the library (its buffers live in a static per-GPU array)."""
+    row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
+    T = len(row_off) - 1
+    D = int(phi.shape[1])
+    R = int(V.shape[1])
+    vt = torch.float64 if math == "f64" else torch.float32
+    _need(phi, torch.float32, (int(row_off[-1]), D), "phi")
+    _need(alpha, torch.float32, (int(C), D), "alpha")
+    _need(V, vt, (T, R, D), "V")
+    cc = _cluster_map(col_cluster, T, R)
+    AV = torch.empty_like(V)
+    p = _lib.Problem(T=T, C=int(C), D=D,
+                     row_off=row_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                     phi=phi.data_ptr(), phi_dtype=_lib.CMTCS_F32, phi_f32=None, y=None,
+                     beta=float(beta), math=MATH[math], max_rhs=R, max_iters=1, max_K=0,
+                     op=_lib.CMTCS_OP_DENSE, freq=None)
+    stream = torch.cuda.current_stream(V.device).cuda_stream
+    _lib.check(_lib.load().cmtcs_apply_noalloc(
+        ctypes.byref(p), _ptr(alpha), R, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        _ptr(V), _ptr(AV), ctypes.c_void_p(stream)))
+    return AV
+
+
 def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
         alpha_max=1e10, probes_fn=None, callback=None, graph=False, learn_pi=False,
         common_probes=False):

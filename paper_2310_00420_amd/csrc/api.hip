@@ -2,6 +2,7 @@
 // and the host loop that drives one batched CG solve (Alg. 1 over all right-hand sides of all
 // tasks, Sec. 3.3) per E-step of Alg. 2.
 #include <algorithm>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -700,6 +701,132 @@ cmtcs_status_t check_opts(const cmtcs_handle_s* h, const cmtcs_opts_t* o, bool n
 
 }  // namespace
 
+// ---------------------------------------------------------------------------------------------
+// The operator without a handle (cmtcs_apply_noalloc): every buffer beyond the caller's inputs
+// and outputs lives in one statically sized device array per GPU.  Host code never uses the
+// array's name as an address: the device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`.
+hipError_t scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Dv[t][j] = V[t][j] for j < R, 0 for the padding slots R <= j < Rp.
+template <typename VT>
+__global__ __launch_bounds__(256) void k_pad_cols(const VT* __restrict__ V, VT* __restrict__ Dv,
+                                                  int R, int Rp, int D) {
+  const int col = blockIdx.x;
+  const int t = col / Rp, j = col % Rp;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  Dv[(int64_t)col * D + d] = j < R ? V[((int64_t)t * R + j) * D + d] : (VT)0;
+}
+
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+template <typename VT>
+cmtcs_status_t apply_noalloc(const cmtcs_problem_t* p, const float* alpha, int R,
+                             const int32_t* col_cluster, const void* V, void* AV,
+                             hipStream_t st) {
+  const int T = p->T, C = p->C, D = p->D;
+  const int Rp = col_slots(R);
+  int cand[kMaxTileCands];
+  op_row_candidates(sizeof(VT) == 8, 0, cand);
+  const int fr = cand[0];
+  op_row_candidates(sizeof(VT) == 8, 1, cand);
+  const int ar = cand[0];
+  const int ng = Rp / 16 / group_width(Rp);
+  // host tables: W offsets, tiles of both products, cluster of every column slot
+  std::vector<int64_t> woff(T + 1, 0);
+  std::vector<int4> ft, at;
+  for (int t = 0; t < T; ++t) {
+    const int np = round16((int)(p->row_off[t + 1] - p->row_off[t]));
+    woff[t + 1] = woff[t] + (int64_t)Rp * np;
+    for (int n0 = 0; n0 < np; n0 += tile_step(fr))
+      for (int cg = 0; cg < ng; ++cg) ft.push_back(make_int4(t, n0, cg, 0));
+    for (int d0 = 0; d0 < D; d0 += tile_step(ar))
+      for (int cg = 0; cg < ng; ++cg) at.push_back(make_int4(t, d0, cg, 0));
+  }
+  std::vector<int> colc((size_t)T * Rp, -1);
+  for (int t = 0; t < T; ++t)
+    for (int j = 0; j < R; ++j) colc[(size_t)t * Rp + j] = col_cluster[(size_t)t * R + j];
+  // scratch sections, each 256-byte aligned
+  const size_t vec = (size_t)T * Rp * D * sizeof(VT);
+  const size_t sz[7] = {sizeof(int64_t) * (T + 1), sizeof(int64_t) * (T + 1),
+                        sizeof(int4) * ft.size(), sizeof(int4) * at.size(),
+                        sizeof(int) * colc.size(), vec, (size_t)woff[T] * sizeof(VT)};
+  size_t off[8] = {0};
+  for (int i = 0; i < 7; ++i) off[i + 1] = off[i] + align256(sz[i]);
+  const size_t total = off[7] + align256(vec);   // + A V in the padded layout
+  if (total > kNoAllocScratchBytes)
+    return fail(CMTCS_E_INVALID,
+                "problem too large for cmtcs_apply_noalloc: needs " + std::to_string(total) +
+                    " bytes of scratch, the limit is " + std::to_string(kNoAllocScratchBytes));
+  void* base = nullptr;
+  HIP_TRY(scratch_address(&base), "hipGetSymbolAddress(scratch)");
+  char* b = (char*)base;
+  int64_t* row_off_d = (int64_t*)(b + off[0]);
+  int64_t* w_off_d = (int64_t*)(b + off[1]);
+  int4* fwd = (int4*)(b + off[2]);
+  int4* adj = (int4*)(b + off[3]);
+  int* colc_d = (int*)(b + off[4]);
+  VT* Dv = (VT*)(b + off[5]);
+  VT* W = (VT*)(b + off[6]);
+  VT* AD = (VT*)(b + off[7]);
+  HIP_TRY(hipMemcpyAsync(row_off_d, p->row_off, sz[0], hipMemcpyHostToDevice, st),
+          "hipMemcpyAsync(row_off)");
+  HIP_TRY(hipMemcpyAsync(w_off_d, woff.data(), sz[1], hipMemcpyHostToDevice, st),
+          "hipMemcpyAsync(w_off)");
+  if (!ft.empty())
+    HIP_TRY(hipMemcpyAsync(fwd, ft.data(), sz[2], hipMemcpyHostToDevice, st),
+            "hipMemcpyAsync(fwd tiles)");
+  HIP_TRY(hipMemcpyAsync(adj, at.data(), sz[3], hipMemcpyHostToDevice, st),
+          "hipMemcpyAsync(adj tiles)");
+  HIP_TRY(hipMemcpyAsync(colc_d, colc.data(), sz[4], hipMemcpyHostToDevice, st),
+          "hipMemcpyAsync(colc)");
+  // the host tables above are freed on return: wait for their copies
+  HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize(noalloc tables)");
+  Geometry g;
+  g.T = T; g.C = C; g.D = D; g.R = R; g.Rp = Rp;
+  g.row_off = row_off_d; g.w_off = w_off_d;
+  hipLaunchKernelGGL((k_pad_cols<VT>), dim3(T * Rp, (D + 255) / 256), dim3(256), 0, st,
+                     (const VT*)V, Dv, R, Rp, D);
+  HIP_TRY(hipGetLastError(), "launch(pad_cols)");
+  const float* phi = (const float*)p->phi;
+  HIP_TRY(launch_phi_v<VT>(g, phi, fwd, (int)ft.size(), Dv, W, nullptr, fr, st),
+          "launch(phi_v)");
+  HIP_TRY(launch_phit_w<VT>(g, phi, adj, (int)at.size(), W, Dv, AD, alpha, colc_d, p->beta,
+                            nullptr, ar, st), "launch(phit_w)");
+  CgState s{};
+  s.X = AD;
+  HIP_TRY(launch_solve_output<VT>(g, s, AV, nullptr, nullptr, 0, nullptr, nullptr, st),
+          "launch(copy out)");
+  return CMTCS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void* stream) {
@@ -1058,6 +1185,48 @@ cmtcs_status_t cmtcs_profile(cmtcs_handle_t h, int32_t enable, double* totals_ms
     }
   }
   return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_apply_noalloc(const cmtcs_problem_t* p, const float* alpha,
+                                   int32_t R_per_task, const int32_t* col_cluster, const void* V,
+                                   void* AV, void* stream) {
+  if (p == nullptr) return fail(CMTCS_E_INVALID, "problem is NULL");
+  if (p->T < 1 || p->C < 1) return fail(CMTCS_E_INVALID, "T and C must be >= 1");
+  if (p->D < 16 || p->D % 16 != 0 || p->D > 16384)
+    return fail(CMTCS_E_INVALID, "D must be a positive multiple of 16, at most 16384");
+  if (p->op != CMTCS_OP_DENSE)
+    return fail(CMTCS_E_UNSUPPORTED, "cmtcs_apply_noalloc takes dense problems only");
+  if (p->math != CMTCS_MATH_F64 && p->math != CMTCS_MATH_F32)
+    return fail(CMTCS_E_UNSUPPORTED, "cmtcs_apply_noalloc runs MATH_F64 or MATH_F32");
+  if (p->phi_dtype != CMTCS_F32) return fail(CMTCS_E_INVALID, "phi_dtype must be F32");
+  if (!(p->beta > 0.0)) return fail(CMTCS_E_INVALID, "beta must be > 0");
+  if (p->row_off == nullptr || p->row_off[0] != 0)
+    return fail(CMTCS_E_INVALID, "row_off must be non-NULL with row_off[0] = 0");
+  for (int t = 0; t < p->T; ++t)
+    if (p->row_off[t + 1] < p->row_off[t])
+      return fail(CMTCS_E_INVALID, "row_off must be non-decreasing");
+  if (p->row_off[p->T] > 0 && p->phi == nullptr) return fail(CMTCS_E_INVALID, "phi is NULL");
+  if (R_per_task < 1) return fail(CMTCS_E_INVALID, "R_per_task must be >= 1");
+  if (!alpha || !col_cluster || !V || !AV)
+    return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  for (int64_t i = 0; i < (int64_t)p->T * R_per_task; ++i)
+    if (col_cluster[i] < 0 || col_cluster[i] >= p->C)
+      return fail(CMTCS_E_INVALID, "col_cluster entries must be in 0..C-1");
+  {
+    // 32-bit per-task offsets of the operator products (as checked by cmtcs_create)
+    const int64_t lim = int64_t(1) << 32, slots = col_slots(R_per_task);
+    if (slots * p->D * 8 >= lim)
+      return fail(CMTCS_E_UNSUPPORTED, "column slots * D * 8 bytes must be below 4 GiB");
+    for (int t = 0; t < p->T; ++t) {
+      const int64_t nt = p->row_off[t + 1] - p->row_off[t];
+      if ((nt + 15) / 16 * 16 * p->D * 4 >= lim || slots * ((nt + 15) / 16 * 16) * 8 >= lim)
+        return fail(CMTCS_E_UNSUPPORTED, "a task's block must be below 4 GiB");
+    }
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (p->math == CMTCS_MATH_F64)
+    return apply_noalloc<double>(p, alpha, R_per_task, col_cluster, V, AV, st);
+  return apply_noalloc<float>(p, alpha, R_per_task, col_cluster, V, AV, st);
 }
 
 cmtcs_status_t cmtcs_tiles(cmtcs_handle_t h, int32_t* rows) {

@@ -87,6 +87,27 @@ def test_create_rejects_bad_fourier_problems(over, frag):
     test_create_rejects_bad_problems(over, frag)
 
 
+def test_apply_noalloc_rejects_on_the_host():
+    """Argument errors and problems beyond the static scratch array are reported before any
+    HIP call."""
+    lib = _lib.load()
+    cc = (ctypes.c_int32 * 64)()
+    assert lib.cmtcs_apply_noalloc(None, 1, 1, cc, 1, 1, None) == _lib.CMTCS_E_INVALID
+    p, keep = _problem()
+    assert lib.cmtcs_apply_noalloc(ctypes.byref(p), None, 1, cc, 1, 1, None) == \
+        _lib.CMTCS_E_INVALID
+    p, keep = _problem(op=_lib.CMTCS_OP_PARTIAL_FOURIER, D=64)
+    assert lib.cmtcs_apply_noalloc(ctypes.byref(p), 1, 1, cc, 1, 1, None) == \
+        _lib.CMTCS_E_UNSUPPORTED
+    # 720 column slots x 16384 x 8 bytes of padded right-hand sides alone exceed 64 MiB
+    R = 600
+    big = (ctypes.c_int32 * R)()
+    p, keep = _problem(T=1, D=16384, row_off=np.array([0, 8], np.int64))
+    assert lib.cmtcs_apply_noalloc(ctypes.byref(p), 1, R, big, 1, 1, None) == \
+        _lib.CMTCS_E_INVALID
+    assert "too large" in lib.cmtcs_last_error().decode()
+
+
 def test_null_arguments():
     lib = _lib.load()
     assert lib.cmtcs_create(None, None, None) == _lib.CMTCS_E_INVALID
