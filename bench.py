@@ -20,7 +20,8 @@ sample on the host CPU.  The default FP64 run also reports:
   detail.configs  the plain FP32 configuration (T=32, D=1024) and the ragged batching
                   configuration (T=256, D=2048) timed the same way;
   detail.fourier  the paper's own sensing (Sec. 4): partial-Fourier Phi_t with T=64, C=4,
-                  D=4096, N=1024 frequencies, K=32, sigma 0.05.
+                  D=4096, N=1024 frequencies, K=32, sigma 0.05;
+  detail.jacobi   the timed EM iterations again with Jacobi-preconditioned CG.
 """
 
 import argparse
@@ -268,7 +269,7 @@ def roofline(m, w, math, config, prof, iters):
 
 
 def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup, steps,
-                 unprofiled=False, alpha0=None):
+                 unprofiled=False, alpha0=None, precond=False):
     """Times `steps` EM iterations (E-step + M-step, K probes, the workload's CG policy) after
     `warmup` untimed ones, with HIP-event kernel timing on the library's stream; optionally the
     same iterations again without kernel timing.  Returns the measurements and the host copy of
@@ -280,7 +281,7 @@ def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup
     alpha = torch.tensor(a0, dtype=torch.float32, device=dev)
     log_pi = torch.tensor(w.log_pi, device=dev)
     kw = dict(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters, seed=1,
-              refine_every=refine_every if math == "mixed" else 0)
+              refine_every=refine_every if math == "mixed" else 0, precond=precond)
     first = None
 
     def em_iteration(it):
@@ -469,6 +470,15 @@ def main():
                           rc["ms_per_step"], alpha0=wc.alpha0 + 1.0)}
         print("well-conditioned forms done", file=sys.stderr, flush=True)
     if main_run and not a.no_configs:
+        # the same EM iterations with Jacobi-preconditioned CG (not in the paper)
+        rp = run_workload(torch, Cmtcs, w, dev, a.config, "f64", a.phi16, a.refine_every,
+                          a.warmup, a.steps, precond=True)
+        rp.pop("_model")[0].close()
+        rp.pop("_first")
+        res["detail"]["jacobi"] = {k: rp[k] for k in ("value", "ms_per_step",
+                                                       "rhs_iters_per_em_iter", "max_cg_steps",
+                                                       "kernel_ms_per_em_iter")}
+        print("jacobi done", file=sys.stderr, flush=True)
         res["detail"]["fourier"] = run_fourier_workload(torch, Cmtcs, "fourier", dev, 1, 2)
         print("fourier done", file=sys.stderr, flush=True)
         configs = {}

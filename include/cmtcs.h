@@ -159,6 +159,18 @@ typedef struct {
                                errors of ell_tc and ell_tc' become correlated, so that their
                                difference, which decides q_t, varies less.  0 = independent
                                probes per (t, c) as in Alg. 2 */
+  int32_t precond;          /* 0: CG as in Alg. 1.  1: Jacobi-preconditioned CG (not in the
+                               paper; dense problems, MATH_F64 / MATH_F32), M = diag(A_tc) =
+                               beta diag(Phi_t^T Phi_t) + alpha_c: z = M^-1 r, gamma_u =
+                               r.z / d.Ad, xi_u = r'.z' / r.z, d = z' + xi d, the stop rule on the
+                               plain ||r||.  The iteration is CG on M^-1/2 A M^-1/2, so in
+                               cmtcs_estep each probe's right-hand side is M^1/2 p (its Lanczos
+                               run then starts at p and Eq. (hutch-trace) estimates
+                               p^T log(M^-1/2 A M^-1/2) p), the log-determinant adds
+                               -sum_d log M_dd, and s = M^-1/2 (.) (1/K) sum_k p_k (.) x_k, which
+                               stays unbiased for diag Sigma.  Fewer steps where alpha spreads
+                               over decades (pruned coordinates).  cmtcs_solve returns A^-1 B
+                               and the preconditioned gamma_u, xi_u */
 } cmtcs_opts_t;
 
 /* Optional per-right-hand-side outputs, device pointers, each may be NULL.  For cmtcs_estep

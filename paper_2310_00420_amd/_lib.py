@@ -36,7 +36,7 @@ class Opts(ctypes.Structure):
                 ("refine_every", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("em_iter", ctypes.c_uint64), ("probes", ctypes.c_void_p),
                 ("alpha_max", ctypes.c_double), ("graph", ctypes.c_int32),
-                ("common_probes", ctypes.c_int32)]
+                ("common_probes", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class CgStats(ctypes.Structure):

@@ -118,18 +118,19 @@ class Cmtcs:
 
     @staticmethod
     def _opts(K=0, fixed_iters=0, tol=1e-6, max_iters=200, seed=1, em_iter=0, probes=None,
-              alpha_max=1e10, refine_every=0, graph=False, common_probes=False):
+              alpha_max=1e10, refine_every=0, graph=False, common_probes=False, precond=False):
         return _lib.Opts(K=K, max_iters=max_iters, fixed_iters=fixed_iters, tol=tol,
                          refine_every=refine_every, seed=seed, em_iter=em_iter,
                          probes=None if probes is None else probes.data_ptr(),
                          alpha_max=alpha_max, graph=int(bool(graph)),
-                         common_probes=int(bool(common_probes)))
+                         common_probes=int(bool(common_probes)), precond=int(bool(precond)))
 
     def estep(self, alpha, log_pi, K, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
               em_iter=0, probes=None, stats=False, refine_every=0, graph=False,
-              common_probes=False):
+              common_probes=False, precond=False):
         """One E-step (Alg. 2 inner loop).  Returns a dict of device tensors.  With
-        ``common_probes`` every cluster of a task uses the same generated probes."""
+        ``common_probes`` every cluster of a task uses the same generated probes; with
+        ``precond`` the solves are Jacobi-preconditioned (see cmtcs_opts_t.precond)."""
         self._check_stream()
         T, C, D, dev = self.T, self.C, self.D, self.device
         _need(alpha, torch.float32, (C, D), "alpha")
@@ -153,7 +154,7 @@ class Cmtcs:
                               out["k_eff"].data_ptr())
         o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
                        em_iter=em_iter, probes=probes, refine_every=refine_every, graph=graph,
-                       common_probes=common_probes)
+                       common_probes=common_probes, precond=precond)
         _lib.check(_lib.load().cmtcs_estep(
             self._h, _ptr(alpha), _ptr(log_pi), ctypes.byref(o), _ptr(out["mu"]), _ptr(out["s"]),
             _ptr(out["logdet"]), _ptr(out["ell"]), _ptr(out["q"]),
@@ -184,7 +185,7 @@ class Cmtcs:
 
     def em_iter(self, alpha, log_pi, K, out=None, fixed_iters=0, tol=1e-6, max_iters=200,
                 seed=1, em_iter=0, probes=None, alpha_max=1e10, graph=False,
-                common_probes=False):
+                common_probes=False, precond=False):
         """One EM iteration (Alg. 2): E-step from ``alpha``, then the M-step into ``alpha`` (in
         place).  ``out`` (the dict a previous call returned) is reused for the outputs, so that
         with ``graph`` the recorded iteration replays on the same buffers."""
@@ -201,14 +202,14 @@ class Cmtcs:
                        q=torch.empty(T, C, dtype=torch.float64, device=dev))
         o = self._opts(K=K, fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, seed=seed,
                        em_iter=em_iter, probes=probes, alpha_max=alpha_max, graph=graph,
-                       common_probes=common_probes)
+                       common_probes=common_probes, precond=precond)
         _lib.check(_lib.load().cmtcs_em_iter(
             self._h, _ptr(alpha), _ptr(log_pi), ctypes.byref(o), _ptr(out["mu"]), _ptr(out["s"]),
             _ptr(out["logdet"]), _ptr(out["ell"]), _ptr(out["q"])))
         return out
 
     def solve(self, alpha, B, col_cluster, fixed_iters=0, tol=1e-6, max_iters=200,
-              coefs=False, stats=False, graph=False):
+              coefs=False, stats=False, graph=False, precond=False):
         """X[t][j] = A_{t, col_cluster[j]}^-1 B[t][j] by CG (Alg. 1)."""
         self._check_stream()
         T, C, D = self.T, self.C, self.D
@@ -228,7 +229,8 @@ class Cmtcs:
             out["iters"] = torch.empty(T, R, dtype=torch.int32, device=self.device)
             out["status"] = torch.empty(T, R, dtype=torch.uint8, device=self.device)
             st = _lib.CgStats(out["iters"].data_ptr(), out["status"].data_ptr(), None, None, None)
-        o = self._opts(fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, graph=graph)
+        o = self._opts(fixed_iters=fixed_iters, tol=tol, max_iters=max_iters, graph=graph,
+                       precond=precond)
         _lib.check(_lib.load().cmtcs_solve(
             self._h, _ptr(alpha), R, cc.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(B),
             _ptr(X), _ptr(g), _ptr(x), ctypes.byref(o),
@@ -319,14 +321,15 @@ def apply_noalloc(phi, row_off, beta, C, alpha, V, col_cluster, math="f64"):
 
 def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
         alpha_max=1e10, probes_fn=None, callback=None, graph=False, learn_pi=False,
-        common_probes=False):
+        common_probes=False, precond=False):
     """CoFEM (Alg. 2): n_em iterations of E-step + M-step from alpha0, then a_t = argmax_c q_tc
     (lowest c on ties) and mu_{t, a_t} from the last E-step.  With ``graph`` each iteration is
     one replay of the recorded EM iteration (cmtcs_em_iter), on output buffers reused from one
     iteration to the next; ``callback(it, alpha, out)`` then sees alpha as the E-step used it
     (a copy) and the outputs before the next iteration overwrites them.  With ``learn_pi`` each
     M-step also updates the cluster weights (cmtcs_mstep_pi) on a copy of ``log_pi``, returned
-    as "log_pi".  ``common_probes``: every cluster of a task uses the same generated probes."""
+    as "log_pi".  ``common_probes``: every cluster of a task uses the same generated probes.
+    ``precond``: Jacobi-preconditioned solves (cmtcs_opts_t.precond)."""
     alpha = alpha0.clone()
     log_pi = log_pi.clone() if learn_pi else log_pi
     out = None
@@ -336,7 +339,8 @@ def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, 
             before = alpha.clone() if callback is not None else None
             out = model.em_iter(alpha, log_pi, K, out=out, fixed_iters=fixed_iters, tol=tol,
                                 max_iters=max_iters, seed=seed, em_iter=it, probes=pr,
-                                alpha_max=alpha_max, graph=True, common_probes=common_probes)
+                                alpha_max=alpha_max, graph=True, common_probes=common_probes,
+                                precond=precond)
             if callback is not None:
                 callback(it, before, out)
             if learn_pi:
@@ -344,7 +348,7 @@ def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, 
             continue
         out = model.estep(alpha, log_pi, K, fixed_iters=fixed_iters, tol=tol,
                           max_iters=max_iters, seed=seed, em_iter=it, probes=pr, graph=graph,
-                          common_probes=common_probes)
+                          common_probes=common_probes, precond=precond)
         if callback is not None:
             callback(it, alpha, out)
         model.mstep(out["mu"], out["s"], out["q"], alpha, alpha_max=alpha_max)

@@ -50,6 +50,12 @@ struct cmtcs_handle_s {
   const int* freq = nullptr;
   int* hcount = nullptr;
   int* bad_freq = nullptr;
+  // Jacobi preconditioner (opts.precond): beta diag(Phi_t^T Phi_t) per task (once), and per call
+  // M = diag(A_tc) with sum_d log M; pc_on is set by each entry point for its own launches
+  double* mbase = nullptr;
+  double* mdiag = nullptr;
+  double* slogm = nullptr;
+  bool pc_on = false;
   int max_rhs = 0, max_iters = 0, max_K = 0, Rp_max = 0;
   size_t vbytes = 8;
   std::vector<int64_t> row_off;
@@ -96,10 +102,10 @@ struct cmtcs_handle_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   struct GraphKey {
-    const float* alpha; int R, Rp, steps, fixed, fwd_rows, adj_rows;
+    const float* alpha; int R, Rp, steps, fixed, fwd_rows, adj_rows; bool pc;
     bool operator==(const GraphKey& o) const {
       return alpha == o.alpha && R == o.R && Rp == o.Rp && steps == o.steps && fixed == o.fixed &&
-             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows;
+             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows && pc == o.pc;
     }
   } graph_key{};
   // recorded EM iteration (cmtcs_em_iter with opts.graph): E-step and M-step as one graph
@@ -107,13 +113,13 @@ struct cmtcs_handle_s {
   hipGraphExec_t em_exec = nullptr;
   struct EmKey {
     const void* p[8];   // alpha, log_pi, mu, s, logdet, ell, q, probes
-    int K, steps, fixed, R, Rp, fwd_rows, adj_rows, crn;
+    int K, steps, fixed, R, Rp, fwd_rows, adj_rows, crn, pc;
     double tol, alpha_max;
     bool operator==(const EmKey& o) const {
       for (int i = 0; i < 8; ++i)
         if (p[i] != o.p[i]) return false;
       return K == o.K && steps == o.steps && fixed == o.fixed && R == o.R && Rp == o.Rp &&
-             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows && crn == o.crn &&
+             fwd_rows == o.fwd_rows && adj_rows == o.adj_rows && crn == o.crn && pc == o.pc &&
              tol == o.tol && alpha_max == o.alpha_max;
     }
   } em_key{};
@@ -157,7 +163,7 @@ struct cmtcs_handle_s {
   // stream; the recording is reused while its key matches.
   template <typename VT>
   cmtcs_status_t run_cg_graph(const Geometry& g, const float* alpha, int steps, int fixed) {
-    const GraphKey key{alpha, g.R, g.Rp, steps, fixed, fwd_rows, adj_rows};
+    const GraphKey key{alpha, g.R, g.Rp, steps, fixed, fwd_rows, adj_rows, pc_on};
     if (graph_exec == nullptr || !(key == graph_key)) {
       if (graph_exec) { (void)hipGraphExecDestroy(graph_exec); graph_exec = nullptr; }
       if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
@@ -258,6 +264,7 @@ struct cmtcs_handle_s {
     s.gam = gam; s.xi = xi; s.act = act;
     s.alpha = nullptr; s.colc = colc; s.beta = beta;
     s.d16 = nullptr; s.d16_kind = 0; s.d16_ld = 0;
+    s.mdiag = pc_on ? mdiag : nullptr;
     return s;
   }
 
@@ -470,6 +477,7 @@ struct cmtcs_handle_s {
   template <typename VT>
   cmtcs_status_t apply(const float* alpha, int R, const int32_t* col_cluster, const void* V,
                        void* AV) {
+    pc_on = false;
     const int Rp = col_slots(R);
     if (fourier) {
       const Geometry g = geom(R, Rp);
@@ -505,6 +513,7 @@ struct cmtcs_handle_s {
   template <typename VT>
   cmtcs_status_t grad(int R, const int32_t* col_cluster, const void* Xs, const void* Lam,
                       double y_coef, float* dalpha, float* dphi) {
+    pc_on = false;
     const int Rp = col_slots(2 * R);
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
@@ -533,6 +542,8 @@ struct cmtcs_handle_s {
     if (!fourier) rs = tune<VT>(g, alpha);
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_set_key(key_d, key, st), "launch(set_key)");
+    pc_on = o.precond != 0;
+    if (pc_on) HIP_TRY(launch_jacobi(g, mbase, alpha, mdiag, slogm, st), "launch(jacobi)");
     RhsSource src;
     src.kind = 0; src.b = b; src.B = nullptr; src.K = K; src.keyp = key_d; src.probes = o.probes;
     src.crn = o.common_probes;
@@ -551,7 +562,7 @@ struct cmtcs_handle_s {
     HIP_TRY(launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, st),
             "launch(slq)");
     HIP_TRY(launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q,
-                            keff, st),
+                            keff, pc_on ? slogm : nullptr, st),
             "launch(resp)");
     if (stats != nullptr) {
       HIP_TRY(launch_stats_estep(g, cg(), K, ok, keff, stats->iters, stats->status, stats->k_eff,
@@ -579,6 +590,7 @@ struct cmtcs_handle_s {
     src.crn = o.common_probes;
     // the cluster map is rewritten here (other calls on the handle reuse its buffer)
     hipError_t e = launch_fill_colc(colc, T, g.R, g.Rp, K, nullptr, s);
+    if (e == hipSuccess && pc_on) e = launch_jacobi(g, mbase, alpha, mdiag, slogm, s);
     if (e == hipSuccess) e = launch_cg_init<VT>(g, cg(), src, fixed ? 0.0 : o.tol, steps, s);
     if (e == hipSuccess) e = cg_steps_all<VT>(g, alpha, steps, fixed, s);
     if (e == hipSuccess)
@@ -588,7 +600,7 @@ struct cmtcs_handle_s {
       e = launch_slq(g, cg(), K, steps, (double)D, slq_ws, tau, ok, rmin, rmax, slq_lds, s);
     if (e == hipSuccess)
       e = launch_resp<VT>(g, cg(), K, (const VT*)b, tau, ok, slog, log_pi, logdet, ell, q, keff,
-                          s);
+                          pc_on ? slogm : nullptr, s);
     if (e == hipSuccess) e = launch_mstep(T, C, D, mu, sd, q, o.alpha_max, alpha, s);
     return e;
   }
@@ -616,8 +628,10 @@ struct cmtcs_handle_s {
     rs = tune<VT>(g, alpha);   // trial launches happen here, never inside a recording
     if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_set_key(key_d, probe_key(o.seed, o.em_iter), st), "launch(set_key)");
+    pc_on = o.precond != 0;
     const EmKey key{{alpha, log_pi, mu, sd, logdet, ell, q, o.probes}, K, steps, fixed, R, Rp,
-                    fwd_rows, adj_rows, o.common_probes, fixed ? 0.0 : o.tol, o.alpha_max};
+                    fwd_rows, adj_rows, o.common_probes, o.precond,
+                    fixed ? 0.0 : o.tol, o.alpha_max};
     if (em_exec == nullptr || !(key == em_key)) {
       if (em_exec) { (void)hipGraphExecDestroy(em_exec); em_exec = nullptr; }
       if (em_graph) { (void)hipGraphDestroy(em_graph); em_graph = nullptr; }
@@ -659,6 +673,8 @@ struct cmtcs_handle_s {
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = B; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
     src.crn = 0;
+    pc_on = o.precond != 0;
+    if (pc_on) HIP_TRY(launch_jacobi(g, mbase, alpha, mdiag, slogm, st), "launch(jacobi)");
     if (fourier) {
       rs = run_fourier(g, alpha, 0, src, fixed ? 0.0 : o.tol, steps, fixed);
     } else {
@@ -691,6 +707,10 @@ cmtcs_status_t check_opts(const cmtcs_handle_s* h, const cmtcs_opts_t* o, bool n
   }
   if (o->common_probes != 0 && o->common_probes != 1)
     return fail(CMTCS_E_INVALID, "common_probes must be 0 or 1");
+  if (o->precond != 0 && o->precond != 1) return fail(CMTCS_E_INVALID, "precond must be 0 or 1");
+  if (o->precond && (h->math == CMTCS_MATH_MIXED || h->fourier))
+    return fail(CMTCS_E_UNSUPPORTED,
+                "precond is available for dense problems in MATH_F64 and MATH_F32 only");
   if (need_K) {
     if (o->K < 1 || o->K > h->max_K) return fail(CMTCS_E_INVALID, "K must be in 1..max_K");
     if ((int64_t)h->C * (o->K + 1) > h->max_rhs)
@@ -954,6 +974,9 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   } else {
     A(&h->Rv, vec); A(&h->Dv, vec); A(&h->AD, vec);
     A(&h->W, Rpm * np_sum * h->vbytes);
+    A(&h->mbase, sizeof(double) * T * D);
+    A(&h->mdiag, sizeof(double) * T * C * D);
+    A(&h->slogm, sizeof(double) * T * C);
   }
   A(&h->b, T * D * h->vbytes);
   A(&h->rr, sizeof(double) * T * Rpm);
@@ -1009,6 +1032,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
                                h->st);
     else if (f64) e = launch_rhs<double>(g, h->phi, h->y, h->beta, (double*)h->b, h->st);
     else e = launch_rhs<float>(g, h->phi, h->y, h->beta, (float*)h->b, h->st);
+    if (e == hipSuccess && !fourier) e = launch_colnorm(g, h->phi, h->beta, h->mbase, h->st);
   }
   if (e == hipSuccess && fourier)
     e = hipMemcpyAsync(&bad, h->bad_freq, sizeof(int), hipMemcpyDeviceToHost, h->st);

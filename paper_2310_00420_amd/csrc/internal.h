@@ -74,6 +74,25 @@ __device__ inline double probe_entry(uint64_t key, int t, int c, int k, int d, i
 }
 
 // ---------------------------------------------------------------------------------------------
+// Fixed-order block reduction of two doubles at once; every thread receives both sums.  `sh`
+// needs 2 BS/64 doubles of shared memory.
+template <int BS>
+__device__ inline d2 block_sum2(double a, double b, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { sh[2 * w] = a; sh[2 * w + 1] = b; }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < BS / 64; ++i) { sa += sh[2 * i]; sb += sh[2 * i + 1]; }
+  return d2{sa, sb};
+}
+
 // Fixed-order block reduction of doubles (deterministic run to run).  All threads of the block
 // must call it; every thread receives the sum.  `sh` needs BS/64 doubles of shared memory.
 template <int BS>
@@ -210,6 +229,10 @@ struct CgState {
   void* d16;
   int d16_kind;
   int64_t d16_ld;   // pitch of d16's columns (elements)
+  // Jacobi preconditioner (not in the paper): M = diag(A_tc), [T][C][D] FP64, or null for plain
+  // CG.  With it, rr holds r.z (z = M^-1 r), d is built from z, and the stop rule still tests
+  // the unpreconditioned ||r||; probe right-hand sides are M^1/2 p.
+  const double* mdiag;
 };
 // Source of the right-hand sides for cg_init.
 struct RhsSource {
@@ -314,11 +337,19 @@ template <typename VT>
 hipError_t launch_rhs(const Geometry& g, const float* phi, const float* y, double beta, VT* b,
                       hipStream_t st);
 hipError_t launch_sum_log_alpha(int C, int D, const float* alpha, double* slog, hipStream_t st);
+// Jacobi preconditioner of an E-step or solve: mdiag[t][c][d] = mbase[t][d] + alpha[c][d]
+// (mbase = beta diag(Phi_t^T Phi_t), computed once per handle by launch_colnorm) and
+// slogm[t][c] = sum_d log mdiag[t][c][d].
+hipError_t launch_colnorm(const Geometry& g, const float* phi, double beta, double* mbase,
+                          hipStream_t st);
+hipError_t launch_jacobi(const Geometry& g, const double* mbase, const float* alpha,
+                         double* mdiag, double* slogm, hipStream_t st);
+
 template <typename VT>
 hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
                        const double* tau, const uint8_t* ok, const double* slog,
                        const double* log_pi, double* logdet, double* ell, double* q,
-                       int* keff, hipStream_t st);
+                       int* keff, const double* slogm, hipStream_t st);
 hipError_t launch_mstep(int T, int C, int D, const float* mu, const float* sdiag,
                         const double* q, double alpha_max, float* alpha, hipStream_t st);
 hipError_t launch_update_pi(int T, int C, const double* q, double* log_pi, hipStream_t st);

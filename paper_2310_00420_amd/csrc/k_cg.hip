@@ -13,7 +13,9 @@
 
 namespace cmtcs {
 
-template <typename VT, int BS, int EPT>
+// PC: Jacobi-preconditioned start (mdiag = M = diag(A_tc) per (t, c)): probe right-hand sides
+// are M^1/2 p, z = M^-1 r, d = z, rr holds r.z, and thr is tol^2 ||b||^2 on the plain residual.
+template <typename VT, int BS, int EPT, bool PC>
 __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restrict__ Rv,
                                                 VT* __restrict__ Dv, double* __restrict__ rr,
                                                 double* __restrict__ thr,
@@ -23,8 +25,10 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
                                                 const VT* __restrict__ B, int K,
                                                 const uint64_t* __restrict__ keyp,
                                                 const int8_t* __restrict__ probes, double tol2,
-                                                int C, int R, int Rp, int D, int crn) {
-  __shared__ double sh[BS / 64];
+                                                int C, int R, int Rp, int D, int crn,
+                                                const double* __restrict__ mdiag,
+                                                const int* __restrict__ colc) {
+  __shared__ double sh[2 * (BS / 64)];
   const int col = blockIdx.x;
   const int t = col / Rp, j = col % Rp;
   const int64_t base = (int64_t)col * D;
@@ -43,7 +47,9 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
     k = j % (K + 1);
     if (probes == nullptr) key = *keyp;
   }
-  double acc = 0.0;
+  const double* mcol = nullptr;
+  if constexpr (PC) mcol = mdiag + ((int64_t)t * C + (kind == 0 ? c : colc[col])) * D;
+  double acc = 0.0, accz = 0.0;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int d = threadIdx.x + e * BS;
@@ -51,20 +57,38 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
     VT v;
     if (kind == 0) {
       if (k == 0) v = b[(int64_t)t * D + d];
-      else if (probes != nullptr)
-        v = (VT)probes[(((int64_t)t * C + c) * K + (k - 1)) * D + d];
-      else v = (VT)probe_entry(key, t, crn ? 0 : c, k - 1, d, C, K, D);
+      else {
+        double pv = probes != nullptr
+                        ? (double)probes[(((int64_t)t * C + c) * K + (k - 1)) * D + d]
+                        : probe_entry(key, t, crn ? 0 : c, k - 1, d, C, K, D);
+        if constexpr (PC) pv *= sqrt(mcol[d]);
+        v = (VT)pv;
+      }
     } else {
       v = B[((int64_t)t * R + j) * D + d];
     }
     X[base + d] = 0;
     Rv[base + d] = v;
-    Dv[base + d] = v;
+    if constexpr (PC) {
+      const VT z = (VT)((double)v / mcol[d]);
+      Dv[base + d] = z;
+      accz += (double)v * (double)z;
+    } else {
+      Dv[base + d] = v;
+    }
     acc += (double)v * (double)v;
   }
-  const double r0 = block_sum<BS>(acc, sh);
+  double r0, rz0;
+  if constexpr (PC) {
+    const d2 sums = block_sum2<BS>(acc, accz, sh);
+    r0 = sums[0];
+    rz0 = sums[1];
+  } else {
+    r0 = block_sum<BS>(acc, sh);
+    rz0 = r0;
+  }
   if (threadIdx.x == 0) {
-    rr[col] = r0;
+    rr[col] = rz0;
     thr[col] = tol2 * r0;
     iters[col] = 0;
     uint8_t st;
@@ -78,7 +102,9 @@ __global__ __launch_bounds__(BS) void k_cg_init(VT* __restrict__ X, VT* __restri
 
 // One step u of Alg. 1 for every active right-hand side (Alg. 1, lines 3-7):
 //   gamma = r.r / d.Ad;  x += gamma d;  r -= gamma Ad;  xi = r'.r' / r.r;  d = r' + xi d.
-template <typename VT, int BS, int EPT>
+// PC (Jacobi, z = M^-1 r): gamma = r.z / d.Ad, xi = r'.z' / r.z, d = z' + xi d; the stop rule
+// tests r'.r'.
+template <typename VT, int BS, int EPT, bool PC>
 __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __restrict__ Rv,
                                                   VT* __restrict__ Dv,
                                                   const VT* __restrict__ AD,
@@ -93,8 +119,9 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
                                                   const float* __restrict__ alpha,
                                                   const int* __restrict__ colc, double beta,
                                                   void* __restrict__ d16, int d16_kind,
-                                                  int64_t d16_ld) {
-  __shared__ double sh[BS / 64];
+                                                  int64_t d16_ld,
+                                                  const double* __restrict__ mdiag, int C) {
+  __shared__ double sh[2 * (BS / 64)];
   const int t = blockIdx.x / R, j = blockIdx.x % R;
   const int64_t idx = (int64_t)t * Rp + j;
   if (state[idx] != kActive) return;
@@ -176,18 +203,41 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
     if (threadIdx.x == 0) gam[(int64_t)u * T * Rp + idx] = g;
     return;
   }
-  const double rrn = block_sum<BS>(pr, sh);
-  const double x_ = rrn / rr_old;
+  double rrn, rzn;
+  if constexpr (PC) {
+    // z = M^-1 r' overwrites the copy of A d, no longer needed
+    const double* mcol = mdiag + ((int64_t)t * C + colc[idx]) * D;
+    double pz = 0.0;
+#pragma unroll
+    for (int e0 = 0; e0 < EPT; e0 += P) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int d = el(e0) + q;
+        if (el(e0) < D) {
+          av[e0 + q] = (VT)((double)rv[e0 + q] / mcol[d]);
+          pz += (double)rv[e0 + q] * (double)av[e0 + q];
+        }
+      }
+    }
+    const d2 sums = block_sum2<BS>(pr, pz, sh);
+    rrn = sums[0];
+    rzn = sums[1];
+  } else {
+    rrn = block_sum<BS>(pr, sh);
+    rzn = rrn;
+  }
+  const double x_ = rzn / rr_old;
   const VT xv_ = (VT)x_;
 #pragma unroll
   for (int e0 = 0; e0 < EPT; e0 += P) {
     const int d = el(e0);
     if (d < D) {
       store(Rv, e0, [&](int q) { return rv[e0 + q]; });
-      store(Dv, e0, [&](int q) { return rv[e0 + q] + xv_ * dv[e0 + q]; });
+      if constexpr (PC) store(Dv, e0, [&](int q) { return av[e0 + q] + xv_ * dv[e0 + q]; });
+      else store(Dv, e0, [&](int q) { return rv[e0 + q] + xv_ * dv[e0 + q]; });
 #pragma unroll
       for (int q = 0; q < P; ++q) {
-        const VT dn = rv[e0 + q] + xv_ * dv[e0 + q];
+        const VT dn = (PC ? av[e0 + q] : rv[e0 + q]) + xv_ * dv[e0 + q];
         if (d16_kind == 1) ((__bf16*)d16)[idx * d16_ld + d + q] = (__bf16)(float)dn;
         else if (d16_kind == 2) ((_Float16*)d16)[idx * d16_ld + d + q] = (_Float16)(float)dn;
       }
@@ -197,10 +247,10 @@ __global__ __launch_bounds__(BS) void k_cg_update(VT* __restrict__ X, VT* __rest
     const int64_t ncol = (int64_t)T * Rp;
     gam[(int64_t)u * ncol + idx] = g;
     xi[(int64_t)u * ncol + idx] = x_;
-    rr[idx] = rrn;
+    rr[idx] = rzn;
     iters[idx] = u + 1;
     uint8_t st = kActive;
-    if (!isfinite(rrn)) st = CMTCS_CG_BREAKDOWN;
+    if (!isfinite(rrn) || !isfinite(rzn)) st = CMTCS_CG_BREAKDOWN;
     else if (rrn == 0.0 || (fixed == 0 && rrn <= thr[idx])) st = CMTCS_CG_CONVERGED;
     else if (u + 1 >= steps) st = fixed ? CMTCS_CG_CONVERGED : CMTCS_CG_MAX_ITER;
     state[idx] = st;
@@ -215,7 +265,8 @@ __global__ __launch_bounds__(256) void k_estep_finalize(const VT* __restrict__ X
                                                         const int8_t* __restrict__ probes,
                                                         float* __restrict__ mu,
                                                         float* __restrict__ sdiag, int C, int Rp,
-                                                        int D, int crn) {
+                                                        int D, int crn,
+                                                        const double* __restrict__ mdiag) {
   const int tc = blockIdx.x;
   const int t = tc / C, c = tc % C;
   const int d = blockIdx.y * 256 + threadIdx.x;
@@ -230,7 +281,9 @@ __global__ __launch_bounds__(256) void k_estep_finalize(const VT* __restrict__ X
                          : probe_entry(key, t, crn ? 0 : c, k, d, C, K, D);
     acc += p * (double)X[base + (int64_t)(k + 1) * D];
   }
-  sdiag[(int64_t)tc * D + d] = (float)(acc / (double)K);
+  // Jacobi: the probe solves are A^-1 M^1/2 p, so the estimate is rescaled by M^-1/2
+  const double sc = mdiag != nullptr ? 1.0 / sqrt(mdiag[(int64_t)tc * D + d]) : 1.0;
+  sdiag[(int64_t)tc * D + d] = (float)(acc / (double)K * sc);
 }
 
 template <typename VT>
@@ -361,20 +414,32 @@ __global__ __launch_bounds__(256) void k_zero_i32(int* __restrict__ p, long n) {
 template <typename VT, int BS, int EPT>
 static hipError_t init_one(const Geometry& g, const CgState& s, const RhsSource& src,
                            double tol2, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_init<VT, BS, EPT>), dim3(g.T * g.Rp), dim3(BS), 0, st, (VT*)s.X,
-                     (VT*)s.Rv, (VT*)s.Dv, s.rr, s.thr, s.state, s.iters, s.act, src.kind,
-                     (const VT*)src.b, (const VT*)src.B, src.K, src.keyp, src.probes, tol2, g.C,
-                     g.R, g.Rp, g.D, src.crn);
+  if (s.mdiag != nullptr)
+    hipLaunchKernelGGL((k_cg_init<VT, BS, EPT, true>), dim3(g.T * g.Rp), dim3(BS), 0, st,
+                       (VT*)s.X, (VT*)s.Rv, (VT*)s.Dv, s.rr, s.thr, s.state, s.iters, s.act,
+                       src.kind, (const VT*)src.b, (const VT*)src.B, src.K, src.keyp,
+                       src.probes, tol2, g.C, g.R, g.Rp, g.D, src.crn, s.mdiag, s.colc);
+  else
+    hipLaunchKernelGGL((k_cg_init<VT, BS, EPT, false>), dim3(g.T * g.Rp), dim3(BS), 0, st,
+                       (VT*)s.X, (VT*)s.Rv, (VT*)s.Dv, s.rr, s.thr, s.state, s.iters, s.act,
+                       src.kind, (const VT*)src.b, (const VT*)src.B, src.K, src.keyp,
+                       src.probes, tol2, g.C, g.R, g.Rp, g.D, src.crn, nullptr, s.colc);
   return hipGetLastError();
 }
 
 template <typename VT, int BS, int EPT>
 static hipError_t update_one(const Geometry& g, const CgState& s, int u, int steps, int fixed,
                              int split, hipStream_t st) {
-  hipLaunchKernelGGL((k_cg_update<VT, BS, EPT>), dim3(g.T * g.R), dim3(BS), 0, st, (VT*)s.X,
-                     (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state, s.iters,
-                     s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split, s.alpha,
-                     s.colc, s.beta, s.d16, s.d16_kind, s.d16_ld);
+  if (s.mdiag != nullptr)
+    hipLaunchKernelGGL((k_cg_update<VT, BS, EPT, true>), dim3(g.T * g.R), dim3(BS), 0, st,
+                       (VT*)s.X, (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state,
+                       s.iters, s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split,
+                       s.alpha, s.colc, s.beta, s.d16, s.d16_kind, s.d16_ld, s.mdiag, g.C);
+  else
+    hipLaunchKernelGGL((k_cg_update<VT, BS, EPT, false>), dim3(g.T * g.R), dim3(BS), 0, st,
+                       (VT*)s.X, (VT*)s.Rv, (VT*)s.Dv, (const VT*)s.AD, s.rr, s.thr, s.state,
+                       s.iters, s.gam, s.xi, s.act, u, steps, fixed, g.T, g.R, g.Rp, g.D, split,
+                       s.alpha, s.colc, s.beta, s.d16, s.d16_kind, s.d16_ld, nullptr, g.C);
   return hipGetLastError();
 }
 
@@ -425,7 +490,8 @@ hipError_t launch_estep_finalize(const Geometry& g, const CgState& s, int K, con
                                  const int8_t* probes, int crn, float* mu, float* sdiag,
                                  hipStream_t st) {
   hipLaunchKernelGGL((k_estep_finalize<VT>), dim3(g.T * g.C, (g.D + 255) / 256), dim3(256), 0,
-                     st, (const VT*)s.X, K, keyp, probes, mu, sdiag, g.C, g.Rp, g.D, crn);
+                     st, (const VT*)s.X, K, keyp, probes, mu, sdiag, g.C, g.Rp, g.D, crn,
+                     s.mdiag);
   return hipGetLastError();
 }
 
@@ -528,6 +594,53 @@ hipError_t launch_grads(const Geometry& g, int R, const VT* XL, const VT* W, con
     return hipGetLastError();
   }
   return hipSuccess;
+}
+
+// mbase[t][d] = beta sum_n Phi_t[n][d]^2: the data part of diag(A_tc), once per handle.
+__global__ __launch_bounds__(256) void k_colnorm(const float* __restrict__ phi,
+                                                 const int64_t* __restrict__ row_off, double beta,
+                                                 double* __restrict__ mbase, int D) {
+  const int t = blockIdx.x;
+  const int d = blockIdx.y * 256 + threadIdx.x;
+  if (d >= D) return;
+  double acc = 0.0;
+  for (int64_t n = row_off[t]; n < row_off[t + 1]; ++n) {
+    const double v = (double)phi[n * D + d];
+    acc += v * v;
+  }
+  mbase[(int64_t)t * D + d] = beta * acc;
+}
+
+// mdiag[t][c][d] = mbase[t][d] + alpha[c][d]; slogm[t][c] = sum_d log mdiag[t][c][d] (one block
+// per (t, c), fixed order).
+__global__ __launch_bounds__(256) void k_jacobi(const double* __restrict__ mbase,
+                                                const float* __restrict__ alpha,
+                                                double* __restrict__ mdiag,
+                                                double* __restrict__ slogm, int C, int D) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x / C, c = blockIdx.x % C;
+  double acc = 0.0;
+  for (int d = threadIdx.x; d < D; d += 256) {
+    const double m = mbase[(int64_t)t * D + d] + (double)alpha[(int64_t)c * D + d];
+    mdiag[(int64_t)blockIdx.x * D + d] = m;
+    acc += log(m);
+  }
+  const double sl = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) slogm[blockIdx.x] = sl;
+}
+
+hipError_t launch_colnorm(const Geometry& g, const float* phi, double beta, double* mbase,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorm, dim3(g.T, (g.D + 255) / 256), dim3(256), 0, st, phi, g.row_off,
+                     beta, mbase, g.D);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi(const Geometry& g, const double* mbase, const float* alpha,
+                         double* mdiag, double* slogm, hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi, dim3(g.T * g.C), dim3(256), 0, st, mbase, alpha, mdiag, slogm,
+                     g.C, g.D);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_i32(int* p, long n, hipStream_t st) {

@@ -43,8 +43,9 @@ __global__ __launch_bounds__(256) void k_resp(const VT* __restrict__ X, const VT
                                               const double* __restrict__ log_pi,
                                               double* __restrict__ logdet,
                                               double* __restrict__ ell, double* __restrict__ q,
-                                              int* __restrict__ keff_out, int C, int K, int Rp,
-                                              int D) {
+                                              int* __restrict__ keff_out,
+                                              const double* __restrict__ slogm, int C, int K,
+                                              int Rp, int D) {
   __shared__ double sh[4];
   const int t = blockIdx.x;
   const VT* bt = b + (int64_t)t * D;
@@ -60,7 +61,10 @@ __global__ __launch_bounds__(256) void k_resp(const VT* __restrict__ X, const VT
         const int64_t p = ((int64_t)t * C + c) * K + k;
         if (ok[p]) { st += tau[p]; ++keff; }
       }
-      const double nu = keff > 0 ? -st / (double)keff : NAN;
+      // Jacobi preconditioning: the quadrature estimates log det of M^-1/2 A M^-1/2, and
+      // log det A = sum_d log M_dd + that
+      const double corr = slogm != nullptr ? slogm[(int64_t)t * C + c] : 0.0;
+      const double nu = keff > 0 ? -st / (double)keff - corr : NAN;
       keff_out[(int64_t)t * C + c] = keff;
       logdet[(int64_t)t * C + c] = nu;
       ell[(int64_t)t * C + c] = nu + slog[c] + dot;
@@ -132,9 +136,9 @@ template <typename VT>
 hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
                        const double* tau, const uint8_t* ok, const double* slog,
                        const double* log_pi, double* logdet, double* ell, double* q,
-                       int* keff, hipStream_t st) {
+                       int* keff, const double* slogm, hipStream_t st) {
   hipLaunchKernelGGL((k_resp<VT>), dim3(g.T), dim3(256), 0, st, (const VT*)s.X, b, tau, ok, slog,
-                     log_pi, logdet, ell, q, keff, g.C, K, g.Rp, g.D);
+                     log_pi, logdet, ell, q, keff, slogm, g.C, K, g.Rp, g.D);
   return hipGetLastError();
 }
 
@@ -157,10 +161,10 @@ template hipError_t launch_rhs<float>(const Geometry&, const float*, const float
 template hipError_t launch_resp<double>(const Geometry&, const CgState&, int, const double*,
                                         const double*, const uint8_t*, const double*,
                                         const double*, double*, double*, double*, int*,
-                                        hipStream_t);
+                                        const double*, hipStream_t);
 template hipError_t launch_resp<float>(const Geometry&, const CgState&, int, const float*,
                                        const double*, const uint8_t*, const double*,
                                        const double*, double*, double*, double*, int*,
-                                       hipStream_t);
+                                       const double*, hipStream_t);
 
 }  // namespace cmtcs

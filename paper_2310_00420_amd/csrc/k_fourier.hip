@@ -107,24 +107,6 @@ __device__ inline void fft(d2* buf, const double* ctab) {
   for (; Ns < N; Ns *= 4) fft_stage<4, INV, BS, N>(buf, ctab, Ns);
 }
 
-// Sums of two values over the block in a fixed order; every thread receives both.
-template <int BS>
-__device__ inline d2 block_sum2(double a, double b, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_xor(a, o, 64);
-    b += __shfl_xor(b, o, 64);
-  }
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) { sh[2 * w] = a; sh[2 * w + 1] = b; }
-  __syncthreads();
-  double sa = 0.0, sb = 0.0;
-#pragma unroll
-  for (int i = 0; i < BS / 64; ++i) { sa += sh[2 * i]; sb += sh[2 * i + 1]; }
-  return d2{sa, sb};
-}
-
 }  // namespace
 
 // Threads per workgroup for length 2^LOGN: a quarter of the length (one radix-4 butterfly per

@@ -46,7 +46,11 @@ template <typename VT> constexpr int ring_depth() { return sizeof(VT) == 8 ? 6 :
 int op_row_candidates(bool f64, int kind, int* rows) {
   if (!f64) {   // the first entry is the default
     rows[0] = 64; rows[1] = 32;
-    if (kind == 0) return 2;
+    if (kind == 0) {
+      // 16-row forward tiles for short tasks: N_t = 256 gives 16 tiles per task instead of 8
+      rows[2] = 16;
+      return 3;
+    }
     rows[2] = -32;
     return 3;
   }
@@ -785,6 +789,7 @@ hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, 
     if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
     if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, st);
   } else {
+    if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
     if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, st);
     if (rows == 64) return phi_v_rf<VT, 4>(g, phi, tiles, ntiles, V, W, act, st);
   }

@@ -35,7 +35,7 @@ def _policy(cfg):
     return ocg.CGPolicy(fixed_iters=cfg.fixed_iters, tol=cfg.tol, max_iters=cfg.max_iters)
 
 
-def _oracle_columnwise(w, b, alpha, K, pol, seed, it, probes, tasks):
+def _oracle_columnwise(w, b, alpha, K, pol, seed, it, probes, tasks, precond=None):
     """The oracle with its operator applied one column at a time: the same arithmetic in a
     different FP64 summation order (used only to measure that order's effect)."""
     orig = cofem._cg.cg
@@ -46,15 +46,26 @@ def _oracle_columnwise(w, b, alpha, K, pol, seed, it, probes, tasks):
                              for i in range(V.shape[1])], axis=1)
         return orig(ap, B, policy)
 
+    orig_p = cofem._cg.pcg
+
+    def pcg_cols(apply_A, B, policy, m):
+        def ap(V, cols):
+            return np.stack([apply_A(V[:, i:i + 1], cols[i:i + 1])[:, 0]
+                             for i in range(V.shape[1])], axis=1)
+        return orig_p(ap, B, policy, m)
+
     cofem._cg.cg = cg_cols
+    cofem._cg.pcg = pcg_cols
     try:
         return cofem.estep(w.phi_list(), b, w.beta, alpha, w.log_pi, K, pol, seed=seed, it=it,
-                           probes=probes, t_sel=tasks)
+                           probes=probes, t_sel=tasks, precond=precond)
     finally:
         cofem._cg.cg = orig
+        cofem._cg.pcg = orig_p
 
 
-def _run(w, tasks, math="f64", probes=None, seed=1, it=0, alpha=None, K=None, spread=True):
+def _run(w, tasks, math="f64", probes=None, seed=1, it=0, alpha=None, K=None, spread=True,
+         precond=False):
     cfg = w.cfg
     K = cfg.K if K is None else K
     # the library takes alpha in float32: the oracle gets the same values
@@ -63,11 +74,12 @@ def _run(w, tasks, math="f64", probes=None, seed=1, it=0, alpha=None, K=None, sp
     pr = None if probes is None else torch.tensor(probes.astype(np.int8), device=DEV)
     g = m.estep(alpha_dev(alpha), log_pi_dev(w.log_pi), K, fixed_iters=cfg.fixed_iters,
                 tol=cfg.tol, max_iters=cfg.max_iters, seed=seed, em_iter=it, probes=pr,
-                stats=True)
+                stats=True, precond=precond)
     torch.cuda.synchronize()
     b = cofem.rhs(w.phi_list(), w.y_list(), w.beta)
+    pc = "jacobi" if precond else None
     ref = cofem.estep(w.phi_list(), b, w.beta, alpha, w.log_pi, K, _policy(cfg), seed=seed,
-                      it=it, probes=probes, t_sel=tasks)
+                      it=it, probes=probes, t_sel=tasks, precond=pc)
     err = compare_estep(g, ref, tasks)
     err["kappa_hat"] = kappa_hat(g, tasks)
     # every probe entered the log-determinant average (no non-positive Ritz value)
@@ -77,7 +89,7 @@ def _run(w, tasks, math="f64", probes=None, seed=1, it=0, alpha=None, K=None, sp
     it_o = ref["iters"].reshape(len(tasks), -1)
     err["iters_maxdiff"] = int(np.max(np.abs(it_g - it_o)))
     if spread:
-        alt = _oracle_columnwise(w, b, alpha, K, _policy(cfg), seed, it, probes, tasks)
+        alt = _oracle_columnwise(w, b, alpha, K, _policy(cfg), seed, it, probes, tasks, pc)
         sp = estep_errors(alt, ref)
         # CG step counts: a column may stop where either FP64 order of the oracle stops (+-1)
         it_a = alt["iters"].reshape(len(tasks), -1)

@@ -58,7 +58,7 @@ def test_apply(math, tol, shape):
     ("f64", 1e-12, "32,32"), ("f64", 1e-12, "16,16"), ("f64", 1e-12, "-16,32"),
     ("f64", 1e-12, "-16,16"), ("f64", 1e-12, "-16,-16"), ("f64", 1e-12, "32,-16"),
     ("f32", 1e-5, "64,64"), ("f32", 1e-5, "32,32"), ("f32", 1e-5, "64,-32"),
-    ("f32", 1e-5, "32,-32")])
+    ("f32", 1e-5, "32,-32"), ("f32", 1e-5, "16,64"), ("f32", 1e-5, "16,-32")])
 @pytest.mark.parametrize("shape", [
     dict(T=4, C=3, D=208, N=[0, 17, 70, 129], R=37),      # ragged rows, partial tiles
     dict(T=2, C=4, D=512, N=[256, 200], R=150),            # two column groups
