@@ -7,12 +7,13 @@
 // vectors through one complex transform pair with a real, symmetric multiplier.
 //
 // The whole CG solve of a right-hand side (Alg. 1) runs in one workgroup: the column lives in
-// registers, the transforms in LDS, and nothing but the step sizes gamma_u, xi_u (for the
+// registers, the transforms in LDS (two buffers, so that each stage needs one barrier), and
+// nothing but the step sizes gamma_u, xi_u (for the
 // log-determinant, Eq. (tridiag)) and the final solution goes to HBM.  A workgroup solves two
 // columns of the same task at once: since h is real and symmetric, F^H diag(h) F applied to
 // v1 + i v2 gives the two real results as the real and imaginary parts, so one complex FFT pair
 // serves both.  The transform is the Stockham autosort FFT (radix 4, one radix-2 stage when
-// log2 D is odd), in place in LDS: each stage reads its butterfly inputs, waits, then writes.
+// log2 D is odd), out of place between the two LDS buffers.
 // Twiddles come from a table of cos(2 pi i / D), i <= D/4, built by each workgroup in LDS.
 #include <algorithm>
 
@@ -44,39 +45,41 @@ __device__ inline d2 cmul(d2 a, d2 b) {
   return d2{__builtin_fma(a[0], b[0], -a[1] * b[1]), __builtin_fma(a[0], b[1], a[1] * b[0])};
 }
 
-// One Stockham stage of radix R (2 or 4) over N points: butterfly j (0 <= j < N/R) reads
-// x[j + r N/R], multiplies input r by the twiddle w^(r k) (k = j mod Ns, w = exp(-2 pi i /
-// (R Ns))), transforms the R values and writes them to (j / Ns) R Ns + k + r Ns.  Ns is the
-// length of the sub-transforms already done.  Every thread of the block must call it.
+// One Stockham stage of radix R (2 or 4) over N points, out of place: butterfly j
+// (0 <= j < N/R) reads src[j + r N/R], multiplies input r by the twiddle w^(r k) (k = j mod Ns,
+// w = exp(-2 pi i / (R Ns))), transforms the R values and writes them to
+// dst[(j / Ns) R Ns + k + r Ns].  Ns is the length of the sub-transforms already done.  Every
+// thread of the block must call it; one barrier at the end publishes dst.
 template <int R, bool INV, int BS, int N>
-__device__ inline void fft_stage(d2* buf, const double* ctab, int Ns) {
+__device__ inline void fft_stage(const d2* src, d2* dst, const double* ctab, int Ns) {
   constexpr int NBF = N / R;                       // butterflies
   constexpr int PER = NBF >= BS ? NBF / BS : 1;    // per thread
-  d2 v[PER][R];
-#pragma unroll
+  // one butterfly at a time: their registers would otherwise crowd out the columns' state
+#pragma unroll 1
   for (int i = 0; i < PER; ++i) {
     const int j = (int)threadIdx.x + i * BS;
     if (j < NBF) {
+      d2 v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[j + r * NBF];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int j = (int)threadIdx.x + i * BS;
-    if (j < NBF) {
+      for (int r = 0; r < R; ++r) v[r] = src[j + r * NBF];
       const int k = j & (Ns - 1);
       const int step = N / (R * Ns);
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], root<INV>(r * k * step, N, ctab));
+      // w^k from the table; w^2k and w^3k as its square and cube (two FP64 complex products
+      // instead of four more LDS reads)
+      const d2 w1 = root<INV>(k * step, N, ctab);
+      v[1] = cmul(v[1], w1);
+      if constexpr (R == 4) {
+        const d2 w2 = cmul(w1, w1);
+        v[2] = cmul(v[2], w2);
+        v[3] = cmul(v[3], cmul(w1, w2));
+      }
       d2 u[R];
       if constexpr (R == 2) {
-        u[0] = v[i][0] + v[i][1];
-        u[1] = v[i][0] - v[i][1];
+        u[0] = v[0] + v[1];
+        u[1] = v[0] - v[1];
       } else {
-        const d2 a0 = v[i][0] + v[i][2], a1 = v[i][0] - v[i][2];
-        const d2 a2 = v[i][1] + v[i][3], a3 = v[i][1] - v[i][3];
+        const d2 a0 = v[0] + v[2], a1 = v[0] - v[2];
+        const d2 a2 = v[1] + v[3], a3 = v[1] - v[3];
         // -i a3 (forward) or +i a3 (inverse)
         const d2 ma3 = INV ? d2{-a3[1], a3[0]} : d2{a3[1], -a3[0]};
         u[0] = a0 + a2;
@@ -86,32 +89,36 @@ __device__ inline void fft_stage(d2* buf, const double* ctab, int Ns) {
       }
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * Ns] = u[r];
+      for (int r = 0; r < R; ++r) dst[base + r * Ns] = u[r];
     }
   }
   __syncthreads();
 }
 
-// Unnormalised DFT of the N points in buf (forward: exp(-2 pi i k d / N); inverse: conjugate).
+// Unnormalised DFT of the N points in *in (forward: exp(-2 pi i k d / N); inverse: conjugate),
+// ping-ponging between the two buffers; on return *in points to the buffer holding the result.
 template <bool INV, int BS, int LOGN>
-__device__ inline void fft(d2* buf, const double* ctab) {
+__device__ inline void fft(d2** in, d2** other, const double* ctab) {
   constexpr int N = 1 << LOGN;
   int Ns = 1;
   if constexpr (LOGN & 1) {
-    fft_stage<2, INV, BS, N>(buf, ctab, Ns);
+    fft_stage<2, INV, BS, N>(*in, *other, ctab, Ns);
+    d2* tmp = *in; *in = *other; *other = tmp;
     Ns = 2;
   }
   // a runtime loop over the radix-4 stages: unrolled, the address arithmetic of every stage is
   // invariant across CG steps and would be kept in registers
 #pragma unroll 1
-  for (; Ns < N; Ns *= 4) fft_stage<4, INV, BS, N>(buf, ctab, Ns);
+  for (; Ns < N; Ns *= 4) {
+    fft_stage<4, INV, BS, N>(*in, *other, ctab, Ns);
+    d2* tmp = *in; *in = *other; *other = tmp;
+  }
 }
 
 }  // namespace
 
 // Threads per workgroup for length 2^LOGN: a quarter of the length (one radix-4 butterfly per
-// thread and stage), at least one wave and at most 512, so that a wave may hold 256 registers
-// (two columns of 2^LOGN / 512 elements in x, r, d and A d, plus the butterflies in flight).
+// thread and stage, four elements of each column in registers), at least one wave.
 template <int LOGN>
 constexpr int fourier_bs() {
   return std::max(64, std::min(512, (1 << LOGN) / 4));
@@ -132,10 +139,10 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
     double tol2, int steps, int fixed, int T, int C, int R, int Rp) {
   constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>(), E = N / BS;
   extern __shared__ double lds[];
-  d2* buf = reinterpret_cast<d2*>(lds);           // N complex points
-  double* ctab = lds + 2 * N;                      // N/4 + 1 cosines (N/4 + 2 slots)
+  d2* bufA = reinterpret_cast<d2*>(lds);           // two buffers of N complex points
+  d2* bufB = bufA + N;
+  double* ctab = lds + 4 * N;                      // N/4 + 1 cosines (N/4 + 2 slots)
   double* red = ctab + (N / 4 + 2);                // 2 BS/64 partial sums
-  d2* xs = reinterpret_cast<d2*>(red + 2 * (BS / 64));   // x of both columns, N pairs
   const int tid = threadIdx.x;
   const int pairs = Rp / 2;
   const int t = blockIdx.x / pairs, p = blockIdx.x % pairs;
@@ -143,11 +150,11 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
   for (int i = tid; i <= N / 4; i += BS) ctab[i] = cospi(2.0 * (double)i / (double)N);
 
   // the two columns: right-hand sides, diagonal terms, multipliers
-  // r and d of both columns stay in registers, x in LDS (each thread its own elements); alpha
-  // of each column's cluster and the multiplier counts are re-read (from cache) where used
-  double rv[2][E], dv[2][E];
-  const float* alc[2];
-  const int* hct = hcount + (int64_t)t * N;
+  // x, r and d of both columns stay in registers, and so do alpha of each column's cluster
+  // (float) and the multiplier counts of the thread's frequencies (one byte each)
+  double xv[2][E], rv[2][E], dv[2][E];
+  float al[2][E];
+  uint32_t hcp[(E + 3) / 4];
   bool live[2];
   uint64_t key = 0;
   if (kind == 0 && probes == nullptr) key = *keyp;
@@ -157,7 +164,6 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
     live[q] = j < R;
     const int64_t idx = (int64_t)t * Rp + j;
     const int c = live[q] ? colc[idx] : 0;
-    alc[q] = alpha + (int64_t)c * N;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int d = tid + e * BS;
@@ -173,29 +179,41 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
           v = B[((int64_t)t * R + j) * N + d];
         }
       }
+      xv[q][e] = 0.0;
       rv[q][e] = v;
       dv[q][e] = v;
+      al[q][e] = live[q] ? alpha[(int64_t)c * N + d] : 0.0f;
     }
   }
   const double hscale = 0.5 * beta / (double)N;   // h = count / 2, beta, the pair's 1/N
+#pragma unroll
+  for (int i = 0; i < (E + 3) / 4; ++i) hcp[i] = 0;
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    hcp[e / 4] |= (uint32_t)min(hcount[(int64_t)t * N + tid + e * BS], 255) << (8 * (e % 4));
 
-  // beta Phi^T Phi d for both columns (zero for a stopped one), left in buf as (column 0,
-  // column 1) pairs in natural order; A d = that + alpha (.) d is formed where it is read
+  // beta Phi^T Phi d for both columns (zero for a stopped one), left in *res as (column 0,
+  // column 1) pairs in natural order; A d = that + alpha (.) d is formed where it is read.  The
+  // first write goes to bufA: every thread has finished reading the previous step's result by
+  // then (two block reductions lie in between).
+  const d2* res = bufA;
   auto apply = [&](const bool* on) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      buf[tid + e * BS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
+      bufA[tid + e * BS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
     __syncthreads();
-    fft<false, BS, LOGN>(buf, ctab);
+    d2* in = bufA;
+    d2* other = bufB;
+    fft<false, BS, LOGN>(&in, &other, ctab);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      buf[tid + e * BS] = buf[tid + e * BS] * (hscale * (double)hct[tid + e * BS]);
+      in[tid + e * BS] = in[tid + e * BS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
     __syncthreads();
-    fft<true, BS, LOGN>(buf, ctab);
+    fft<true, BS, LOGN>(&in, &other, ctab);
+    res = in;
   };
   auto ad_of = [&](int q, int e) __attribute__((always_inline)) {
-    return __builtin_fma(live[q] ? (double)alc[q][tid + e * BS] : 0.0, dv[q][e],
-                         buf[tid + e * BS][q]);
+    return __builtin_fma((double)al[q][e], dv[q][e], res[tid + e * BS][q]);
   };
 
   if (mode == 1) {
@@ -214,7 +232,6 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
   double pr0 = 0.0, pr1 = 0.0;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    xs[tid + e * BS] = d2{0.0, 0.0};
     pr0 += rv[0][e] * rv[0][e];
     pr1 += rv[1][e] * rv[1][e];
   }
@@ -257,14 +274,12 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
     p1 = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      d2 x2 = xs[tid + e * BS];
 #pragma unroll
       for (int q = 0; q < 2; ++q)
         if (upd[q]) {
-          x2[q] = __builtin_fma(g[q], dv[q][e], x2[q]);
+          xv[q][e] = __builtin_fma(g[q], dv[q][e], xv[q][e]);
           rv[q][e] = __builtin_fma(-g[q], ad_of(q, e), rv[q][e]);
         }
-      xs[tid + e * BS] = x2;
       p0 += rv[0][e] * rv[0][e];
       p1 += rv[1][e] * rv[1][e];
     }
@@ -294,7 +309,7 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
     const int64_t idx = (int64_t)t * Rp + j0 + q;
     const int64_t base = idx * N;
 #pragma unroll
-    for (int e = 0; e < E; ++e) X[base + tid + e * BS] = xs[tid + e * BS][q];
+    for (int e = 0; e < E; ++e) X[base + tid + e * BS] = xv[q][e];
     if (tid == 0) {
       iters[idx] = its[q];
       // a column still active here ran out of steps (steps = 0)
@@ -348,9 +363,8 @@ static hipError_t fourier_one(const Geometry& g, const CgState& s, const int* hc
                               const RhsSource& src, double tol2, int steps, int fixed,
                               hipStream_t st) {
   constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>();
-  // N complex points, the cosine table (padded to an even count, so that x stays 16-byte
-  // aligned), the reduction slots, x of both columns
-  const size_t lds = sizeof(double) * (2 * N + N / 4 + 2 + 2 * (BS / 64) + 2 * N);
+  // two buffers of N complex points, the cosine table, the reduction slots
+  const size_t lds = sizeof(double) * (4 * N + N / 4 + 2 + 2 * (BS / 64));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_fourier_cg<LOGN>,
