@@ -12,8 +12,8 @@
 // log-determinant, Eq. (tridiag)) and the final solution goes to HBM.  A workgroup solves two
 // columns of the same task at once: since h is real and symmetric, F^H diag(h) F applied to
 // v1 + i v2 gives the two real results as the real and imaginary parts, so one complex FFT pair
-// serves both.  The transform is the Stockham autosort FFT (radix 4, one radix-2 stage when
-// log2 D is odd), out of place between the two LDS buffers.
+// serves both.  The transform is the Stockham autosort FFT (radix 8, with one radix-2 or
+// radix-4 stage for the remaining factor), out of place between the two LDS buffers.
 // Twiddles come from a table of cos(2 pi i / D), i <= D/4, built by each workgroup in LDS.
 #include <algorithm>
 
@@ -45,7 +45,19 @@ __device__ inline d2 cmul(d2 a, d2 b) {
   return d2{__builtin_fma(a[0], b[0], -a[1] * b[1]), __builtin_fma(a[0], b[1], a[1] * b[0])};
 }
 
-// One Stockham stage of radix R (2 or 4) over N points, out of place: butterfly j
+// Four-point DFT (forward: exp(-2 pi i k d / 4); inverse: conjugate).
+template <bool INV>
+__device__ inline void dft4(d2 x0, d2 x1, d2 x2, d2 x3, d2& u0, d2& u1, d2& u2, d2& u3) {
+  const d2 a0 = x0 + x2, a1 = x0 - x2, a2 = x1 + x3, a3 = x1 - x3;
+  // -i a3 (forward) or +i a3 (inverse)
+  const d2 ma3 = INV ? d2{-a3[1], a3[0]} : d2{a3[1], -a3[0]};
+  u0 = a0 + a2;
+  u1 = a1 + ma3;
+  u2 = a0 - a2;
+  u3 = a1 - ma3;
+}
+
+// One Stockham stage of radix R (2, 4 or 8) over N points, out of place: butterfly j
 // (0 <= j < N/R) reads src[j + r N/R], multiplies input r by the twiddle w^(r k) (k = j mod Ns,
 // w = exp(-2 pi i / (R Ns))), transforms the R values and writes them to
 // dst[(j / Ns) R Ns + k + r Ns].  Ns is the length of the sub-transforms already done.  Every
@@ -68,24 +80,40 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const double* ctab, int
       // instead of four more LDS reads)
       const d2 w1 = root<INV>(k * step, N, ctab);
       v[1] = cmul(v[1], w1);
-      if constexpr (R == 4) {
-        const d2 w2 = cmul(w1, w1);
+      if constexpr (R >= 4) {
+        const d2 w2 = cmul(w1, w1), w3 = cmul(w1, w2);
         v[2] = cmul(v[2], w2);
-        v[3] = cmul(v[3], cmul(w1, w2));
+        v[3] = cmul(v[3], w3);
+        if constexpr (R == 8) {
+          const d2 w4 = cmul(w2, w2);
+          v[4] = cmul(v[4], w4);
+          v[5] = cmul(v[5], cmul(w1, w4));
+          v[6] = cmul(v[6], cmul(w2, w4));
+          v[7] = cmul(v[7], cmul(w3, w4));
+        }
       }
       d2 u[R];
       if constexpr (R == 2) {
         u[0] = v[0] + v[1];
         u[1] = v[0] - v[1];
+      } else if constexpr (R == 4) {
+        dft4<INV>(v[0], v[1], v[2], v[3], u[0], u[1], u[2], u[3]);
       } else {
-        const d2 a0 = v[0] + v[2], a1 = v[0] - v[2];
-        const d2 a2 = v[1] + v[3], a3 = v[1] - v[3];
-        // -i a3 (forward) or +i a3 (inverse)
-        const d2 ma3 = INV ? d2{-a3[1], a3[0]} : d2{a3[1], -a3[0]};
-        u[0] = a0 + a2;
-        u[1] = a1 + ma3;
-        u[2] = a0 - a2;
-        u[3] = a1 - ma3;
+        // eight points: four-point transforms of the even and odd inputs, combined with the
+        // eighth roots of unity exp(-+ i pi k / 4)
+        d2 a[4], b[4];
+        dft4<INV>(v[0], v[2], v[4], v[6], a[0], a[1], a[2], a[3]);
+        dft4<INV>(v[1], v[3], v[5], v[7], b[0], b[1], b[2], b[3]);
+        constexpr double h = 0.70710678118654752440;   // 1 / sqrt(2)
+        const d2 t1 = INV ? d2{h * (b[1][0] - b[1][1]), h * (b[1][0] + b[1][1])}
+                          : d2{h * (b[1][0] + b[1][1]), h * (b[1][1] - b[1][0])};
+        const d2 t2 = INV ? d2{-b[2][1], b[2][0]} : d2{b[2][1], -b[2][0]};
+        const d2 t3 = INV ? d2{-h * (b[3][0] + b[3][1]), h * (b[3][0] - b[3][1])}
+                          : d2{h * (b[3][1] - b[3][0]), -h * (b[3][0] + b[3][1])};
+        u[0] = a[0] + b[0]; u[4] = a[0] - b[0];
+        u[1] = a[1] + t1;   u[5] = a[1] - t1;
+        u[2] = a[2] + t2;   u[6] = a[2] - t2;
+        u[3] = a[3] + t3;   u[7] = a[3] - t3;
       }
       const int base = (j - k) * R + k;
 #pragma unroll
@@ -101,16 +129,21 @@ template <bool INV, int BS, int LOGN>
 __device__ inline void fft(d2** in, d2** other, const double* ctab) {
   constexpr int N = 1 << LOGN;
   int Ns = 1;
-  if constexpr (LOGN & 1) {
+  // radix 8 where it divides, one radix-2 or radix-4 stage first for the remaining factor
+  if constexpr (LOGN % 3 == 1) {
     fft_stage<2, INV, BS, N>(*in, *other, ctab, Ns);
     d2* tmp = *in; *in = *other; *other = tmp;
     Ns = 2;
+  } else if constexpr (LOGN % 3 == 2) {
+    fft_stage<4, INV, BS, N>(*in, *other, ctab, Ns);
+    d2* tmp = *in; *in = *other; *other = tmp;
+    Ns = 4;
   }
-  // a runtime loop over the radix-4 stages: unrolled, the address arithmetic of every stage is
+  // a runtime loop over the radix-8 stages: unrolled, the address arithmetic of every stage is
   // invariant across CG steps and would be kept in registers
 #pragma unroll 1
-  for (; Ns < N; Ns *= 4) {
-    fft_stage<4, INV, BS, N>(*in, *other, ctab, Ns);
+  for (; Ns < N; Ns *= 8) {
+    fft_stage<8, INV, BS, N>(*in, *other, ctab, Ns);
     d2* tmp = *in; *in = *other; *other = tmp;
   }
 }
