@@ -69,6 +69,7 @@ struct cmtcs_handle_s {
   void *X = nullptr, *Rv = nullptr, *Dv = nullptr, *AD = nullptr, *W = nullptr, *b = nullptr;
   double *rr = nullptr, *thr = nullptr, *gam = nullptr, *xi = nullptr;
   uint8_t* state = nullptr;
+  bool compact = true;
   int* iters = nullptr;
   int* act = nullptr;
   int* colc = nullptr;
@@ -198,10 +199,11 @@ struct cmtcs_handle_s {
     hipError_t e = hipSuccess;
     for (int u = 0; u < steps && e == hipSuccess; ++u) {
       const int* act_u = act + (size_t)u * T;
-      e = launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, fwd_rows, s);
+      e = launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u, cstate(),
+                           fwd_rows, s);
       if (e == hipSuccess)
         e = launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
-                              nullptr, colc, beta, act_u, adj_rows, s);
+                              nullptr, colc, beta, act_u, cstate(), adj_rows, s);
       if (e == hipSuccess) e = launch_cg_update<VT>(g, cs, u, steps, fixed, 0, s);
     }
     return e;
@@ -256,6 +258,10 @@ struct cmtcs_handle_s {
     }
     return CMTCS_OK;
   }
+
+  // Column states for the products of the CG loop (compaction of active columns), unless
+  // CMTCS_COMPACT=0 was set at create.
+  const uint8_t* cstate() const { return compact ? state : nullptr; }
 
   CgState cg() const {
     CgState s;
@@ -357,11 +363,12 @@ struct cmtcs_handle_s {
         hipError_t e = hipSuccess;
         auto fwd = [&]() {
           return launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
-                                  fwd_rows, st);
+                                  nullptr, fwd_rows, st);
         };
         auto adj = [&]() {
           return launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
-                                   (VT*)AD, nullptr, colc, beta, nullptr, adj_rows, st);
+                                   (VT*)AD, nullptr, colc, beta, nullptr, nullptr, adj_rows,
+                                   st);
         };
         for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
           e = kind == 0 ? adj() : fwd();
@@ -426,14 +433,14 @@ struct cmtcs_handle_s {
         HIP_TRY(mixed_product(g16, alpha, act_u, 1), "launch(phi_v16)");
       else
         HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, act_u,
-                                  fwd_rows, st),
+                                  cstate(), fwd_rows, st),
                 "launch(phi_v)");
       if (e4) HIP_TRY(hipEventRecord(e4[1], st), "hipEventRecord");
       if (mixed())
         HIP_TRY(mixed_product(g16, nullptr, act_u, 2), "launch(phit_w16)");
       else
         HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv,
-                                  (VT*)AD, nullptr, colc, beta, act_u, adj_rows, st),
+                                  (VT*)AD, nullptr, colc, beta, act_u, cstate(), adj_rows, st),
                 "launch(phit_w)");
       if (e4) HIP_TRY(hipEventRecord(e4[2], st), "hipEventRecord");
       const bool replace = mixed() && refine_every > 0 && (u + 1) % refine_every == 0;
@@ -443,9 +450,10 @@ struct cmtcs_handle_s {
         // true-residual replacement: r = b - A x with FP32 products from the FP32 Phi, then
         // xi, d and the stop decision from the replaced residual
         HIP_TRY(launch_phi_v<float>(g, phi, fwd_tiles, nfwd, (const float*)X, (float*)W, act_u,
-                                    fwd_rows, st), "launch(phi_v residual)");
+                                    nullptr, fwd_rows, st), "launch(phi_v residual)");
         HIP_TRY(launch_phit_w<float>(g, phi, adj_tiles, nadj, (const float*)W, (const float*)X,
-                                     (float*)AD, alpha, colc, beta, act_u, adj_rows, st),
+                                     (float*)AD, alpha, colc, beta, act_u, nullptr, adj_rows,
+                                     st),
                 "launch(phit_w residual)");
         HIP_TRY(launch_replace(g, s, (const float*)AD, src, u, steps, fixed, st),
                 "launch(replace)");
@@ -499,10 +507,11 @@ struct cmtcs_handle_s {
     src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
     src.crn = 0;
     HIP_TRY(launch_cg_init<VT>(g, cg(), src, 0.0, 0, st), "launch(cg_init)");
-    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
+    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr, nullptr,
                              fwd_rows, st), "launch(phi_v)");
     HIP_TRY(launch_phit_w<VT>(g, phi, adj_tiles, nadj, (const VT*)W, (const VT*)Dv, (VT*)AD,
-                              alpha, colc, beta, nullptr, adj_rows, st), "launch(phit_w)");
+                              alpha, colc, beta, nullptr, nullptr, adj_rows, st),
+            "launch(phit_w)");
     CgState s = cg();
     s.X = AD;   // copy A V out through the solution-copy kernel
     HIP_TRY(launch_solve_output<VT>(g, s, AV, nullptr, nullptr, 0, nullptr, nullptr, st),
@@ -520,7 +529,7 @@ struct cmtcs_handle_s {
     const Geometry g = geom(2 * R, Rp);
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
     HIP_TRY(launch_pack2<VT>(geom(R, Rp), Xs, Lam, Dv, st), "launch(pack2)");
-    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr,
+    HIP_TRY(launch_phi_v<VT>(g, phi, fwd_tiles, nfwd, (const VT*)Dv, (VT*)W, nullptr, nullptr,
                              fwd_rows, st), "launch(phi_v)");
     HIP_TRY(launch_grads<VT>(g, R, (const VT*)Dv, (const VT*)W, y, colc, beta, y_coef, dalpha,
                              dphi, row_off[T], st), "launch(grads)");
@@ -834,10 +843,10 @@ cmtcs_status_t apply_noalloc(const cmtcs_problem_t* p, const float* alpha, int R
                      (const VT*)V, Dv, R, Rp, D);
   HIP_TRY(hipGetLastError(), "launch(pad_cols)");
   const float* phi = (const float*)p->phi;
-  HIP_TRY(launch_phi_v<VT>(g, phi, fwd, (int)ft.size(), Dv, W, nullptr, fr, st),
+  HIP_TRY(launch_phi_v<VT>(g, phi, fwd, (int)ft.size(), Dv, W, nullptr, nullptr, fr, st),
           "launch(phi_v)");
   HIP_TRY(launch_phit_w<VT>(g, phi, adj, (int)at.size(), W, Dv, AD, alpha, colc_d, p->beta,
-                            nullptr, ar, st), "launch(phit_w)");
+                            nullptr, nullptr, ar, st), "launch(phit_w)");
   CgState s{};
   s.X = AD;
   HIP_TRY(launch_solve_output<VT>(g, s, AV, nullptr, nullptr, 0, nullptr, nullptr, st),
@@ -941,6 +950,10 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
     h->slq_lds = std::max(0L, std::min(kSlqLdsBytes, std::atol(sl)));
   const char* at = std::getenv("CMTCS_AUTOTUNE");
   h->autotune = !(at != nullptr && at[0] == '0');
+  // CMTCS_COMPACT=0 makes the CG loop's products multiply every column slot (for comparison:
+  // the results are the same bit for bit)
+  const char* cp = std::getenv("CMTCS_COMPACT");
+  h->compact = !(cp != nullptr && cp[0] == '0');
   // CMTCS_TILES="fwd,adj" pins both tile heights (each one of the supported candidates) and
   // turns the autotuner off; unsupported values leave the defaults in place
   if (const char* pin = std::getenv("CMTCS_TILES")) {

@@ -189,16 +189,22 @@ __host__ __device__ inline int group_width(int Rp) {
 }
 
 // Launchers (k_operator.hip).  `act` is the [T] count of active right-hand sides for the
-// current step (tasks with a zero count are skipped) or null.  `rows` is the output rows per
-// wave tile the tile table was built for (one of op_row_candidates).
+// current step (tasks with a zero count are skipped) or null.  `state` is the CG loop's [T*Rp]
+// column states or null: with it both products compact each task's active columns into its
+// leading fragments (W then holds the columns by compacted position, so a forward and an
+// adjoint product of one step take the same `state`), without it every slot is multiplied.
+// `rows` is the output rows per wave tile the tile table was built for (one of
+// op_row_candidates).
 template <typename VT>
 hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
-                        const VT* V, VT* W, const int* act, int rows, hipStream_t st);
+                        const VT* V, VT* W, const int* act, const uint8_t* state, int rows,
+                        hipStream_t st);
 // alpha == nullptr: AV = Phi^T W alone (beta and the diagonal term are left to the caller).
 template <typename VT>
 hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
-                         double beta, const int* act, int rows, hipStream_t st);
+                         double beta, const int* act, const uint8_t* state, int rows,
+                         hipStream_t st);
 // Writes the supported tile heights of product `kind` (0: Phi V, 1: Phi^T W) for FP64 (f64)
 // or FP32 right-hand sides, default first, and returns their count (at most kMaxTileCands).  A
 // positive height is the output rows of a one-wave tile of the register-pipelined kernels; a

@@ -29,6 +29,49 @@ __device__ inline int xcd_block(int b, int nb) {
   return x * q + min(x, rem) + i;
 }
 
+// Compaction of a task's right-hand sides in the CG loop.  Column positions 0 .. nact-1 of task
+// t list its active slots (state kActive) in increasing order; the remaining positions hold its
+// stopped and padding slots, from the last position down.  A tile of column group g multiplies
+// the fragments that hold positions 16 kColGroup g .. up to the last active one, so fragments
+// whose columns have all stopped (and, once a task has fewer active columns, the padding
+// fragment) cost nothing.  The forward product reads V at the slots and writes W by position;
+// the adjoint reads W by position and writes at the slots.  Every output column is the same
+// sequence of operations whichever fragment holds it, so the results do not depend on the
+// compaction.  One wave scans the task's states (64 a round, by ballot) and stores
+// map[i] = slot of position p0 + i for 0 <= i < 16 kColGroup (if `store`); it returns nact.
+__device__ inline int col_map(const uint8_t* __restrict__ state, int t, int Rp, int p0,
+                              int* __restrict__ map, bool store = true) {
+  const int lane = threadIdx.x & 63;
+  const uint8_t* st = state + (int64_t)t * Rp;
+  const uint64_t lt = lane == 0 ? 0ull : ~0ull >> (64 - lane);
+  int nact = 0, nstop = 0;
+  for (int base = 0; base < Rp; base += 64) {
+    const int j = base + lane;
+    const bool valid = j < Rp;
+    const bool a = valid && st[j] == kActive;
+    const uint64_t ma = __ballot(a), ms = __ballot(valid && !a);
+    const int p = a ? nact + __popcll(ma & lt) : Rp - 1 - (nstop + __popcll(ms & lt));
+    const int i = p - p0;
+    if (store && valid && i >= 0 && i < 16 * kColGroup) map[i] = j;
+    nact += __popcll(ma);
+    nstop += __popcll(ms);
+  }
+  return uniform(nact);
+}
+
+// Column fragments a tile of the group starting at fragment cf0 multiplies: all of the group,
+// or with a column map those up to the last active position.
+__device__ inline int active_frags(int ncf, int cf0, int nact) {
+  return min(ncf, (nact - 16 * cf0 + 15) >> 4);
+}
+
+// Makes one wave's LDS stores visible to its own later LDS loads.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Output rows per wave tile (16 * RF) that the instantiations below support; the autotuner of
 // the host layer picks one per product.  FP64 tiles keep RF * 9 accumulators of 8 registers.
 // Waves (tiles) per workgroup.  Four measured faster than one on the FP64 tiles, although a
@@ -64,10 +107,12 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
                                                const int64_t* __restrict__ w_off,
                                                const int4* __restrict__ tiles, int ntiles,
                                                const VT* __restrict__ V, VT* __restrict__ W,
-                                               const int* __restrict__ act, int D, int Rp) {
+                                               const int* __restrict__ act,
+                                               const uint8_t* __restrict__ state, int D, int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<VT, 4>::type vt4;
   constexpr int kRingA = ring_depth<VT>();
+  __shared__ int cmap[kOpWaves][16 * kColGroup];
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
   // tile fields are wave-uniform: keep them in scalar registers so that every branch on them
@@ -80,7 +125,13 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
-  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  int* map = cmap[threadIdx.x >> 6];
+  if (state != nullptr) {
+    ncf = active_frags(ncf, cf0, col_map(state, t, Rp, 16 * cf0, map));
+    if (ncf <= 0) return;
+    wave_lds_sync();
+  }
 
   // Phi rows of the task and V_t through buffer descriptors (per-lane 32-bit byte offsets, the
   // chunk's start as a scalar offset).  Matrix row i16 of fragment rf is Phi row
@@ -93,8 +144,14 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   for (int rf = 0; rf < RF; ++rf)
     aoff[rf] = (uint32_t)(((n0 + rf * 16 + Mfma<VT>::a_row(i16)) * D + 4 * g4) * 4);
   const rsrc_t rv = make_rsrc(V + (int64_t)t * Rp * D, (uint32_t)((int64_t)Rp * D * sizeof(VT)));
-  const uint32_t boff0 = (uint32_t)(((cf0 * 16 + i16) * D + 4 * g4) * sizeof(VT));
-  const uint32_t bstep = (uint32_t)(16 * D * sizeof(VT));
+  // V column of lane i16 in fragment f: its slot (position cf0*16 + f*16 + i16)
+  uint32_t boff[kColGroup];
+#pragma unroll
+  for (int f = 0; f < kColGroup; ++f) {
+    const int pos = min(f, ncf - 1) * 16 + i16;
+    const int slot = state != nullptr ? map[pos] : cf0 * 16 + pos;
+    boff[f] = (uint32_t)((slot * D + 4 * g4) * sizeof(VT));
+  }
 
   acc_t acc[RF][kColGroup];
   auto zero_acc = [&]() __attribute__((always_inline)) {
@@ -123,10 +180,7 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
     const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 16 * (int)sizeof(VT));
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) {
-      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
-      x[cf] = buf_load<vt4>(rv, boff0 + (uint32_t)f * bstep, soff);
-    }
+    for (int cf = 0; cf < kColGroup; ++cf) x[cf] = buf_load<vt4>(rv, boff[cf], soff);
   };
   // first: the chunk that starts the accumulation (its first k-step takes a zero accumulator)
   auto mma = [&](const f4 (&x)[RF], const vt4 (&y)[kColGroup], auto full, auto first)
@@ -228,13 +282,16 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
                                                    const int64_t* __restrict__ w_off,
                                                    const int4* __restrict__ tiles, int ntiles,
                                                    const VT* __restrict__ V, VT* __restrict__ W,
-                                                   const int* __restrict__ act, int D, int Rp) {
+                                                   const int* __restrict__ act,
+                                                   const uint8_t* __restrict__ state, int D,
+                                                   int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<VT, 4>::type vt4;
   typedef LdsChunk<VT> L;
   typedef typename L::piece_t piece_t;
   constexpr int kRingA = ring_depth<VT>();
   __shared__ VT lds[2][16 * kColGroup][L::kLd];
+  __shared__ int cmap[16 * kColGroup];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int blk = uniform(xcd_block(blockIdx.x, gridDim.x));
@@ -246,7 +303,13 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
-  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  if (state != nullptr) {
+    // every wave scans (the same count); wave 0 stores the map
+    ncf = active_frags(ncf, cf0, col_map(state, t, Rp, 16 * cf0, cmap, wave == 0));
+    if (ncf <= 0) return;   // uniform over the block
+    __syncthreads();
+  }
 
   // as in k_phi_v: Phi through a buffer descriptor; rows past N_t (also whole tiles of the
   // block past np) read as zeros and their outputs are zeroed or not stored
@@ -265,7 +328,8 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   for (int i = 0; i < L::kPerThread; ++i) {
     const int p = min((int)threadIdx.x + i * 64 * kOpWaves, npieces - 1);
     const int col = p / L::kPieces, q = p % L::kPieces;
-    soff_v[i] = (uint32_t)(((cf0 * 16 + col) * D + q * L::kPer16) * sizeof(VT));
+    const int slot = state != nullptr ? cmap[col] : cf0 * 16 + col;
+    soff_v[i] = (uint32_t)((slot * D + q * L::kPer16) * sizeof(VT));
     sdst[0][i] = &lds[0][col][q * L::kPer16];
     sdst[1][i] = &lds[1][col][q * L::kPer16];
   }
@@ -390,15 +454,20 @@ __device__ inline void phit_w_store(const typename Mfma<VT>::acc_t (&acc)[RF][kC
                                     int d0, int cf0, int ncf, int i16, int g4, int D, int Rp,
                                     VT* __restrict__ AV, const VT* __restrict__ V,
                                     const float* __restrict__ alpha,
-                                    const int* __restrict__ colc, double beta) {
+                                    const int* __restrict__ colc, double beta,
+                                    const int* __restrict__ map) {
   typedef typename VecOf<VT, RF>::type vrf;
+  // output column of lane i16 in fragment cf: position (cf0 + cf) * 16 + i16, at its slot
+  auto slot_of = [&](int cf) __attribute__((always_inline)) {
+    return map != nullptr ? map[cf * 16 + i16] : (cf0 + cf) * 16 + i16;
+  };
   if (alpha == nullptr) {
     // bare product Phi^T W (the CG update adds beta and the diagonal term): stores only, so
     // the epilogue issues no load and never waits on memory
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
       if (cf >= ncf) continue;
-      const int64_t col = ((int64_t)t * Rp + (cf0 + cf) * 16 + i16) * D;
+      const int64_t col = ((int64_t)t * Rp + slot_of(cf)) * D;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int d = d0 + RF * Mfma<VT>::out_row(g4, r);
@@ -418,7 +487,7 @@ __device__ inline void phit_w_store(const typename Mfma<VT>::acc_t (&acc)[RF][kC
 #pragma unroll
   for (int cf = 0; cf < kColGroup; ++cf) {
     if (cf >= ncf) continue;
-    const int j = (cf0 + cf) * 16 + i16;
+    const int j = slot_of(cf);
     const int c = colc[(int64_t)t * Rp + j];
     const int64_t col = ((int64_t)t * Rp + j) * D;
     const float* al = alpha + (int64_t)(c >= 0 ? c : 0) * D;
@@ -456,9 +525,12 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
                                                 VT* __restrict__ AV,
                                                 const float* __restrict__ alpha,
                                                 const int* __restrict__ colc, double beta,
-                                                const int* __restrict__ act, int D, int Rp) {
+                                                const int* __restrict__ act,
+                                                const uint8_t* __restrict__ state, int D,
+                                                int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<float, RF>::type frf;
+  __shared__ int cmap[kOpWaves][16 * kColGroup];
   // k-steps of the 16x16x4 tiles per chunk (chunks of KC = 16 rows of n; 8-row chunks, with
   // 16-byte right-hand-side fragments, measured 2.5% slower in FP64)
   constexpr int KS = 4;
@@ -475,7 +547,14 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
-  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  int* map = nullptr;
+  if (state != nullptr) {
+    map = cmap[threadIdx.x >> 6];
+    ncf = active_frags(ncf, cf0, col_map(state, t, Rp, 16 * cf0, map));
+    if (ncf <= 0) return;
+    wave_lds_sync();
+  }
   const int dl = d0 + RF * i16;          // first of the RF output rows this lane loads
   // Phi rows of the task and W_t through buffer descriptors: per-lane 32-bit byte offsets,
   // the chunk's start in scalar registers.  Lanes past D read column 0 (outputs not stored).
@@ -576,7 +655,7 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
   if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
   else run(std::false_type{});
 
-  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
+  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta, map);
 }
 
 // LDS-staged adjoint product: as k_phi_v_lds for Phi^T W.  A block of four 16*RF-row waves
@@ -591,7 +670,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     const int64_t* __restrict__ w_off, const int4* __restrict__ tiles, int ntiles,
     const VT* __restrict__ W, const VT* __restrict__ V, VT* __restrict__ AV,
     const float* __restrict__ alpha, const int* __restrict__ colc, double beta,
-    const int* __restrict__ act, int D, int Rp) {
+    const int* __restrict__ act, const uint8_t* __restrict__ state, int D, int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<VT, 4>::type vt4;
   typedef typename VecOf<float, RF>::type frf;
@@ -603,6 +682,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // two waves per SIMD without spilling (six do not)
   constexpr int kRingA = 4;
   __shared__ VT lds[2][16 * kColGroup][L::kLd];
+  __shared__ int cmap[16 * kColGroup];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
   const int blk = uniform(xcd_block(blockIdx.x, gridDim.x));
@@ -614,7 +694,15 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   const int64_t r0 = row_off[t];
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
-  const int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  const int* map = nullptr;
+  if (state != nullptr) {
+    // every wave scans (the same count); wave 0 stores the map
+    ncf = active_frags(ncf, cf0, col_map(state, t, Rp, 16 * cf0, cmap, wave == 0));
+    if (ncf <= 0) return;   // uniform over the block
+    __syncthreads();
+    map = cmap;
+  }
   const int nch = np / KC;
 
   acc_t acc[RF][kColGroup];
@@ -626,7 +714,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   };
   if (nch == 0) {   // empty task (uniform over the block): the product is zero
     zero_acc();
-    phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
+    phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta, map);
     return;
   }
   // Phi as in k_phit_w: lanes past D read column 0 (outputs not stored); a chunk's descriptor
@@ -736,62 +824,67 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   if (ncf == kColGroup) run(std::true_type{});
   else run(std::false_type{});
 
-  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta);
+  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta, map);
 }
 
 template <typename VT, int RF>
 static hipError_t phi_v_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
-                           const VT* V, VT* W, const int* act, hipStream_t st) {
+                           const VT* V, VT* W, const int* act, const uint8_t* state,
+                           hipStream_t st) {
   hipLaunchKernelGGL((k_phi_v<VT, RF>), dim3((ntiles + kOpWaves - 1) / kOpWaves), dim3(64 * kOpWaves), 0, st, phi,
-                     g.row_off, g.w_off, tiles, ntiles, V, W, act, g.D, g.Rp);
+                     g.row_off, g.w_off, tiles, ntiles, V, W, act, state, g.D, g.Rp);
   return hipGetLastError();
 }
 
 template <typename VT, int RF>
 static hipError_t phit_w_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                             const VT* W, const VT* V, VT* AV, const float* alpha,
-                            const int* colc, double beta, const int* act, hipStream_t st) {
+                            const int* colc, double beta, const int* act,
+                            const uint8_t* state, hipStream_t st) {
   hipLaunchKernelGGL((k_phit_w<VT, RF>), dim3((ntiles + kOpWaves - 1) / kOpWaves), dim3(64 * kOpWaves), 0, st, phi,
-                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
-                     g.Rp);
+                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                     g.D, g.Rp);
   return hipGetLastError();
 }
 
 template <typename VT, int RF>
 static hipError_t phi_v_lds_rf(const Geometry& g, const float* phi, const int4* tiles,
-                               int ntiles, const VT* V, VT* W, const int* act, hipStream_t st) {
+                               int ntiles, const VT* V, VT* W, const int* act, const uint8_t* state,
+                           hipStream_t st) {
   hipLaunchKernelGGL((k_phi_v_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
-                     g.row_off, g.w_off, tiles, ntiles, V, W, act, g.D, g.Rp);
+                     g.row_off, g.w_off, tiles, ntiles, V, W, act, state, g.D, g.Rp);
   return hipGetLastError();
 }
 
 template <typename VT, int RF>
 static hipError_t phit_w_lds_rf(const Geometry& g, const float* phi, const int4* tiles,
                                 int ntiles, const VT* W, const VT* V, VT* AV, const float* alpha,
-                                const int* colc, double beta, const int* act, hipStream_t st) {
+                                const int* colc, double beta, const int* act,
+                            const uint8_t* state, hipStream_t st) {
   hipLaunchKernelGGL((k_phit_w_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
-                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, g.D,
-                     g.Rp);
+                     g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                     g.D, g.Rp);
   return hipGetLastError();
 }
 
 template <typename VT>
 hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
-                        const VT* V, VT* W, const int* act, int rows, hipStream_t st) {
+                        const VT* V, VT* W, const int* act, const uint8_t* state, int rows,
+                        hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
   if (rows < 0) {   // LDS-staged variant: one tile per block of four waves of -rows rows each
     if constexpr (sizeof(VT) == 8) {
-      if (rows == -16) return phi_v_lds_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
+      if (rows == -16) return phi_v_lds_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, state, st);
     }
     return hipErrorInvalidValue;
   }
   if constexpr (sizeof(VT) == 8) {
-    if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
-    if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, st);
+    if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, state, st);
+    if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, state, st);
   } else {
-    if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, st);
-    if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, st);
-    if (rows == 64) return phi_v_rf<VT, 4>(g, phi, tiles, ntiles, V, W, act, st);
+    if (rows == 16) return phi_v_rf<VT, 1>(g, phi, tiles, ntiles, V, W, act, state, st);
+    if (rows == 32) return phi_v_rf<VT, 2>(g, phi, tiles, ntiles, V, W, act, state, st);
+    if (rows == 64) return phi_v_rf<VT, 4>(g, phi, tiles, ntiles, V, W, act, state, st);
   }
   return hipErrorInvalidValue;
 }
@@ -799,41 +892,52 @@ hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, 
 template <typename VT>
 hipError_t launch_phit_w(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                          const VT* W, const VT* V, VT* AV, const float* alpha, const int* colc,
-                         double beta, const int* act, int rows, hipStream_t st) {
+                         double beta, const int* act, const uint8_t* state, int rows,
+                         hipStream_t st) {
   if (ntiles == 0) return hipSuccess;
   if (rows < 0) {   // LDS-staged variant: one tile per block of four waves of -rows rows each
     if constexpr (sizeof(VT) == 8) {
       if (rows == -16)
-        return phit_w_lds_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+        return phit_w_lds_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                                     st);
     } else {
       if (rows == -32)
-        return phit_w_lds_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+        return phit_w_lds_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                                     st);
     }
     return hipErrorInvalidValue;
   }
   if constexpr (sizeof(VT) == 8) {
     if (rows == 16)
-      return phit_w_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+      return phit_w_rf<VT, 1>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                                     st);
     if (rows == 32)
-      return phit_w_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+      return phit_w_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                                     st);
   } else {
     if (rows == 32)
-      return phit_w_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+      return phit_w_rf<VT, 2>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                                     st);
     if (rows == 64)
-      return phit_w_rf<VT, 4>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, st);
+      return phit_w_rf<VT, 4>(g, phi, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
+                                     st);
   }
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_phi_v<double>(const Geometry&, const float*, const int4*, int,
-                                         const double*, double*, const int*, int, hipStream_t);
+                                         const double*, double*, const int*, const uint8_t*, int,
+                                         hipStream_t);
 template hipError_t launch_phi_v<float>(const Geometry&, const float*, const int4*, int,
-                                        const float*, float*, const int*, int, hipStream_t);
+                                        const float*, float*, const int*, const uint8_t*, int,
+                                        hipStream_t);
 template hipError_t launch_phit_w<double>(const Geometry&, const float*, const int4*, int,
                                           const double*, const double*, double*, const float*,
-                                          const int*, double, const int*, int, hipStream_t);
+                                          const int*, double, const int*, const uint8_t*, int,
+                                          hipStream_t);
 template hipError_t launch_phit_w<float>(const Geometry&, const float*, const int4*, int,
                                          const float*, const float*, float*, const float*,
-                                         const int*, double, const int*, int, hipStream_t);
+                                         const int*, double, const int*, const uint8_t*, int,
+                                          hipStream_t);
 
 }  // namespace cmtcs
