@@ -40,6 +40,15 @@ template <> struct Mfma<double> {
   __device__ static inline int out_row(int g, int r) { return g + 4 * r; }
   __device__ static inline int a_row(int i) { return 4 * (i & 3) + (i >> 2); }
 };
+// FP64 4x4x4 product in four blocks: A and B take the lanes of the 16x16x4 product (block b
+// holds matrix rows 4b .. 4b+3 and the same four columns), so with B's lane i16 reading column
+// i16 & 3 the four blocks give 16 rows x 4 columns; lane (i16, g4) receives matrix row
+// narrow_row(i16, g4), column i16 & 3.  Defined for FP64 only.
+template <typename VT> __device__ VT mma4(VT a, VT b, VT c);
+template <> __device__ inline double mma4<double>(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline int narrow_row(int i16, int g) { return g + 4 * (i16 >> 2); }
 template <> struct Mfma<float> {
   typedef f4 acc_t;
   __device__ static inline acc_t mma(float a, float b, acc_t c) {

@@ -65,6 +65,15 @@ __device__ inline int active_frags(int ncf, int cf0, int nact) {
   return min(ncf, (nact - 16 * cf0 + 15) >> 4);
 }
 
+// Whether a full group's last fragment holds at most four active positions: the LDS-staged FP64
+// kernels then multiply only its first four columns, with 4x4x4 products (a quarter of the
+// work; the other twelve are stopped or padding columns, whose outputs nothing reads).
+__device__ inline bool narrow_last(int ncf, int cf0, int nact) {
+  return ncf == kColGroup && nact - 16 * (cf0 + kColGroup - 1) <= 4;
+}
+template <typename VT, int RF>
+constexpr bool kNarrowOk = sizeof(VT) == 8 && RF == 1;
+
 // Makes one wave's LDS stores visible to its own later LDS loads.
 __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -304,10 +313,13 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   const int nt = (int)(row_off[t + 1] - r0);
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
   int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
+  bool narrow = false;
   if (state != nullptr) {
     // every wave scans (the same count); wave 0 stores the map
-    ncf = active_frags(ncf, cf0, col_map(state, t, Rp, 16 * cf0, cmap, wave == 0));
+    const int nact = col_map(state, t, Rp, 16 * cf0, cmap, wave == 0);
+    ncf = active_frags(ncf, cf0, nact);
     if (ncf <= 0) return;   // uniform over the block
+    if constexpr (kNarrowOk<VT, RF>) narrow = narrow_last(ncf, cf0, nact);
     __syncthreads();
   }
 
@@ -320,7 +332,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     aoff[rf] = (uint32_t)(((n0 + rf * 16 + Mfma<VT>::a_row(i16)) * D + 4 * g4) * 4);
   // staging: piece p of the chunk is column p / kPieces, 16-byte piece p % kPieces; pieces past
   // the group's columns are clamped onto the last one (a duplicate load and an identical store)
-  const int npieces = 16 * ncf * L::kPieces;
+  const int npieces = (16 * ncf - (narrow ? 12 : 0)) * L::kPieces;
   const rsrc_t rv = make_rsrc(V + (int64_t)t * Rp * D, (uint32_t)((int64_t)Rp * D * sizeof(VT)));
   uint32_t soff_v[L::kPerThread];
   VT* sdst[2][L::kPerThread];
@@ -335,11 +347,13 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   }
 
   acc_t acc[RF][kColGroup];
+  VT acc4 = 0;   // the narrow last fragment
   auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int rf = 0; rf < RF; ++rf)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf) acc[rf][cf] = acc_t{0, 0, 0, 0};
+    acc4 = 0;
   };
 
   const int nch = D / 16;
@@ -362,25 +376,37 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // the right-hand-side fragments are read in two halves (k-steps 0-1, then 2-3), which halves
   // the registers they hold; the products run in the same order as in k_phi_v
   typedef typename VecOf<VT, 2>::type vt2;
-  auto step = [&](const f4 (&x)[RF], int buf, auto full, auto first) __attribute__((always_inline)) {
+  // nw: the last fragment is narrow (4x4x4 products on its first four columns; FP64, RF = 1)
+  auto step = [&](const f4 (&x)[RF], int buf, auto full, auto nw, auto first)
+      __attribute__((always_inline)) {
+    constexpr bool kNw = decltype(nw)::value;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       vt2 b[kColGroup];
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
-          b[cf] = *(const vt2*)&lds[buf][cf * 16 + i16][4 * g4 + 2 * h];
+          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == kColGroup - 1) ? (i16 & 3) : i16)]
+                                        [4 * g4 + 2 * h];
 #pragma unroll
       for (int ss = 0; ss < 2; ++ss) {
         const int s = 2 * h + ss;
 #pragma unroll
         for (int cf = 0; cf < kColGroup; ++cf)
-          if (decltype(full)::value || cf < ncf)
+          if (decltype(full)::value || cf < ncf) {
+            if constexpr (kNw) {
+              if (cf == kColGroup - 1) {
+                acc4 = mma4<VT>((VT)x[0][s], b[cf][ss],
+                                (decltype(first)::value && s == 0) ? (VT)0 : acc4);
+                continue;
+              }
+            }
 #pragma unroll
             for (int rf = 0; rf < RF; ++rf) {
               const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[rf][cf];
               acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], b[cf][ss], cin);
             }
+          }
       }
     }
   };
@@ -388,21 +414,21 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+2; then the
   // Phi load of chunk c + kRingA - 1, issued after the staging loads so that the next wait for
   // staged data does not also wait for it; barrier.
-  auto chunk = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+  auto chunk = [&](int c, auto ic, auto full, auto nw, auto first) __attribute__((always_inline)) {
     constexpr int i = decltype(ic)::value;
-    step(a[i], i & 1, full, first);
+    step(a[i], i & 1, full, nw, first);
     stage_store((i + 1) & 1);
     stage_load(c + i + 2);
     load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
     __syncthreads();
   };
-  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+  auto ring = [&](int c, auto full, auto nw, auto first) __attribute__((always_inline)) {
     static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
-      chunk(c, ic, full,
+      chunk(c, ic, full, nw,
             std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
     });
   };
-  auto run = [&](auto full) __attribute__((always_inline)) {
+  auto run = [&](auto full, auto nw) __attribute__((always_inline)) {
     stage_load(0);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
@@ -412,22 +438,30 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     int c = 0;
     if (nch >= kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
       // first round peeled so that the accumulators start in the matrix-core result registers
-      ring(0, full, std::true_type{});
-      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
+      ring(0, full, nw, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, nw, std::false_type{});
     } else {
       zero_acc();
     }
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
-      step(a[i], i & 1, full, std::false_type{});
+      step(a[i], i & 1, full, nw, std::false_type{});
       stage_store((i + 1) & 1);
       stage_load(c + i + 2);
       __syncthreads();
     }
   };
-  if (ncf == kColGroup) run(std::true_type{});
-  else run(std::false_type{});
+  if (ncf == kColGroup) {
+    if constexpr (kNarrowOk<VT, RF>) {
+      if (narrow) run(std::true_type{}, std::true_type{});
+      else run(std::true_type{}, std::false_type{});
+    } else {
+      run(std::true_type{}, std::false_type{});
+    }
+  } else {
+    run(std::false_type{}, std::false_type{});
+  }
 
   VT* Wt = W + w_off[t];
 #pragma unroll
@@ -437,6 +471,14 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
       if (cf >= ncf) continue;
+      if constexpr (kNarrowOk<VT, RF>) {
+        if (narrow && cf == kColGroup - 1) {
+          // one value per lane: row narrow_row, column i16 & 3 (Phi row order as in a_row)
+          const int row = rb + Mfma<VT>::a_row(narrow_row(i16, g4));
+          Wt[(int64_t)((cf0 + cf) * 16 + (i16 & 3)) * np + row] = row < nt ? acc4 : (VT)0;
+          continue;
+        }
+      }
       const int j = (cf0 + cf) * 16 + i16;
       vt4 o;
 #pragma unroll
@@ -696,21 +738,27 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   const int np = (int)((w_off[t + 1] - w_off[t]) / Rp);
   int ncf = uniform(min(kColGroup, Rp / 16 - cf0));
   const int* map = nullptr;
+  bool narrow = false;
   if (state != nullptr) {
     // every wave scans (the same count); wave 0 stores the map
-    ncf = active_frags(ncf, cf0, col_map(state, t, Rp, 16 * cf0, cmap, wave == 0));
+    const int nact = col_map(state, t, Rp, 16 * cf0, cmap, wave == 0);
+    ncf = active_frags(ncf, cf0, nact);
     if (ncf <= 0) return;   // uniform over the block
+    // the narrow fragment's outputs go through the bare-product store below
+    if constexpr (kNarrowOk<VT, RF>) narrow = alpha == nullptr && narrow_last(ncf, cf0, nact);
     __syncthreads();
     map = cmap;
   }
   const int nch = np / KC;
 
   acc_t acc[RF][kColGroup];
+  VT acc4 = 0;   // the narrow last fragment
   auto zero_acc = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int f = 0; f < RF; ++f)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf) acc[f][cf] = acc_t{0, 0, 0, 0};
+    acc4 = 0;
   };
   if (nch == 0) {   // empty task (uniform over the block): the product is zero
     zero_acc();
@@ -725,7 +773,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   const uint32_t aoff0 = (uint32_t)((KS * g4 * D + (dl < D ? dl : 0)) * 4);
   // staging of W_t: piece p of the chunk is column p / kPieces, 16-byte piece p % kPieces;
   // pieces past the group's columns are clamped onto the last one
-  const int npieces = 16 * ncf * L::kPieces;
+  const int npieces = (16 * ncf - (narrow ? 12 : 0)) * L::kPieces;
   const rsrc_t rw = make_rsrc(W + w_off[t], (uint32_t)((int64_t)Rp * np * sizeof(VT)));
   uint32_t soff_w[L::kPerThread];
   VT* sdst[L::kPerThread];   // in buffer 0; buffer 1 lies kBuf elements further
@@ -759,20 +807,33 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // the W fragments are read in two halves (k-steps 0-1, then 2-3), which halves the registers
   // they hold; the products run in the same order as in k_phit_w
   typedef typename VecOf<VT, 2>::type vt2;
-  auto step = [&](const frf (&x)[KS], int buf, auto full, auto first) __attribute__((always_inline)) {
+  // nw: the last fragment is narrow (as in k_phi_v_lds)
+  auto step = [&](const frf (&x)[KS], int buf, auto full, auto nw, auto first)
+      __attribute__((always_inline)) {
+    constexpr bool kNw = decltype(nw)::value;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       vt2 b[kColGroup];
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (decltype(full)::value || cf < ncf)
-          b[cf] = *(const vt2*)&lds[buf][cf * 16 + i16][4 * g4 + 2 * h];
+          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == kColGroup - 1) ? (i16 & 3) : i16)]
+                                        [4 * g4 + 2 * h];
 #pragma unroll
       for (int ss = 0; ss < 2; ++ss) {
         const int s = 2 * h + ss;
 #pragma unroll
         for (int cf = 0; cf < kColGroup; ++cf)
-          if (decltype(full)::value || cf < ncf)
+          if (decltype(full)::value || cf < ncf) {
+            if constexpr (kNw) {
+              if (cf == kColGroup - 1) {
+                float av;
+                if constexpr (RF == 1) av = x[s]; else av = x[s][0];
+                acc4 = mma4<VT>((VT)av, b[cf][ss],
+                                (decltype(first)::value && s == 0) ? (VT)0 : acc4);
+                continue;
+              }
+            }
 #pragma unroll
             for (int f = 0; f < RF; ++f) {
               float av;
@@ -780,25 +841,26 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
               const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[f][cf];
               acc[f][cf] = Mfma<VT>::mma((VT)av, b[cf][ss], cin);
             }
+          }
       }
     }
   };
   // per chunk as in k_phi_v_lds
-  auto chunk = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+  auto chunk = [&](int c, auto ic, auto full, auto nw, auto first) __attribute__((always_inline)) {
     constexpr int i = decltype(ic)::value;
-    step(a[i], i & 1, full, first);
+    step(a[i], i & 1, full, nw, first);
     stage_store((i + 1) & 1);
     stage_load(c + i + 2);
     load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
     __syncthreads();
   };
-  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+  auto ring = [&](int c, auto full, auto nw, auto first) __attribute__((always_inline)) {
     static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
-      chunk(c, ic, full,
+      chunk(c, ic, full, nw,
             std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
     });
   };
-  auto run = [&](auto full) __attribute__((always_inline)) {
+  auto run = [&](auto full, auto nw) __attribute__((always_inline)) {
     stage_load(0);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
@@ -807,24 +869,41 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     __syncthreads();
     int c = 0;
     if (nch >= kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
-      ring(0, full, std::true_type{});
-      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
+      ring(0, full, nw, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, nw, std::false_type{});
     } else {
       zero_acc();
     }
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
-      step(a[i], i & 1, full, std::false_type{});
+      step(a[i], i & 1, full, nw, std::false_type{});
       stage_store((i + 1) & 1);
       stage_load(c + i + 2);
       __syncthreads();
     }
   };
-  if (ncf == kColGroup) run(std::true_type{});
-  else run(std::false_type{});
+  if (ncf == kColGroup) {
+    if constexpr (kNarrowOk<VT, RF>) {
+      if (narrow) run(std::true_type{}, std::true_type{});
+      else run(std::true_type{}, std::false_type{});
+    } else {
+      run(std::true_type{}, std::false_type{});
+    }
+  } else {
+    run(std::false_type{}, std::false_type{});
+  }
 
-  phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta, map);
+  phit_w_store<VT, RF>(acc, t, d0, cf0, narrow ? ncf - 1 : ncf, i16, g4, D, Rp, AV, V, alpha,
+                       colc, beta, map);
+  if constexpr (kNarrowOk<VT, RF>) {
+    if (narrow) {
+      // bare product (alpha is null here): one value per lane, row narrow_row, column i16 & 3
+      const int d = d0 + narrow_row(i16, g4);
+      const int slot = map[(kColGroup - 1) * 16 + (i16 & 3)];
+      if (d < D) AV[((int64_t)t * Rp + slot) * D + d] = acc4;
+    }
+  }
 }
 
 template <typename VT, int RF>
