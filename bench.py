@@ -67,6 +67,14 @@ def parse():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the short runs of the plain-FP32 and batching configurations that "
                          "the default FP64 run reports under detail.configs")
+    ap.add_argument("--step-active", metavar="PATH",
+                    help="write the per-step active right-hand sides of each task in the timed "
+                         "E-steps to PATH (JSON), for --step-table")
+    ap.add_argument("--step-table", nargs=2, metavar=("TRACE_CSV", "ACTIVE_JSON"),
+                    help="host only: join a rocprofv3 kernel trace (kernel_trace.csv) of a run "
+                         "with --step-active with that file and print, per group of CG steps of "
+                         "the last E-step, the product launches' durations against the column "
+                         "fragments they multiply (markdown)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after timing, copy 1 GiB device-to-device three times (a plain copy "
                          "kernel of known size, for scaling HBM byte counters)")
@@ -268,6 +276,61 @@ def roofline(m, w, math, config, prof, iters):
             "flop_per_launch": flops / max(launches, 1)}
 
 
+def fragment_work(nact, R, group=144):
+    """Column fragments (16 columns each) the CG loop's products multiply for a task with
+    `nact` active of R right-hand sides: active columns are compacted into the leading
+    fragments of each 144-column group, and a full group's last fragment with at most four
+    active columns costs a quarter (4x4x4 products, FP64 LDS-staged kernels)."""
+    work = 0.0
+    for g0 in range(0, R, group):
+        n = min(max(nact - g0, 0), group)
+        if n == 0:
+            break
+        full = min(group, -(-R // 16) * 16 - g0) // 16
+        frags = -(-n // 16)
+        work += frags - 0.75 if (frags == full == group // 16 and n - 16 * (frags - 1) <= 4) \
+            else frags
+    return work
+
+
+def step_table(trace_csv, active_json):
+    """Durations of the product launches of the last E-step in a kernel trace against the
+    fragments they multiply (steps grouped by that work, fastest first)."""
+    import csv
+    act = json.load(open(active_json))
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    names = [r["Kernel_Name"].replace("void ", "", 1) for r in rows]
+    last_init = max(i for i, n in enumerate(names) if "k_cg_init" in n)
+    per = {}
+    for r, n in zip(rows[last_init:], names[last_init:]):
+        for key in ("k_phi_v", "k_phit_w"):
+            if n.startswith("cmtcs::" + key + "_lds<") or n.startswith("cmtcs::" + key + "<"):
+                per.setdefault(key, []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    steps = act["active"][-1]            # [step][task] of the last E-step
+    R = act["R"]
+    work = [sum(fragment_work(n, R) for n in s) for s in steps]
+    cols = [sum(s) for s in steps]
+    nst = min(len(work), *(len(v) for v in per.values()))
+    order = sorted(range(nst), key=lambda u: work[u])
+    nb = 8
+    out = ["| steps | active columns (mean) | fragments multiplied (mean, of %d) | forward us "
+           "(mean) | adjoint us (mean) | adjoint us per 1000 fragments |"
+           % (act["T"] * -(-R // 16)), "|---|---|---|---|---|---|"]
+    for b in range(nb):
+        idx = order[b * nst // nb:(b + 1) * nst // nb]
+        if not idx:
+            continue
+        f = np.mean([per["k_phi_v"][u] for u in idx])
+        g = np.mean([per["k_phit_w"][u] for u in idx])
+        wk = np.mean([work[u] for u in idx])
+        out.append("| %d | %.0f | %.1f | %.1f | %.1f | %.1f |"
+                   % (len(idx), np.mean([cols[u] for u in idx]), wk, f, g,
+                      1e3 * g / max(wk, 1e-9)))
+    return "\n".join(out)
+
+
 def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup, steps,
                  unprofiled=False, alpha0=None, precond=False):
     """Times `steps` EM iterations (E-step + M-step, K probes, the workload's CG policy) after
@@ -329,6 +392,7 @@ def run_workload(torch, Cmtcs, w, dev, config, math, phi16, refine_every, warmup
                         "same_q_as_profiled": bool(torch.equal(out2["q"], out["q"]))}
     res["_first"] = first
     res["_model"] = (m, alpha, log_pi)
+    res["_iters"] = iters
     return res
 
 
@@ -394,6 +458,9 @@ def main():
     if a.sweep:
         run_sweep(a)
         return
+    if a.step_table:
+        print(step_table(*a.step_table))
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path (tasks would shard "
               "across GPUs with one all-reduce of the M-step sums per EM iteration; not built). "
@@ -418,6 +485,16 @@ def main():
                      a.steps, unprofiled=main_run and not a.no_forms)
     m, alpha, log_pi = r.pop("_model")
     first = r.pop("_first")
+    iters = r.pop("_iters")
+    if a.step_active:
+        # active right-hand sides of task t at CG step u: columns that took more than u steps
+        R = cfg.C * (cfg.K + 1)
+        steps_max = cfg.fixed_iters if cfg.fixed_iters > 0 else cfg.max_iters
+        act = []
+        for it in iters:
+            n = it.cpu().numpy()
+            act.append([[int((n[t] > u).sum()) for t in range(cfg.T)] for u in range(steps_max)])
+        json.dump({"T": cfg.T, "R": R, "active": act}, open(a.step_active, "w"))
     res = {
         "metric": "CG RHS-iters/sec + EM iter time, D=4096 T=64 C=4 K=32; MFMA/HBM roofline %",
         "value": r["value"], "unit": "RHS-iters/s", "n_gpus": 1, "steps": a.steps,
@@ -487,6 +564,7 @@ def main():
             rk = run_workload(torch, Cmtcs, wk, dev, name, math, a.phi16, a.refine_every, 1, 2)
             rk.pop("_model")[0].close()
             rk.pop("_first")
+            rk.pop("_iters")
             configs["%s_%s" % (name, math)] = {"workload": workload_name(wk.cfg), "math": math,
                                                **rk}
             print("config %s %s done" % (name, math), file=sys.stderr, flush=True)

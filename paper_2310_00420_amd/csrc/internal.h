@@ -153,11 +153,12 @@ template <typename T> __device__ inline T buf_load(rsrc_t r, uint32_t voff, uint
 
 // Calls f(std::integral_constant<int, i>{}) for i = 0 .. N-1 (a compile-time unrolled loop).
 template <typename F, int... I>
-__device__ inline void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+__device__ inline __attribute__((always_inline)) void static_for_impl(
+    F&& f, std::integer_sequence<int, I...>) {
   (f(std::integral_constant<int, I>{}), ...);
 }
 template <int N, typename F>
-__device__ inline void static_for(F&& f) {
+__device__ inline __attribute__((always_inline)) void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 

@@ -65,11 +65,12 @@ __device__ inline int active_frags(int ncf, int cf0, int nact) {
   return min(ncf, (nact - 16 * cf0 + 15) >> 4);
 }
 
-// Whether a full group's last fragment holds at most four active positions: the LDS-staged FP64
-// kernels then multiply only its first four columns, with 4x4x4 products (a quarter of the
-// work; the other twelve are stopped or padding columns, whose outputs nothing reads).
+// Whether the last fragment a tile multiplies holds at most four active positions: the
+// LDS-staged FP64 kernels then multiply only its first four columns, with 4x4x4 products (a
+// quarter of the work; the other twelve are stopped or padding columns, whose outputs nothing
+// reads).
 __device__ inline bool narrow_last(int ncf, int cf0, int nact) {
-  return ncf == kColGroup && nact - 16 * (cf0 + kColGroup - 1) <= 4;
+  return nact - 16 * (cf0 + ncf - 1) <= 4;
 }
 template <typename VT, int RF>
 constexpr bool kNarrowOk = sizeof(VT) == 8 && RF == 1;
@@ -377,25 +378,26 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // the registers they hold; the products run in the same order as in k_phi_v
   typedef typename VecOf<VT, 2>::type vt2;
   // nw: the last fragment is narrow (4x4x4 products on its first four columns; FP64, RF = 1)
-  auto step = [&](const f4 (&x)[RF], int buf, auto full, auto nw, auto first)
+  auto step = [&](const f4 (&x)[RF], int buf, auto nf, auto nw, auto first)
       __attribute__((always_inline)) {
+    constexpr int NF = decltype(nf)::value;
     constexpr bool kNw = decltype(nw)::value;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       vt2 b[kColGroup];
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
-        if (decltype(full)::value || cf < ncf)
-          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == kColGroup - 1) ? (i16 & 3) : i16)]
+        if (cf < NF)
+          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == NF - 1) ? (i16 & 3) : i16)]
                                         [4 * g4 + 2 * h];
 #pragma unroll
       for (int ss = 0; ss < 2; ++ss) {
         const int s = 2 * h + ss;
 #pragma unroll
         for (int cf = 0; cf < kColGroup; ++cf)
-          if (decltype(full)::value || cf < ncf) {
+          if (cf < NF) {
             if constexpr (kNw) {
-              if (cf == kColGroup - 1) {
+              if (cf == NF - 1) {
                 acc4 = mma4<VT>((VT)x[0][s], b[cf][ss],
                                 (decltype(first)::value && s == 0) ? (VT)0 : acc4);
                 continue;
@@ -414,21 +416,21 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // (whose chunk c-1 every wave finished before the last barrier); stage chunk c+2; then the
   // Phi load of chunk c + kRingA - 1, issued after the staging loads so that the next wait for
   // staged data does not also wait for it; barrier.
-  auto chunk = [&](int c, auto ic, auto full, auto nw, auto first) __attribute__((always_inline)) {
+  auto chunk = [&](int c, auto ic, auto nf, auto nw, auto first) __attribute__((always_inline)) {
     constexpr int i = decltype(ic)::value;
-    step(a[i], i & 1, full, nw, first);
+    step(a[i], i & 1, nf, nw, first);
     stage_store((i + 1) & 1);
     stage_load(c + i + 2);
     load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
     __syncthreads();
   };
-  auto ring = [&](int c, auto full, auto nw, auto first) __attribute__((always_inline)) {
+  auto ring = [&](int c, auto nf, auto nw, auto first) __attribute__((always_inline)) {
     static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
-      chunk(c, ic, full, nw,
+      chunk(c, ic, nf, nw,
             std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
     });
   };
-  auto run = [&](auto full, auto nw) __attribute__((always_inline)) {
+  auto run = [&](auto nf, auto nw) __attribute__((always_inline)) {
     stage_load(0);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
@@ -438,30 +440,33 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     int c = 0;
     if (nch >= kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
       // first round peeled so that the accumulators start in the matrix-core result registers
-      ring(0, full, nw, std::true_type{});
-      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, nw, std::false_type{});
+      ring(0, nf, nw, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, nf, nw, std::false_type{});
     } else {
       zero_acc();
     }
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
-      step(a[i], i & 1, full, nw, std::false_type{});
+      step(a[i], i & 1, nf, nw, std::false_type{});
       stage_store((i + 1) & 1);
       stage_load(c + i + 2);
       __syncthreads();
     }
   };
-  if (ncf == kColGroup) {
+  // one instantiation per fragment count (and narrow last fragment), chosen once per tile:
+  // guards on a run-time count inside the pipeline cost more than the skipped products save
+  static_for<kColGroup>([&](auto i) __attribute__((always_inline)) {
+    constexpr int NF = decltype(i)::value + 1;
+    if (ncf != NF) return;
     if constexpr (kNarrowOk<VT, RF>) {
-      if (narrow) run(std::true_type{}, std::true_type{});
-      else run(std::true_type{}, std::false_type{});
-    } else {
-      run(std::true_type{}, std::false_type{});
+      if (narrow) {
+        run(std::integral_constant<int, NF>{}, std::true_type{});
+        return;
+      }
     }
-  } else {
-    run(std::false_type{}, std::false_type{});
-  }
+    run(std::integral_constant<int, NF>{}, std::false_type{});
+  });
 
   VT* Wt = W + w_off[t];
 #pragma unroll
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     for (int cf = 0; cf < kColGroup; ++cf) {
       if (cf >= ncf) continue;
       if constexpr (kNarrowOk<VT, RF>) {
-        if (narrow && cf == kColGroup - 1) {
+        if (narrow && cf == ncf - 1) {
           // one value per lane: row narrow_row, column i16 & 3 (Phi row order as in a_row)
           const int row = rb + Mfma<VT>::a_row(narrow_row(i16, g4));
           Wt[(int64_t)((cf0 + cf) * 16 + (i16 & 3)) * np + row] = row < nt ? acc4 : (VT)0;
@@ -808,25 +813,26 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // they hold; the products run in the same order as in k_phit_w
   typedef typename VecOf<VT, 2>::type vt2;
   // nw: the last fragment is narrow (as in k_phi_v_lds)
-  auto step = [&](const frf (&x)[KS], int buf, auto full, auto nw, auto first)
+  auto step = [&](const frf (&x)[KS], int buf, auto nf, auto nw, auto first)
       __attribute__((always_inline)) {
+    constexpr int NF = decltype(nf)::value;
     constexpr bool kNw = decltype(nw)::value;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       vt2 b[kColGroup];
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
-        if (decltype(full)::value || cf < ncf)
-          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == kColGroup - 1) ? (i16 & 3) : i16)]
+        if (cf < NF)
+          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == NF - 1) ? (i16 & 3) : i16)]
                                         [4 * g4 + 2 * h];
 #pragma unroll
       for (int ss = 0; ss < 2; ++ss) {
         const int s = 2 * h + ss;
 #pragma unroll
         for (int cf = 0; cf < kColGroup; ++cf)
-          if (decltype(full)::value || cf < ncf) {
+          if (cf < NF) {
             if constexpr (kNw) {
-              if (cf == kColGroup - 1) {
+              if (cf == NF - 1) {
                 float av;
                 if constexpr (RF == 1) av = x[s]; else av = x[s][0];
                 acc4 = mma4<VT>((VT)av, b[cf][ss],
@@ -846,21 +852,21 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     }
   };
   // per chunk as in k_phi_v_lds
-  auto chunk = [&](int c, auto ic, auto full, auto nw, auto first) __attribute__((always_inline)) {
+  auto chunk = [&](int c, auto ic, auto nf, auto nw, auto first) __attribute__((always_inline)) {
     constexpr int i = decltype(ic)::value;
-    step(a[i], i & 1, full, nw, first);
+    step(a[i], i & 1, nf, nw, first);
     stage_store((i + 1) & 1);
     stage_load(c + i + 2);
     load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
     __syncthreads();
   };
-  auto ring = [&](int c, auto full, auto nw, auto first) __attribute__((always_inline)) {
+  auto ring = [&](int c, auto nf, auto nw, auto first) __attribute__((always_inline)) {
     static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
-      chunk(c, ic, full, nw,
+      chunk(c, ic, nf, nw,
             std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
     });
   };
-  auto run = [&](auto full, auto nw) __attribute__((always_inline)) {
+  auto run = [&](auto nf, auto nw) __attribute__((always_inline)) {
     stage_load(0);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
@@ -869,30 +875,33 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     __syncthreads();
     int c = 0;
     if (nch >= kRingA) {   // kRingA is even: chunk c + i is in buffer i & 1
-      ring(0, full, nw, std::true_type{});
-      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, nw, std::false_type{});
+      ring(0, nf, nw, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, nf, nw, std::false_type{});
     } else {
       zero_acc();
     }
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
-      step(a[i], i & 1, full, nw, std::false_type{});
+      step(a[i], i & 1, nf, nw, std::false_type{});
       stage_store((i + 1) & 1);
       stage_load(c + i + 2);
       __syncthreads();
     }
   };
-  if (ncf == kColGroup) {
+  // one instantiation per fragment count (and narrow last fragment), chosen once per tile:
+  // guards on a run-time count inside the pipeline cost more than the skipped products save
+  static_for<kColGroup>([&](auto i) __attribute__((always_inline)) {
+    constexpr int NF = decltype(i)::value + 1;
+    if (ncf != NF) return;
     if constexpr (kNarrowOk<VT, RF>) {
-      if (narrow) run(std::true_type{}, std::true_type{});
-      else run(std::true_type{}, std::false_type{});
-    } else {
-      run(std::true_type{}, std::false_type{});
+      if (narrow) {
+        run(std::integral_constant<int, NF>{}, std::true_type{});
+        return;
+      }
     }
-  } else {
-    run(std::false_type{}, std::false_type{});
-  }
+    run(std::integral_constant<int, NF>{}, std::false_type{});
+  });
 
   phit_w_store<VT, RF>(acc, t, d0, cf0, narrow ? ncf - 1 : ncf, i16, g4, D, Rp, AV, V, alpha,
                        colc, beta, map);
@@ -900,7 +909,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     if (narrow) {
       // bare product (alpha is null here): one value per lane, row narrow_row, column i16 & 3
       const int d = d0 + narrow_row(i16, g4);
-      const int slot = map[(kColGroup - 1) * 16 + (i16 & 3)];
+      const int slot = map[(ncf - 1) * 16 + (i16 & 3)];
       if (d < D) AV[((int64_t)t * Rp + slot) * D + d] = acc4;
     }
   }
