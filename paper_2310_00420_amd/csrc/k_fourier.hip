@@ -14,7 +14,7 @@
 // v1 + i v2 gives the two real results as the real and imaginary parts, so one complex FFT pair
 // serves both.  The transform is the Stockham autosort FFT (radix 8, with one radix-2 or
 // radix-4 stage for the remaining factor), out of place between the two LDS buffers.
-// Twiddles come from a table of cos(2 pi i / D), i <= D/4, built by each workgroup in LDS.
+// Twiddles come from per-stage tables built by each workgroup in LDS.
 #include <algorithm>
 
 #include "internal.h"
@@ -24,22 +24,26 @@ namespace cmtcs {
 
 namespace {
 
-// exp(-2 pi i m / N) (forward) or its conjugate (inverse), 0 <= m < N, from the quarter-wave
-// cosine table c[i] = cos(2 pi i / N), i = 0..N/4 (sin(2 pi i / N) = c[N/4 - i]).
-template <bool INV>
-__device__ inline d2 root(int m, int N, const double* c) {
-  const int q4 = N >> 2;
-  const int quad = m / q4, i = m - quad * q4;
-  const double cs = c[i], sn = c[q4 - i];
-  double re, im;   // cos(theta), -sin(theta) for theta = 2 pi m / N
-  switch (quad) {
-    case 0: re = cs; im = -sn; break;
-    case 1: re = -sn; im = -cs; break;
-    case 2: re = -cs; im = sn; break;
-    default: re = sn; im = cs; break;
-  }
-  return d2{re, INV ? -im : im};
+// Stages of the length-2^LOGN transform: one radix-2 or radix-4 stage for the factor that
+// radix 8 leaves, then radix 8.  Stage s (sub-transform length Ns before it, radix R) uses the
+// twiddles w^k = exp(-2 pi i k / (R Ns)), k < Ns, stored contiguously per stage, so that the
+// lanes of a butterfly row read consecutive entries.
+template <int LOGN>
+constexpr int first_radix() { return LOGN % 3 == 1 ? 2 : LOGN % 3 == 2 ? 4 : 8; }
+template <int LOGN>
+constexpr int twiddle_len() {
+  int n = 0;
+  for (int ns = 1, r = first_radix<LOGN>(); ns < (1 << LOGN); ns *= r, r = 8) n += ns;
+  return n;
 }
+
+// LDS slot of point i in a transform buffer: one unused slot after every 16 points, so that
+// the strided stores of the first radix-8 stage (stride 8 points) fall in distinct banks while
+// runs of consecutive points stay contiguous.  For a multiple m of 16, pad(i + m) =
+// pad(i) + pad(m).
+__device__ inline int pad(int i) { return i + (i >> 4); }
+template <int N>
+constexpr int padded_len() { return N + N / 16; }
 
 __device__ inline d2 cmul(d2 a, d2 b) {
   return d2{__builtin_fma(a[0], b[0], -a[1] * b[1]), __builtin_fma(a[0], b[1], a[1] * b[0])};
@@ -63,7 +67,7 @@ __device__ inline void dft4(d2 x0, d2 x1, d2 x2, d2 x3, d2& u0, d2& u1, d2& u2, 
 // dst[(j / Ns) R Ns + k + r Ns].  Ns is the length of the sub-transforms already done.  Every
 // thread of the block must call it; one barrier at the end publishes dst.
 template <int R, bool INV, int BS, int N>
-__device__ inline void fft_stage(const d2* src, d2* dst, const double* ctab, int Ns) {
+__device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns) {
   constexpr int NBF = N / R;                       // butterflies
   constexpr int PER = NBF >= BS ? NBF / BS : 1;    // per thread
   // one butterfly at a time: their registers would otherwise crowd out the columns' state
@@ -73,12 +77,13 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const double* ctab, int
     if (j < NBF) {
       d2 v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = src[j + r * NBF];
+      for (int r = 0; r < R; ++r)
+        v[r] = src[NBF % 16 == 0 ? pad(j) + r * (NBF + NBF / 16) : pad(j + r * NBF)];
       const int k = j & (Ns - 1);
-      const int step = N / (R * Ns);
-      // w^k from the table; w^2k and w^3k as its square and cube (two FP64 complex products
-      // instead of four more LDS reads)
-      const d2 w1 = root<INV>(k * step, N, ctab);
+      // w^k from the stage's table (conjugated for the inverse); its higher powers by FP64
+      // complex products instead of more LDS reads
+      const d2 t1 = tw[k];
+      const d2 w1 = INV ? d2{t1[0], -t1[1]} : t1;
       v[1] = cmul(v[1], w1);
       if constexpr (R >= 4) {
         const d2 w2 = cmul(w1, w1), w3 = cmul(w1, w2);
@@ -117,7 +122,7 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const double* ctab, int
       }
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[base + r * Ns] = u[r];
+      for (int r = 0; r < R; ++r) dst[pad(base + r * Ns)] = u[r];
     }
   }
   __syncthreads();
@@ -126,32 +131,31 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const double* ctab, int
 // Unnormalised DFT of the N points in *in (forward: exp(-2 pi i k d / N); inverse: conjugate),
 // ping-ponging between the two buffers; on return *in points to the buffer holding the result.
 template <bool INV, int BS, int LOGN>
-__device__ inline void fft(d2** in, d2** other, const double* ctab) {
+__device__ inline void fft(d2** in, d2** other, const d2* tw) {
   constexpr int N = 1 << LOGN;
   int Ns = 1;
   // radix 8 where it divides, one radix-2 or radix-4 stage first for the remaining factor
-  if constexpr (LOGN % 3 == 1) {
-    fft_stage<2, INV, BS, N>(*in, *other, ctab, Ns);
+  if constexpr (first_radix<LOGN>() != 8) {
+    fft_stage<first_radix<LOGN>(), INV, BS, N>(*in, *other, tw, Ns);
     d2* tmp = *in; *in = *other; *other = tmp;
-    Ns = 2;
-  } else if constexpr (LOGN % 3 == 2) {
-    fft_stage<4, INV, BS, N>(*in, *other, ctab, Ns);
-    d2* tmp = *in; *in = *other; *other = tmp;
-    Ns = 4;
+    tw += 1;
+    Ns = first_radix<LOGN>();
   }
   // a runtime loop over the radix-8 stages: unrolled, the address arithmetic of every stage is
   // invariant across CG steps and would be kept in registers
 #pragma unroll 1
   for (; Ns < N; Ns *= 8) {
-    fft_stage<8, INV, BS, N>(*in, *other, ctab, Ns);
+    fft_stage<8, INV, BS, N>(*in, *other, tw, Ns);
     d2* tmp = *in; *in = *other; *other = tmp;
+    tw += Ns;
   }
 }
 
 }  // namespace
 
-// Threads per workgroup for length 2^LOGN: a quarter of the length (one radix-4 butterfly per
-// thread and stage, four elements of each column in registers), at least one wave.
+// Threads per workgroup for length 2^LOGN: a quarter of the length (four elements of each
+// column in registers), at most 512 (one radix-8 butterfly per thread and stage at D = 4096),
+// at least one wave.
 template <int LOGN>
 constexpr int fourier_bs() {
   return std::max(64, std::min(512, (1 << LOGN) / 4));
@@ -171,16 +175,30 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
     const uint64_t* __restrict__ keyp, const int8_t* __restrict__ probes, int crn, double beta,
     double tol2, int steps, int fixed, int T, int C, int R, int Rp) {
   constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>(), E = N / BS;
+  constexpr int NP = padded_len<N>();
   extern __shared__ double lds[];
-  d2* bufA = reinterpret_cast<d2*>(lds);           // two buffers of N complex points
-  d2* bufB = bufA + N;
-  double* ctab = lds + 4 * N;                      // N/4 + 1 cosines (N/4 + 2 slots)
-  double* red = ctab + (N / 4 + 2);                // 2 BS/64 partial sums
+  d2* bufA = reinterpret_cast<d2*>(lds);           // two buffers of N complex points (padded)
+  d2* bufB = bufA + NP;
+  d2* tw = bufB + NP;                              // twiddles of every stage
+  double* red = reinterpret_cast<double*>(tw + twiddle_len<LOGN>());   // 2 BS/64 partial sums
   const int tid = threadIdx.x;
+  // LDS slot of the thread's point e: pad(tid + e BS) (BS is a multiple of 16)
+  const int ptid = pad(tid);
+  constexpr int PBS = BS + BS / 16;
   const int pairs = Rp / 2;
   const int t = blockIdx.x / pairs, p = blockIdx.x % pairs;
   const int j0 = 2 * p;
-  for (int i = tid; i <= N / 4; i += BS) ctab[i] = cospi(2.0 * (double)i / (double)N);
+  {
+    int off = 0;
+    for (int ns = 1, r = first_radix<LOGN>(); ns < N; ns *= r, r = 8) {
+      for (int k = tid; k < ns; k += BS) {
+        double sn, cs;
+        sincospi(2.0 * (double)k / (double)(r * ns), &sn, &cs);
+        tw[off + k] = d2{cs, -sn};
+      }
+      off += ns;
+    }
+  }
 
   // the two columns: right-hand sides, diagonal terms, multipliers
   // x, r and d of both columns stay in registers, and so do alpha of each column's cluster
@@ -233,24 +251,25 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
   auto apply = [&](const bool* on) __attribute__((always_inline)) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      bufA[tid + e * BS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
+      bufA[ptid + e * PBS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
     __syncthreads();
     d2* in = bufA;
     d2* other = bufB;
-    fft<false, BS, LOGN>(&in, &other, ctab);
+    fft<false, BS, LOGN>(&in, &other, tw);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      in[tid + e * BS] = in[tid + e * BS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
+      in[ptid + e * PBS] =
+          in[ptid + e * PBS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
     __syncthreads();
-    fft<true, BS, LOGN>(&in, &other, ctab);
+    fft<true, BS, LOGN>(&in, &other, tw);
     res = in;
   };
   auto ad_of = [&](int q, int e) __attribute__((always_inline)) {
-    return __builtin_fma((double)al[q][e], dv[q][e], res[tid + e * BS][q]);
+    return __builtin_fma((double)al[q][e], dv[q][e], res[ptid + e * PBS][q]);
   };
 
   if (mode == 1) {
-    __syncthreads();   // the cosine table
+    __syncthreads();   // the twiddle tables
     apply(live);
 #pragma unroll
     for (int q = 0; q < 2; ++q)
@@ -396,8 +415,9 @@ static hipError_t fourier_one(const Geometry& g, const CgState& s, const int* hc
                               const RhsSource& src, double tol2, int steps, int fixed,
                               hipStream_t st) {
   constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>();
-  // two buffers of N complex points, the cosine table, the reduction slots
-  const size_t lds = sizeof(double) * (4 * N + N / 4 + 2 + 2 * (BS / 64));
+  // two padded buffers of N complex points, the twiddle tables, the reduction slots
+  const size_t lds =
+      sizeof(double) * (4 * padded_len<N>() + 2 * twiddle_len<LOGN>() + 2 * (BS / 64));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_fourier_cg<LOGN>,
