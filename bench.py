@@ -239,6 +239,53 @@ def run_sweep(a):
                           data="synthetic Gaussian Phi", rows=rows)), flush=True)
 
 
+def dense_em_iteration(torch, phi, row_off, y, beta, alpha, log_pi, budget=64 << 30):
+    """One iteration of standard EM (Eqs. (estep), (mstep)), the comparison method that CoFEM
+    replaces, on the same GPU in FP64 through torch.linalg: per task and cluster a Cholesky
+    factorisation L of A = beta Phi_t^T Phi_t + diag(alpha_c), mu = A^-1 b_t, the diagonal of
+    Sigma = A^-1 = L^-T L^-1 as column sums of (L^-1)^2, log det Sigma = -2 sum log diag L, ell,
+    q and the M-step.  A baseline for timing (not part of the library).  phi [sum N_t][D] and y
+    float32 on the device; alpha [C][D], log_pi [C] float64 on the device; tasks are processed
+    in groups sized to `budget` bytes of factor storage.
+
+    Not called by any timing run: over 256 matrices of order 1024 (T = 64, C = 4) the batched
+    factorisation and solves faulted the GPU inside torch.linalg, with no cause established."""
+    f64 = torch.float64
+    dev = phi.device
+    T = len(row_off) - 1
+    C, D = alpha.shape
+    tb = int(max(1, min(T, budget // (4 * C * D * D * 8))))
+    mu = torch.empty(T, C, D, dtype=f64, device=dev)
+    var = torch.empty_like(mu)
+    logdet = torch.empty(T, C, dtype=f64, device=dev)
+    ell = torch.empty_like(logdet)
+    sla = torch.log(alpha).sum(dim=1)
+    for t0 in range(0, T, tb):
+        ts = list(range(t0, min(T, t0 + tb)))
+        P = [phi[int(row_off[t]):int(row_off[t + 1])].double() for t in ts]
+        yv = [y[int(row_off[t]):int(row_off[t + 1])].double() for t in ts]
+        G = torch.stack([beta * (p.T.contiguous() @ p) for p in P])
+        b = torch.stack([beta * (p.T.contiguous() @ v) for p, v in zip(P, yv)])
+        A = G[:, None] + torch.diag_embed(alpha)[None]
+        del G
+        L = torch.linalg.cholesky(A)
+        del A
+        m = torch.cholesky_solve(b[:, None, :, None].expand(-1, C, -1, -1).contiguous(), L)[..., 0]
+        eye = torch.eye(D, dtype=f64, device=dev).expand(len(ts), C, D, D)
+        Li = torch.linalg.solve_triangular(L, eye, upper=False)
+        v = (Li * Li).sum(dim=-2)
+        del Li
+        ld = -2.0 * torch.log(torch.diagonal(L, dim1=-2, dim2=-1)).sum(dim=-1)
+        del L
+        mu[t0:t0 + len(ts)] = m
+        var[t0:t0 + len(ts)] = v
+        logdet[t0:t0 + len(ts)] = ld
+        ell[t0:t0 + len(ts)] = ld + sla[None] + (b[:, None, :] * m).sum(dim=-1)
+    q = torch.softmax(0.5 * ell + log_pi[None], dim=1)
+    den = (q[:, :, None] * (mu * mu + var)).sum(dim=0)
+    return dict(mu=mu, var=var, logdet=logdet, ell=ell, q=q, alpha=q.sum(dim=0)[:, None] / den)
+
+
 def roofline(m, w, math, config, prof, iters):
     """Roofline position of the dominant product over the profiled EM iterations (HIP-event
     kernel time on the library's stream, algorithmic work of the RHS-iterations executed)."""
