@@ -112,7 +112,11 @@ typedef struct {
                                ignored for OP_PARTIAL_FOURIER)                              */
   cmtcs_dtype_t phi_dtype;  /* F32 for MATH_F64 / MATH_F32; for MATH_MIXED the 16-bit type
                                (BF16 or F16) the library stores Phi in                      */
-  const float* phi_f32;     /* reserved, must be NULL                                       */
+  const float* phi_resid;   /* MATH_MIXED only: optional device [row_off[T]][D] float Phi
+                               for the FP32 true-residual products (opts.refine_every), e.g.
+                               a more accurate copy than phi; NULL = phi.  Caller-owned, read
+                               by every residual replacement.  Must be NULL for the other
+                               math modes and for OP_PARTIAL_FOURIER (CMTCS_E_INVALID)       */
   const float* y;           /* device measurements, stacked like Phi: [row_off[T]] (OP_DENSE)
                                or [row_off[T]][2] (re, im) pairs (OP_PARTIAL_FOURIER)       */
   double beta;              /* noise precision, > 0                                         */

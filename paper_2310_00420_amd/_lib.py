@@ -24,7 +24,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int32), ("C", ctypes.c_int32), ("D", ctypes.c_int32),
                 ("row_off", ctypes.POINTER(ctypes.c_int64)),
                 ("phi", ctypes.c_void_p), ("phi_dtype", ctypes.c_int),
-                ("phi_f32", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("phi_resid", ctypes.c_void_p), ("y", ctypes.c_void_p),
                 ("beta", ctypes.c_double), ("math", ctypes.c_int),
                 ("max_rhs", ctypes.c_int32), ("max_iters", ctypes.c_int32),
                 ("max_K", ctypes.c_int32), ("op", ctypes.c_int), ("freq", ctypes.c_void_p)]

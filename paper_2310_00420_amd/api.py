@@ -53,7 +53,7 @@ class Cmtcs:
     """
 
     def __init__(self, phi, row_off, y, beta, C, math="f64", max_rhs=None, max_iters=200,
-                 max_K=32, phi16="bf16", freq=None, D=None):
+                 max_K=32, phi16="bf16", freq=None, D=None, phi_resid=None):
         lib = _lib.load()
         self.row_off = np.ascontiguousarray(np.asarray(row_off, dtype=np.int64))
         self.T = len(self.row_off) - 1
@@ -75,7 +75,9 @@ class Cmtcs:
         dtype = _lib.CMTCS_F32
         if math == "mixed":
             dtype = {"bf16": _lib.CMTCS_BF16, "f16": _lib.CMTCS_F16}[phi16]
-        self.phi, self.y, self.freq = phi, y, freq
+        if phi_resid is not None:
+            _need(phi_resid, torch.float32, (rows, self.D), "phi_resid")
+        self.phi, self.y, self.freq, self.phi_resid = phi, y, freq, phi_resid
         self.max_K = int(max_K)
         self.max_iters = int(max_iters)
         self.max_rhs = int(max_rhs if max_rhs is not None else self.C * (self.max_K + 1))
@@ -84,7 +86,9 @@ class Cmtcs:
         self._roff = self.row_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         p = _lib.Problem(T=self.T, C=self.C, D=self.D, row_off=self._roff,
                          phi=None if phi is None else phi.data_ptr(),
-                         phi_dtype=dtype, phi_f32=None, y=y.data_ptr(), beta=self.beta,
+                         phi_dtype=dtype,
+                         phi_resid=None if phi_resid is None else phi_resid.data_ptr(),
+                         y=y.data_ptr(), beta=self.beta,
                          math=MATH[math], max_rhs=self.max_rhs, max_iters=self.max_iters,
                          max_K=self.max_K,
                          op=_lib.CMTCS_OP_PARTIAL_FOURIER if self.fourier else _lib.CMTCS_OP_DENSE,
@@ -309,7 +313,7 @@ def apply_noalloc(phi, row_off, beta, C, alpha, V, col_cluster, math="f64"):
     AV = torch.empty_like(V)
     p = _lib.Problem(T=T, C=int(C), D=D,
                      row_off=row_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                     phi=phi.data_ptr(), phi_dtype=_lib.CMTCS_F32, phi_f32=None, y=None,
+                     phi=phi.data_ptr(), phi_dtype=_lib.CMTCS_F32, phi_resid=None, y=None,
                      beta=float(beta), math=MATH[math], max_rhs=R, max_iters=1, max_K=0,
                      op=_lib.CMTCS_OP_DENSE, freq=None)
     stream = torch.cuda.current_stream(V.device).cuda_stream

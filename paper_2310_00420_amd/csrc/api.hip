@@ -60,6 +60,7 @@ struct cmtcs_handle_s {
   size_t vbytes = 8;
   std::vector<int64_t> row_off;
   const float* phi = nullptr;
+  const float* phi_res = nullptr;   // MATH_MIXED: Phi of the FP32 true-residual products
   const float* y = nullptr;
   hipStream_t st = nullptr;
 
@@ -449,9 +450,9 @@ struct cmtcs_handle_s {
       if (replace) {
         // true-residual replacement: r = b - A x with FP32 products from the FP32 Phi, then
         // xi, d and the stop decision from the replaced residual
-        HIP_TRY(launch_phi_v<float>(g, phi, fwd_tiles, nfwd, (const float*)X, (float*)W, act_u,
-                                    nullptr, fwd_rows, st), "launch(phi_v residual)");
-        HIP_TRY(launch_phit_w<float>(g, phi, adj_tiles, nadj, (const float*)W, (const float*)X,
+        HIP_TRY(launch_phi_v<float>(g, phi_res, fwd_tiles, nfwd, (const float*)X, (float*)W,
+                                    act_u, nullptr, fwd_rows, st), "launch(phi_v residual)");
+        HIP_TRY(launch_phit_w<float>(g, phi_res, adj_tiles, nadj, (const float*)W, (const float*)X,
                                      (float*)AD, alpha, colc, beta, act_u, nullptr, adj_rows,
                                      st),
                 "launch(phit_w residual)");
@@ -893,6 +894,8 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
     return fail(CMTCS_E_INVALID, "max_rhs must be >= C*(max_K+1)");
   if (p->math != CMTCS_MATH_F64 && p->math != CMTCS_MATH_F32 && p->math != CMTCS_MATH_MIXED)
     return fail(CMTCS_E_INVALID, "unknown math mode");
+  if (p->phi_resid != nullptr && (p->math != CMTCS_MATH_MIXED || fourier))
+    return fail(CMTCS_E_INVALID, "phi_resid is for MATH_MIXED dense problems only");
   if (p->math == CMTCS_MATH_MIXED) {
     if (p->phi_dtype != CMTCS_BF16 && p->phi_dtype != CMTCS_F16)
       return fail(CMTCS_E_INVALID, "MATH_MIXED needs phi_dtype BF16 or F16");
@@ -926,6 +929,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   h->row_off.assign(p->row_off, p->row_off + p->T + 1);
   h->phi_dtype = p->phi_dtype;
   h->phi = (const float*)p->phi;
+  h->phi_res = p->phi_resid != nullptr ? p->phi_resid : (const float*)p->phi;
   h->y = p->y;
   h->fourier = fourier;
   h->freq = p->freq;

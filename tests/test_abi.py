@@ -42,7 +42,7 @@ def _problem(**over):
     T = over.pop("T", 2)
     row_off = over.pop("row_off", np.array([0, 4, 8], np.int64))
     p = dict(T=T, C=2, D=32, row_off=row_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-             phi=1, phi_dtype=_lib.CMTCS_F32, phi_f32=None, y=1, beta=1.0,
+             phi=1, phi_dtype=_lib.CMTCS_F32, phi_resid=None, y=1, beta=1.0,
              math=_lib.CMTCS_MATH_F64, max_rhs=34, max_iters=10, max_K=16)
     p.update(over)
     return _lib.Problem(**p), row_off
@@ -63,6 +63,8 @@ def _problem(**over):
     (dict(math=_lib.CMTCS_MATH_MIXED), "MATH_MIXED"),
     (dict(math=_lib.CMTCS_MATH_MIXED, phi_dtype=_lib.CMTCS_BF16, D=48), "multiple of 32"),
     (dict(phi_dtype=_lib.CMTCS_BF16), "phi_dtype F32"),
+    (dict(phi_resid=1), "phi_resid"),
+    (dict(math=_lib.CMTCS_MATH_F32, phi_resid=1), "phi_resid"),
     (dict(D=16384, row_off=np.array([0, 4, 65540], np.int64)), "Phi block"),
     (dict(D=16384, max_rhs=40000), "column slots"),
 ])

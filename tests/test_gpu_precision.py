@@ -41,12 +41,34 @@ def _round16(a, kind):
     return u.view(np.float32).astype(np.float64)
 
 
-def _model(w, kind, K, max_iters, max_rhs=None):
+def _model(w, kind, K, max_iters, max_rhs=None, phi_resid=None):
     from paper_2310_00420_amd import Cmtcs
     phi = torch.from_numpy(np.ascontiguousarray(w.Phi)).to(DEV)
     y = torch.from_numpy(np.ascontiguousarray(w.y)).to(DEV)
     return Cmtcs(phi, w.row_off, y, w.beta, w.cfg.C, math="mixed", phi16=kind,
-                 max_iters=max_iters, max_K=K, max_rhs=max_rhs)
+                 max_iters=max_iters, max_K=K, max_rhs=max_rhs, phi_resid=phi_resid)
+
+
+def test_mixed_phi_resid_is_the_residual_operator():
+    """cmtcs_problem_t.phi_resid supplies the Phi of the FP32 true-residual products: a copy of
+    phi gives the same E-step bit for bit as none, and a different matrix (phi scaled by 1.01)
+    changes the results, which only the residual replacements can have done."""
+    w = synth.make(synth.Config("mx-res", T=4, C=2, D=256, N=128, sparsity=8, groups=2, K=8,
+                                tol=1e-6, max_iters=300, sigma=1.0))
+    alpha = w.alpha0 + 1.0
+    kw = dict(tol=w.cfg.tol, max_iters=w.cfg.max_iters, refine_every=5, stats=True)
+    phi = torch.from_numpy(np.ascontiguousarray(w.Phi)).to(DEV)
+    out = []
+    for pr in (None, phi.clone(), phi * 1.01):
+        m = _model(w, "f16", w.cfg.K, w.cfg.max_iters, phi_resid=pr)
+        g = m.estep(alpha_dev(alpha), log_pi_dev(w.log_pi), w.cfg.K, **kw)
+        torch.cuda.synchronize()
+        out.append({k: v.clone() for k, v in g.items()})
+        m.close()
+    for k in ("mu", "s", "logdet", "ell", "iters"):
+        assert torch.equal(out[0][k], out[1][k]), k
+    assert not torch.equal(out[0]["mu"], out[2]["mu"])
+    assert torch.isfinite(out[2]["mu"]).all()
 
 
 @pytest.mark.parametrize("kind", ["bf16", "f16"])
