@@ -324,19 +324,17 @@ def roofline(m, w, math, config, prof, iters):
 
 
 def fragment_work(nact, R, group=144):
-    """Column fragments (16 columns each) the CG loop's products multiply for a task with
-    `nact` active of R right-hand sides: active columns are compacted into the leading
-    fragments of each 144-column group, and a full group's last fragment with at most four
-    active columns costs a quarter (4x4x4 products, FP64 LDS-staged kernels)."""
+    """Column fragments (16 columns each) the CG loop's FP64 LDS-staged products multiply for a
+    task with `nact` active of R right-hand sides: active columns are compacted into the
+    leading fragments of each 144-column group, and a last fragment with at most four active
+    columns costs a quarter (4x4x4 products)."""
     work = 0.0
     for g0 in range(0, R, group):
         n = min(max(nact - g0, 0), group)
         if n == 0:
             break
-        full = min(group, -(-R // 16) * 16 - g0) // 16
         frags = -(-n // 16)
-        work += frags - 0.75 if (frags == full == group // 16 and n - 16 * (frags - 1) <= 4) \
-            else frags
+        work += frags - 0.75 if n - 16 * (frags - 1) <= 4 else frags
     return work
 
 
@@ -372,7 +370,7 @@ def step_table(trace_csv, active_json):
         f = np.mean([per["k_phi_v"][u] for u in idx])
         g = np.mean([per["k_phit_w"][u] for u in idx])
         wk = np.mean([work[u] for u in idx])
-        out.append("| %d | %.0f | %.1f | %.1f | %.1f | %.1f |"
+        out.append("| %d | %.0f | %.2f | %.1f | %.1f | %.1f |"
                    % (len(idx), np.mean([cols[u] for u in idx]), wk, f, g,
                       1e3 * g / max(wk, 1e-9)))
     return "\n".join(out)
