@@ -35,6 +35,34 @@ cmtcs_status_t hip_fail(hipError_t e, const char* what) {
 
 int round16(int x) { return (x + 15) / 16 * 16; }
 
+// Task order for a tile table in which every task has the same number of tiles and each tile
+// of task t does work w[t] (the adjoint products: a tile contracts over the task's N_t rows).
+// Blocks go to the 8 XCDs round-robin and xcd_block gives each XCD a contiguous eighth of the
+// table, so the table is laid out as 8 runs of T/8 tasks with nearly equal total work: tasks
+// by decreasing work, each onto the least-loaded run that has room; each run then holds its
+// tasks longest first.  Tiles of one task stay adjacent (they share the task's W through L2).
+std::vector<int> balanced_task_order(const std::vector<int64_t>& w) {
+  const int T = (int)w.size();
+  std::vector<int> idx(T);
+  for (int t = 0; t < T; ++t) idx[t] = t;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return w[a] > w[b]; });
+  std::vector<std::vector<int>> runs(8);
+  std::vector<int64_t> load(8, 0);
+  for (int t : idx) {
+    int best = -1;
+    for (int x = 0; x < 8; ++x) {
+      const int cap = T / 8 + (x < T % 8 ? 1 : 0);
+      if ((int)runs[x].size() < cap && (best < 0 || load[x] < load[best])) best = x;
+    }
+    runs[best].push_back(t);
+    load[best] += w[t];
+  }
+  std::vector<int> order;
+  order.reserve(T);
+  for (const auto& r : runs) order.insert(order.end(), r.begin(), r.end());
+  return order;
+}
+
 // Profiled steps whose HIP events are harvested together (cmtcs_profile).
 constexpr int kCheckEvery = 8;
 
@@ -289,17 +317,21 @@ struct cmtcs_handle_s {
   cmtcs_status_t prepare(int Rp) {
     if (Rp == cur_Rp && fwd_rows == cur_fwd_rows && adj_rows == cur_adj_rows) return CMTCS_OK;
     const int fr = fwd_rows, ar = adj_rows, ng = ngroups(Rp);
-    std::vector<int64_t> woff(T + 1, 0);
+    std::vector<int64_t> woff(T + 1, 0), adj_work(T);
     std::vector<int4> ft, at;
     for (int t = 0; t < T; ++t) {
       const int nt = (int)(row_off[t + 1] - row_off[t]);
       const int np = round16(nt);
       woff[t + 1] = woff[t] + (int64_t)Rp * np;
+      // forward tiles: the same work each (a contraction over D), so equal counts per XCD
+      // balance them in task order
       for (int n0 = 0; n0 < np; n0 += tile_step(fr))
         for (int cg = 0; cg < ng; ++cg) ft.push_back(make_int4(t, n0, cg, 0));
+      adj_work[t] = np + 16;   // contraction rows, plus the epilogue as a few more
+    }
+    for (int t : balanced_task_order(adj_work))
       for (int d0 = 0; d0 < D; d0 += tile_step(ar))
         for (int cg = 0; cg < ng; ++cg) at.push_back(make_int4(t, d0, cg, 0));
-    }
     HIP_TRY(hipMemcpyAsync(w_off_d, woff.data(), sizeof(int64_t) * (T + 1),
                            hipMemcpyHostToDevice, st), "hipMemcpyAsync(w_off)");
     if (!ft.empty())
@@ -308,16 +340,18 @@ struct cmtcs_handle_s {
     HIP_TRY(hipMemcpyAsync(adj_tiles, at.data(), sizeof(int4) * at.size(),
                            hipMemcpyHostToDevice, st), "hipMemcpyAsync(adj tiles)");
     if (mixed()) {
-      std::vector<int64_t> w16(T + 1, 0);
+      std::vector<int64_t> w16(T + 1, 0), adj16_work(T);
       std::vector<int4> f16, a16;
       for (int t = 0; t < T; ++t) {
         const int np = (int)((row_off[t + 1] - row_off[t] + 31) / 32 * 32);
         w16[t + 1] = w16[t] + (int64_t)Rp * ld16(np);
         for (int n0 = 0; n0 < np; n0 += 4 * kRows16)   // one tile per block of four waves
           for (int cg = 0; cg < ng; ++cg) f16.push_back(make_int4(t, n0, cg, 0));
+        adj16_work[t] = np + 32;
+      }
+      for (int t : balanced_task_order(adj16_work))
         for (int d0 = 0; d0 < D; d0 += 4 * kRows16)
           for (int cg = 0; cg < ng; ++cg) a16.push_back(make_int4(t, d0, cg, 0));
-      }
       HIP_TRY(hipMemcpyAsync(w16_off_d, w16.data(), sizeof(int64_t) * (T + 1),
                              hipMemcpyHostToDevice, st), "hipMemcpyAsync(w16_off)");
       if (!f16.empty())
