@@ -249,6 +249,20 @@ cmtcs_status_t cmtcs_mstep(cmtcs_handle_t h, const float* mu, const float* s, co
  * Errors: CMTCS_E_INVALID for a NULL handle or array. */
 cmtcs_status_t cmtcs_mstep_pi(cmtcs_handle_t h, const double* q, double* log_pi);
 
+/* Estimate of the marginal log-likelihood of Sec. 2 from an E-step's ell (metrics, logging,
+ * convergence checks): per task
+ *   L_t = log sum_c pi_c N(y_t; 0, beta^-1 I + Phi_t diag(alpha_c)^-1 Phi_t^T)
+ *       = log sum_c exp(ell_tc / 2 + log pi_c) + const_t,
+ *   const_t = -(n_t / 2) log(2 pi) + (n_t / 2) log beta - (beta / 2) y_t . y_t,
+ * over the task's n_t real measurements (N_t; 2 N_t for partial-Fourier problems, whose complex
+ * measurements enter as [Re; Im]), computed at create; and Lhat = (1/T) sum_t L_t.  With CoFEM's
+ * ell (the Monte Carlo log-determinant of Eq. (logdet-est)) it is an estimate, exact with
+ * exact ell.  ell [T][C] and log_pi [C] double, device; L_task [T] and L_mean (one double)
+ * device outputs, each may be NULL.  A task with a non-finite ell (K_eff = 0) gives a NaN L_t
+ * and Lhat.  The mean is a fixed-order sum.  Asynchronous on the handle's stream. */
+cmtcs_status_t cmtcs_log_likelihood(cmtcs_handle_t h, const double* ell, const double* log_pi,
+                                    double* L_task, double* L_mean);
+
 /* One EM iteration of Alg. 2: cmtcs_estep from alpha_inout (no stats) followed by cmtcs_mstep
  * into alpha_inout, with the same arguments, outputs and results as those two calls.  With
  * opts->graph = 1 (MATH_F64 and MATH_F32) the device work of the whole iteration -- CG start,

@@ -70,6 +70,8 @@ def load():
     lib.cmtcs_mstep.restype = st
     lib.cmtcs_mstep_pi.argtypes = [vp, vp, vp]
     lib.cmtcs_mstep_pi.restype = st
+    lib.cmtcs_log_likelihood.argtypes = [vp, vp, vp, vp, vp]
+    lib.cmtcs_log_likelihood.restype = st
     lib.cmtcs_em_iter.argtypes = [vp, vp, vp, ctypes.POINTER(Opts), vp, vp, vp, vp, vp]
     lib.cmtcs_em_iter.restype = st
     lib.cmtcs_solve.argtypes = [vp, vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), vp, vp,

@@ -187,6 +187,19 @@ class Cmtcs:
         _lib.check(_lib.load().cmtcs_mstep_pi(self._h, _ptr(q), _ptr(log_pi)))
         return log_pi
 
+    def log_likelihood(self, ell, log_pi):
+        """Marginal log-likelihood estimate of Sec. 2 from an E-step's ell: the per-task L_t
+        [T] and their mean Lhat (a one-element tensor), float64 on the device
+        (cmtcs_log_likelihood)."""
+        self._check_stream()
+        _need(ell, torch.float64, (self.T, self.C), "ell")
+        _need(log_pi, torch.float64, (self.C,), "log_pi")
+        Lt = torch.empty(self.T, dtype=torch.float64, device=self.device)
+        L = torch.empty(1, dtype=torch.float64, device=self.device)
+        _lib.check(_lib.load().cmtcs_log_likelihood(self._h, _ptr(ell), _ptr(log_pi), _ptr(Lt),
+                                                    _ptr(L)))
+        return Lt, L
+
     def em_iter(self, alpha, log_pi, K, out=None, fixed_iters=0, tol=1e-6, max_iters=200,
                 seed=1, em_iter=0, probes=None, alpha_max=1e10, graph=False,
                 common_probes=False, precond=False):
@@ -325,7 +338,7 @@ def apply_noalloc(phi, row_off, beta, C, alpha, V, col_cluster, math="f64"):
 
 def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, seed=1,
         alpha_max=1e10, probes_fn=None, callback=None, graph=False, learn_pi=False,
-        common_probes=False, precond=False):
+        common_probes=False, precond=False, start_iter=0):
     """CoFEM (Alg. 2): n_em iterations of E-step + M-step from alpha0, then a_t = argmax_c q_tc
     (lowest c on ties) and mu_{t, a_t} from the last E-step.  With ``graph`` each iteration is
     one replay of the recorded EM iteration (cmtcs_em_iter), on output buffers reused from one
@@ -333,11 +346,16 @@ def fit(model, alpha0, log_pi, K, n_em, fixed_iters=0, tol=1e-6, max_iters=200, 
     (a copy) and the outputs before the next iteration overwrites them.  With ``learn_pi`` each
     M-step also updates the cluster weights (cmtcs_mstep_pi) on a copy of ``log_pi``, returned
     as "log_pi".  ``common_probes``: every cluster of a task uses the same generated probes.
-    ``precond``: Jacobi-preconditioned solves (cmtcs_opts_t.precond)."""
+    ``precond``: Jacobi-preconditioned solves (cmtcs_opts_t.precond).
+
+    Checkpoint and resume: the probes of EM iteration ``it`` depend only on (seed, it), so
+    iterations start_iter .. start_iter + n_em - 1 from a saved alpha (and log_pi with
+    ``learn_pi``) continue a run exactly; a run of n_em iterations equals one of k followed by
+    one of n_em - k with start_iter = k, bit for bit."""
     alpha = alpha0.clone()
     log_pi = log_pi.clone() if learn_pi else log_pi
     out = None
-    for it in range(n_em):
+    for it in range(start_iter, start_iter + n_em):
         pr = None if probes_fn is None else probes_fn(it)
         if graph:
             before = alpha.clone() if callback is not None else None

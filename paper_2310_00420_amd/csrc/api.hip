@@ -95,6 +95,7 @@ struct cmtcs_handle_s {
   std::vector<void*> allocs;
   int64_t* row_off_d = nullptr;
   int64_t* w_off_d = nullptr;
+  double* lconst = nullptr;   // [T] constant of each task's marginal log-likelihood
   void *X = nullptr, *Rv = nullptr, *Dv = nullptr, *AD = nullptr, *W = nullptr, *b = nullptr;
   double *rr = nullptr, *thr = nullptr, *gam = nullptr, *xi = nullptr;
   uint8_t* state = nullptr;
@@ -1051,6 +1052,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   A(&h->ok, P);
   A(&h->keff, sizeof(int) * T * C);
   A(&h->slog, sizeof(double) * C);
+  A(&h->lconst, sizeof(double) * std::max<size_t>(1, T));
   if (h->math == CMTCS_MATH_MIXED) {
     size_t np32_sum = 0, f16_max = 0;
     for (size_t t = 0; t < T; ++t) {
@@ -1084,6 +1086,9 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
     else if (f64) e = launch_rhs<double>(g, h->phi, h->y, h->beta, (double*)h->b, h->st);
     else e = launch_rhs<float>(g, h->phi, h->y, h->beta, (float*)h->b, h->st);
     if (e == hipSuccess && !fourier) e = launch_colnorm(g, h->phi, h->beta, h->mbase, h->st);
+    if (e == hipSuccess)
+      e = launch_log_norm_const(T, h->y, h->row_off_d, fourier ? 2 : 1, h->beta, h->lconst,
+                                h->st);
   }
   if (e == hipSuccess && fourier)
     e = hipMemcpyAsync(&bad, h->bad_freq, sizeof(int), hipMemcpyDeviceToHost, h->st);
@@ -1161,6 +1166,16 @@ cmtcs_status_t cmtcs_mstep_pi(cmtcs_handle_t h, const double* q, double* log_pi)
   if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
   if (!q || !log_pi) return fail(CMTCS_E_INVALID, "a required array argument is NULL");
   HIP_TRY(launch_update_pi(h->T, h->C, q, log_pi, h->st), "launch(mstep_pi)");
+  return CMTCS_OK;
+}
+
+cmtcs_status_t cmtcs_log_likelihood(cmtcs_handle_t h, const double* ell, const double* log_pi,
+                                    double* L_task, double* L_mean) {
+  if (h == nullptr) return fail(CMTCS_E_INVALID, "handle is NULL");
+  if (!ell || !log_pi) return fail(CMTCS_E_INVALID, "a required array argument is NULL");
+  if (!L_task && !L_mean) return CMTCS_OK;
+  HIP_TRY(launch_log_likelihood(h->T, h->C, ell, log_pi, h->lconst, L_task, L_mean, h->st),
+          "launch(log_likelihood)");
   return CMTCS_OK;
 }
 

@@ -369,5 +369,11 @@ hipError_t launch_resp(const Geometry& g, const CgState& s, int K, const VT* b,
 hipError_t launch_mstep(int T, int C, int D, const float* mu, const float* sdiag,
                         const double* q, double alpha_max, float* alpha, hipStream_t st);
 hipError_t launch_update_pi(int T, int C, const double* q, double* log_pi, hipStream_t st);
+// const_t of the marginal likelihood per task (per_row real values per stored measurement row)
+hipError_t launch_log_norm_const(int T, const float* y, const int64_t* row_off, int per_row,
+                                 double beta, double* lconst, hipStream_t st);
+// L_t and their mean from ell [T][C] and log_pi [C]; Lt and L may be null
+hipError_t launch_log_likelihood(int T, int C, const double* ell, const double* log_pi,
+                                 const double* lconst, double* Lt, double* L, hipStream_t st);
 
 }  // namespace cmtcs

@@ -20,6 +20,66 @@ __global__ __launch_bounds__(256) void k_rhs(const float* __restrict__ phi,
   b[(int64_t)t * D + d] = (VT)(beta * acc);
 }
 
+// const_t = -(n_t / 2) log(2 pi) + (n_t / 2) log beta - (beta / 2) y_t . y_t over the task's n_t
+// real measurements (per_row = 1 per stored row, 2 for (re, im) pairs), one block per task:
+// ell_tc / 2 + const_t is then log N(y_t; 0, beta^-1 I + Phi_t diag(alpha_c)^-1 Phi_t^T)
+// (Sec. 2).
+__global__ __launch_bounds__(256) void k_log_norm_const(const float* __restrict__ y,
+                                                        const int64_t* __restrict__ row_off,
+                                                        int per_row, double beta,
+                                                        double* __restrict__ lconst) {
+  __shared__ double sh[4];
+  const int t = blockIdx.x;
+  const int64_t i0 = row_off[t] * per_row, i1 = row_off[t + 1] * per_row;
+  double acc = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) acc += (double)y[i] * (double)y[i];
+  const double yy = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0) {
+    const double n = (double)(i1 - i0);
+    lconst[t] = -0.5 * n * log(2.0 * 3.14159265358979323846) + 0.5 * n * log(beta) - 0.5 * beta * yy;
+  }
+}
+
+// L_t = log sum_c exp(ell_tc / 2 + log pi_c) + const_t (max-shifted) and their mean Lhat, one
+// block; the mean is a fixed-order sum.
+__global__ __launch_bounds__(256) void k_log_likelihood(const double* __restrict__ ell,
+                                                        const double* __restrict__ log_pi,
+                                                        const double* __restrict__ lconst,
+                                                        int T, int C, double* __restrict__ Lt,
+                                                        double* __restrict__ L) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int t = threadIdx.x; t < T; t += 256) {
+    double m = -INFINITY;
+    for (int c = 0; c < C; ++c) m = fmax(m, 0.5 * ell[(int64_t)t * C + c] + log_pi[c]);
+    double sum = 0.0;
+    for (int c = 0; c < C; ++c) sum += exp(0.5 * ell[(int64_t)t * C + c] + log_pi[c] - m);
+    // a non-finite ell (a failed task) propagates instead of being skipped by fmax
+    bool bad = false;
+    for (int c = 0; c < C; ++c) bad = bad || !isfinite(ell[(int64_t)t * C + c]);
+    const double v = bad ? NAN : m + log(sum) + lconst[t];
+    if (Lt != nullptr) Lt[t] = v;
+    acc += v;
+  }
+  const double tot = block_sum<256>(acc, sh);
+  if (threadIdx.x == 0 && L != nullptr) *L = tot / (double)T;
+}
+
+hipError_t launch_log_norm_const(int T, const float* y, const int64_t* row_off, int per_row,
+                                 double beta, double* lconst, hipStream_t st) {
+  if (T == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_log_norm_const, dim3(T), dim3(256), 0, st, y, row_off, per_row, beta,
+                     lconst);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_likelihood(int T, int C, const double* ell, const double* log_pi,
+                                 const double* lconst, double* Lt, double* L, hipStream_t st) {
+  hipLaunchKernelGGL(k_log_likelihood, dim3(1), dim3(256), 0, st, ell, log_pi, lconst, T, C, Lt,
+                     L);
+  return hipGetLastError();
+}
+
 // sum_d log alpha_cd, one block per cluster.
 __global__ __launch_bounds__(256) void k_sum_log_alpha(const float* __restrict__ alpha,
                                                        double* __restrict__ slog, int D) {
