@@ -1,14 +1,15 @@
 """ctypes declarations of the C ABI in ``include/cmtcs.h`` and the loader of ``libcmtcs.so``.
 
 The shared library is built in-tree by ``paper_2310_00420_amd.build``.  There is no fallback:
-if it is missing or fails to load, ``load()`` raises.
+if it is missing or fails to load, ``load()`` raises.  ``CMTCS_LIB`` names another build of the
+same library to load instead (the host-sanitizer build of the tests).
 """
 
 import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcmtcs.so")
+LIB_PATH = os.environ.get("CMTCS_LIB") or os.path.join(HERE, "libcmtcs.so")
 
 CMTCS_OK, CMTCS_E_INVALID, CMTCS_E_HIP, CMTCS_E_NOMEM, CMTCS_E_UNSUPPORTED = range(5)
 CMTCS_F32, CMTCS_BF16, CMTCS_F16 = range(3)

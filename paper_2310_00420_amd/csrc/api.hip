@@ -35,6 +35,17 @@ cmtcs_status_t hip_fail(hipError_t e, const char* what) {
 
 int round16(int x) { return (x + 15) / 16 * 16; }
 
+// An enum field of a caller's struct read as its 32-bit integer.  A caller across the C ABI can
+// store any value there, and loading one outside the enumerators as the enum type is undefined
+// in C++, so the fields are copied out as integers and checked before use.
+template <typename E>
+int32_t enum_bits(const E& e) {
+  static_assert(sizeof(E) == sizeof(int32_t), "C enums are int-sized here");
+  int32_t v;
+  std::memcpy(&v, &e, sizeof v);
+  return v;
+}
+
 // Task order for a tile table in which every task has the same number of tiles and each tile
 // of task t does work w[t] (the adjoint products: a tile contracts over the task's N_t rows).
 // Blocks go to the 8 XCDs round-robin and xcd_block gives each XCD a contiguous eighth of the
@@ -898,6 +909,8 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   if (out == nullptr) return fail(CMTCS_E_INVALID, "out is NULL");
   *out = nullptr;
   if (p == nullptr) return fail(CMTCS_E_INVALID, "problem is NULL");
+  const int32_t op = enum_bits(p->op), math = enum_bits(p->math);
+  const int32_t phi_dtype = enum_bits(p->phi_dtype);
   if (p->T < 1 || p->C < 1) return fail(CMTCS_E_INVALID, "T and C must be >= 1");
   if (p->D < 16 || p->D % 16 != 0 || p->D > 16384)
     return fail(CMTCS_E_INVALID, "D must be a positive multiple of 16, at most 16384");
@@ -907,13 +920,13 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
     if (p->row_off[t + 1] < p->row_off[t])
       return fail(CMTCS_E_INVALID, "row_off must be non-decreasing");
   const int64_t rows = p->row_off[p->T];
-  if (p->op != CMTCS_OP_DENSE && p->op != CMTCS_OP_PARTIAL_FOURIER)
+  if (op != CMTCS_OP_DENSE && op != CMTCS_OP_PARTIAL_FOURIER)
     return fail(CMTCS_E_INVALID, "unknown sensing operator");
-  const bool fourier = p->op == CMTCS_OP_PARTIAL_FOURIER;
+  const bool fourier = op == CMTCS_OP_PARTIAL_FOURIER;
   if (fourier) {
     if (rows > 0 && (p->freq == nullptr || p->y == nullptr))
       return fail(CMTCS_E_INVALID, "freq and y must be non-NULL");
-    if (p->math != CMTCS_MATH_F64)
+    if (math != CMTCS_MATH_F64)
       return fail(CMTCS_E_UNSUPPORTED, "partial-Fourier problems run in MATH_F64 only");
     if (p->D < 64 || p->D > 4096 || (p->D & (p->D - 1)) != 0)
       return fail(CMTCS_E_UNSUPPORTED, "partial-Fourier problems need D a power of two, 64..4096");
@@ -927,15 +940,15 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   if (p->max_K < 0) return fail(CMTCS_E_INVALID, "max_K must be >= 0");
   if ((int64_t)p->C * (p->max_K + 1) > p->max_rhs && p->max_K > 0)
     return fail(CMTCS_E_INVALID, "max_rhs must be >= C*(max_K+1)");
-  if (p->math != CMTCS_MATH_F64 && p->math != CMTCS_MATH_F32 && p->math != CMTCS_MATH_MIXED)
+  if (math != CMTCS_MATH_F64 && math != CMTCS_MATH_F32 && math != CMTCS_MATH_MIXED)
     return fail(CMTCS_E_INVALID, "unknown math mode");
-  if (p->phi_resid != nullptr && (p->math != CMTCS_MATH_MIXED || fourier))
+  if (p->phi_resid != nullptr && (math != CMTCS_MATH_MIXED || fourier))
     return fail(CMTCS_E_INVALID, "phi_resid is for MATH_MIXED dense problems only");
-  if (p->math == CMTCS_MATH_MIXED) {
-    if (p->phi_dtype != CMTCS_BF16 && p->phi_dtype != CMTCS_F16)
+  if (math == CMTCS_MATH_MIXED) {
+    if (phi_dtype != CMTCS_BF16 && phi_dtype != CMTCS_F16)
       return fail(CMTCS_E_INVALID, "MATH_MIXED needs phi_dtype BF16 or F16");
     if (p->D % 32 != 0) return fail(CMTCS_E_INVALID, "MATH_MIXED needs D a multiple of 32");
-  } else if (p->phi_dtype != CMTCS_F32 && !fourier) {
+  } else if (phi_dtype != CMTCS_F32 && !fourier) {
     return fail(CMTCS_E_INVALID, "MATH_F64 and MATH_F32 take phi_dtype F32");
   }
   for (int t = 0; t < p->T; ++t)
@@ -957,12 +970,12 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
 
   cmtcs_handle_s* h = new (std::nothrow) cmtcs_handle_s();
   if (h == nullptr) return fail(CMTCS_E_NOMEM, "host allocation failed");
-  h->T = p->T; h->C = p->C; h->D = p->D; h->beta = p->beta; h->math = p->math;
+  h->T = p->T; h->C = p->C; h->D = p->D; h->beta = p->beta; h->math = (cmtcs_math_t)math;
   h->max_rhs = p->max_rhs; h->max_iters = p->max_iters; h->max_K = p->max_K;
   h->Rp_max = col_slots(p->max_rhs);
-  h->vbytes = p->math == CMTCS_MATH_F64 ? 8 : 4;
+  h->vbytes = math == CMTCS_MATH_F64 ? 8 : 4;
   h->row_off.assign(p->row_off, p->row_off + p->T + 1);
-  h->phi_dtype = p->phi_dtype;
+  h->phi_dtype = (cmtcs_dtype_t)phi_dtype;
   h->phi = (const float*)p->phi;
   h->phi_res = p->phi_resid != nullptr ? p->phi_resid : (const float*)p->phi;
   h->y = p->y;
@@ -1281,14 +1294,16 @@ cmtcs_status_t cmtcs_apply_noalloc(const cmtcs_problem_t* p, const float* alpha,
                                    int32_t R_per_task, const int32_t* col_cluster, const void* V,
                                    void* AV, void* stream) {
   if (p == nullptr) return fail(CMTCS_E_INVALID, "problem is NULL");
+  const int32_t op = enum_bits(p->op), math = enum_bits(p->math);
   if (p->T < 1 || p->C < 1) return fail(CMTCS_E_INVALID, "T and C must be >= 1");
   if (p->D < 16 || p->D % 16 != 0 || p->D > 16384)
     return fail(CMTCS_E_INVALID, "D must be a positive multiple of 16, at most 16384");
-  if (p->op != CMTCS_OP_DENSE)
+  if (op != CMTCS_OP_DENSE)
     return fail(CMTCS_E_UNSUPPORTED, "cmtcs_apply_noalloc takes dense problems only");
-  if (p->math != CMTCS_MATH_F64 && p->math != CMTCS_MATH_F32)
+  if (math != CMTCS_MATH_F64 && math != CMTCS_MATH_F32)
     return fail(CMTCS_E_UNSUPPORTED, "cmtcs_apply_noalloc runs MATH_F64 or MATH_F32");
-  if (p->phi_dtype != CMTCS_F32) return fail(CMTCS_E_INVALID, "phi_dtype must be F32");
+  if (enum_bits(p->phi_dtype) != CMTCS_F32)
+    return fail(CMTCS_E_INVALID, "phi_dtype must be F32");
   if (!(p->beta > 0.0)) return fail(CMTCS_E_INVALID, "beta must be > 0");
   if (p->row_off == nullptr || p->row_off[0] != 0)
     return fail(CMTCS_E_INVALID, "row_off must be non-NULL with row_off[0] = 0");
@@ -1314,7 +1329,7 @@ cmtcs_status_t cmtcs_apply_noalloc(const cmtcs_problem_t* p, const float* alpha,
     }
   }
   hipStream_t st = (hipStream_t)stream;
-  if (p->math == CMTCS_MATH_F64)
+  if (enum_bits(p->math) == CMTCS_MATH_F64)
     return apply_noalloc<double>(p, alpha, R_per_task, col_cluster, V, AV, st);
   return apply_noalloc<float>(p, alpha, R_per_task, col_cluster, V, AV, st);
 }

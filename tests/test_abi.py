@@ -64,6 +64,9 @@ def _problem(**over):
     (dict(math=_lib.CMTCS_MATH_MIXED, phi_dtype=_lib.CMTCS_BF16, D=48), "multiple of 32"),
     (dict(phi_dtype=_lib.CMTCS_BF16), "phi_dtype F32"),
     (dict(phi_resid=1), "phi_resid"),
+    (dict(math=9), "unknown math mode"),
+    (dict(phi_dtype=9), "phi_dtype F32"),
+    (dict(math=_lib.CMTCS_MATH_MIXED, phi_dtype=-1), "BF16 or F16"),
     (dict(math=_lib.CMTCS_MATH_F32, phi_resid=1), "phi_resid"),
     (dict(D=16384, row_off=np.array([0, 4, 65540], np.int64)), "Phi block"),
     (dict(D=16384, max_rhs=40000), "column slots"),
@@ -101,6 +104,13 @@ def test_apply_noalloc_rejects_on_the_host():
     p, keep = _problem(op=_lib.CMTCS_OP_PARTIAL_FOURIER, D=64)
     assert lib.cmtcs_apply_noalloc(ctypes.byref(p), 1, 1, cc, 1, 1, None) == \
         _lib.CMTCS_E_UNSUPPORTED
+    for over in (dict(op=5), dict(math=7), dict(math=_lib.CMTCS_MATH_MIXED)):
+        p, keep = _problem(**over)
+        assert lib.cmtcs_apply_noalloc(ctypes.byref(p), 1, 1, cc, 1, 1, None) == \
+            _lib.CMTCS_E_UNSUPPORTED
+    p, keep = _problem(phi_dtype=4)
+    assert lib.cmtcs_apply_noalloc(ctypes.byref(p), 1, 1, cc, 1, 1, None) == \
+        _lib.CMTCS_E_INVALID
     # 720 column slots x 16384 x 8 bytes of padded right-hand sides alone exceed 64 MiB
     R = 600
     big = (ctypes.c_int32 * R)()
