@@ -271,6 +271,18 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
 // loads it once per chunk into an LDS double buffer (through a few staging registers per
 // thread) instead of each wave loading it into its own registers.  The Phi ring and the
 // accumulators are per wave as in k_phi_v.
+//
+// Layout of a staged chunk in LDS (16 elements along the contraction x up to 144 columns).  The
+// matrix-core operand of lane (i16, g4) is column i16 of a fragment at elements 4 g4 .. 4 g4 + 3,
+// read 16 bytes at a time.  Measured on gfx950 (bank-conflict counters on probe kernels): a
+// 16-byte LDS read is conflict-free when each 16-lane quarter of the wave reads one aligned
+// 256-byte block, and a 16-byte write when the 8 lanes of each eighth fall in distinct banks of
+// a 128-byte row.  FP64 therefore stores a fragment's chunk piece-major: 16-byte piece q (two
+// elements) of column c at 16 q + (c ^ q) pieces into the fragment's 2 KB, so that a quarter
+// wave reads piece q of all 16 columns (one 256-byte row, permuted) and the staging stores,
+// where 8 lanes write pieces 0..7 of one column, land in 8 different banks.  (Columns as padded
+// rows of 18 elements cost 4 conflict cycles on every operand read.)  FP32, whose operand reads
+// are 8 bytes, keeps the padded rows.
 template <typename VT>
 struct LdsChunk {
   static constexpr int kPer16 = 16 / (int)sizeof(VT);            // elements per 16-byte piece
@@ -278,7 +290,18 @@ struct LdsChunk {
   static constexpr int kLd = 16 + kPer16;                        // padded LDS row (elements)
   static constexpr int kMaxPieces = 16 * kColGroup * kPieces;
   static constexpr int kPerThread = (kMaxPieces + 64 * kOpWaves - 1) / (64 * kOpWaves);
+  static constexpr bool kSwizzled = sizeof(VT) == 8;
+  static constexpr int kBufElems = kSwizzled ? kColGroup * 16 * 16 : 16 * kColGroup * kLd;
   typedef typename VecOf<VT, kPer16>::type piece_t;
+  // element offset, within one buffer, of element e (e even for FP64) of column col
+  __device__ static inline int off(int col, int e) {
+    if constexpr (kSwizzled) {
+      const int q = e >> 1;
+      return ((((col >> 4) << 7) + (q << 4) + ((col & 15) ^ q)) << 1) + (e & 1);
+    } else {
+      return col * kLd + e;
+    }
+  }
 };
 
 // The 16-row FP64 LDS-staged tile fits two waves per SIMD without spilling once the
@@ -300,7 +323,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   typedef LdsChunk<VT> L;
   typedef typename L::piece_t piece_t;
   constexpr int kRingA = ring_depth<VT>();
-  __shared__ VT lds[2][16 * kColGroup][L::kLd];
+  __shared__ VT lds[2 * L::kBufElems];
   __shared__ int cmap[16 * kColGroup];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
@@ -343,8 +366,8 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     const int col = p / L::kPieces, q = p % L::kPieces;
     const int slot = state != nullptr ? cmap[col] : cf0 * 16 + col;
     soff_v[i] = (uint32_t)((slot * D + q * L::kPer16) * sizeof(VT));
-    sdst[0][i] = &lds[0][col][q * L::kPer16];
-    sdst[1][i] = &lds[1][col][q * L::kPer16];
+    sdst[0][i] = &lds[L::off(col, q * L::kPer16)];
+    sdst[1][i] = &lds[L::kBufElems + L::off(col, q * L::kPer16)];
   }
 
   acc_t acc[RF][kColGroup];
@@ -388,8 +411,9 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (cf < NF)
-          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == NF - 1) ? (i16 & 3) : i16)]
-                                        [4 * g4 + 2 * h];
+          b[cf] = *(const vt2*)&lds[buf * L::kBufElems +
+                                    L::off(cf * 16 + ((kNw && cf == NF - 1) ? (i16 & 3) : i16),
+                                           4 * g4 + 2 * h)];
 #pragma unroll
       for (int ss = 0; ss < 2; ++ss) {
         const int s = 2 * h + ss;
@@ -728,7 +752,7 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   // a shallower Phi ring than k_phit_w's: with the block sharing the W chunk, four entries keep
   // two waves per SIMD without spilling (six do not)
   constexpr int kRingA = 4;
-  __shared__ VT lds[2][16 * kColGroup][L::kLd];
+  __shared__ VT lds[2 * L::kBufElems];
   __shared__ int cmap[16 * kColGroup];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i16 = lane & 15, g4 = lane >> 4;
@@ -782,13 +806,13 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   const rsrc_t rw = make_rsrc(W + w_off[t], (uint32_t)((int64_t)Rp * np * sizeof(VT)));
   uint32_t soff_w[L::kPerThread];
   VT* sdst[L::kPerThread];   // in buffer 0; buffer 1 lies kBuf elements further
-  constexpr int kBuf = 16 * kColGroup * L::kLd;
+  constexpr int kBuf = L::kBufElems;
 #pragma unroll
   for (int i = 0; i < L::kPerThread; ++i) {
     const int p = min((int)threadIdx.x + i * 64 * kOpWaves, npieces - 1);
     const int col = p / L::kPieces, q = p % L::kPieces;
     soff_w[i] = (uint32_t)(((cf0 * 16 + col) * np + q * L::kPer16) * sizeof(VT));
-    sdst[i] = &lds[0][col][q * L::kPer16];
+    sdst[i] = &lds[L::off(col, q * L::kPer16)];
   }
 
   frf a[kRingA][KS];
@@ -823,8 +847,9 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
         if (cf < NF)
-          b[cf] = *(const vt2*)&lds[buf][cf * 16 + ((kNw && cf == NF - 1) ? (i16 & 3) : i16)]
-                                        [4 * g4 + 2 * h];
+          b[cf] = *(const vt2*)&lds[buf * L::kBufElems +
+                                    L::off(cf * 16 + ((kNw && cf == NF - 1) ? (i16 & 3) : i16),
+                                           4 * g4 + 2 * h)];
 #pragma unroll
       for (int ss = 0; ss < 2; ++ss) {
         const int s = 2 * h + ss;
