@@ -187,43 +187,48 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
 #pragma unroll
     for (int rf = 0; rf < RF; ++rf) x[rf] = buf_load<f4>(rphi, aoff[rf], soff);
   };
-  auto load_b = [&](vt4 (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
+  // nf: the fragment count when it is a compile-time 9 or 8 (the common counts with
+  // compaction), or 0 for any other count, then guarded at run time
+  auto load_b = [&](vt4 (&x)[kColGroup], int c, auto nf) __attribute__((always_inline)) {
+    constexpr int NF = decltype(nf)::value;
     const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 16 * (int)sizeof(VT));
 #pragma unroll
-    for (int cf = 0; cf < kColGroup; ++cf) x[cf] = buf_load<vt4>(rv, boff[cf], soff);
+    for (int cf = 0; cf < kColGroup; ++cf)
+      if (NF == 0 || cf < NF) x[cf] = buf_load<vt4>(rv, boff[cf], soff);
   };
   // first: the chunk that starts the accumulation (its first k-step takes a zero accumulator)
-  auto mma = [&](const f4 (&x)[RF], const vt4 (&y)[kColGroup], auto full, auto first)
+  auto mma = [&](const f4 (&x)[RF], const vt4 (&y)[kColGroup], auto nf, auto first)
       __attribute__((always_inline)) {
+    constexpr int NF = decltype(nf)::value;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
-        if (decltype(full)::value || cf < ncf)
+        if (NF == 0 ? cf < ncf : cf < NF)
 #pragma unroll
           for (int rf = 0; rf < RF; ++rf) {
             const acc_t cin = (decltype(first)::value && s == 0) ? acc_t{0, 0, 0, 0} : acc[rf][cf];
             acc[rf][cf] = Mfma<VT>::mma((VT)x[rf][s], y[cf][s], cin);
           }
   };
-  auto slot = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+  auto slot = [&](int c, auto ic, auto nf, auto first) __attribute__((always_inline)) {
     constexpr int i = decltype(ic)::value;
-    load_b(b[(i + 1) & 1], c + i + 1, full);
+    load_b(b[(i + 1) & 1], c + i + 1, nf);
     load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
     // the scheduling barriers keep the compiler from moving loads across the MFMAs they
     // should overlap, or conversions up to their loads
     __builtin_amdgcn_sched_barrier(0);
-    mma(a[i], b[i & 1], full, first);
+    mma(a[i], b[i & 1], nf, first);
     __builtin_amdgcn_sched_barrier(0);
   };
-  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+  auto ring = [&](int c, auto nf, auto first) __attribute__((always_inline)) {
     static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
-      slot(c, ic, full,
+      slot(c, ic, nf,
            std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
     });
   };
-  auto run = [&](auto full) __attribute__((always_inline)) {
-    load_b(b[0], 0, full);
+  auto run = [&](auto nf) __attribute__((always_inline)) {
+    load_b(b[0], 0, nf);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
     int c = 0;
@@ -231,8 +236,8 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
       // rounds of kRingA chunks; the first is peeled so that the accumulators start in the
       // matrix-core result registers (a zero input to the first k-step) instead of as zeros
       // carried into the loop, which made the compiler copy them across every iteration
-      ring(0, full, std::true_type{});
-      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
+      ring(0, nf, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, nf, std::false_type{});
     } else {
       zero_acc();
     }
@@ -240,12 +245,13 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
-      if (i > 0) load_b(b[i & 1], c + i, full);
-      mma(a[i], b[i & 1], full, std::false_type{});
+      if (i > 0) load_b(b[i & 1], c + i, nf);
+      mma(a[i], b[i & 1], nf, std::false_type{});
     }
   };
-  if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
-  else run(std::false_type{});
+  if (ncf == kColGroup) run(std::integral_constant<int, kColGroup>{});   // no guards
+  else if (ncf == kColGroup - 1) run(std::integral_constant<int, kColGroup - 1>{});
+  else run(std::integral_constant<int, 0>{});
 
   VT* Wt = W + w_off[t];
 #pragma unroll
@@ -322,7 +328,8 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
   typedef typename VecOf<VT, 4>::type vt4;
   typedef LdsChunk<VT> L;
   typedef typename L::piece_t piece_t;
-  constexpr int kRingA = ring_depth<VT>();
+  // four chunks in the Phi ring (three ahead): with the per-count instantiations six spilled
+  constexpr int kRingA = 4;
   __shared__ VT lds[2 * L::kBufElems];
   __shared__ int cmap[16 * kColGroup];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -661,22 +668,26 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
 #pragma unroll
     for (int s = 0; s < KS; ++s) x[s] = buf_load<frf>(ra, aoff[s], 0);
   };
-  auto load_b = [&](vtk (&x)[kColGroup], int c, auto full) __attribute__((always_inline)) {
+  // nf: the fragment count when it is a compile-time 9 or 8, else 0 (guarded at run time)
+  auto load_b = [&](vtk (&x)[kColGroup], int c, auto nf) __attribute__((always_inline)) {
+    constexpr int NF = decltype(nf)::value;
     const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * KC * (int)sizeof(VT));
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf) {
-      const int f = decltype(full)::value ? cf : min(cf, ncf - 1);
+      if (NF != 0 && cf >= NF) continue;
+      const int f = NF != 0 ? cf : min(cf, ncf - 1);
       x[cf] = buf_load<vtk>(rw, boff0 + (uint32_t)f * bstep, soff);
     }
   };
   // first: the chunk that starts the accumulation (its first k-step takes a zero accumulator)
-  auto mma = [&](const frf (&x)[KS], const vtk (&y)[kColGroup], auto full, auto first)
+  auto mma = [&](const frf (&x)[KS], const vtk (&y)[kColGroup], auto nf, auto first)
       __attribute__((always_inline)) {
+    constexpr int NF = decltype(nf)::value;
 #pragma unroll
     for (int s = 0; s < KS; ++s)
 #pragma unroll
       for (int cf = 0; cf < kColGroup; ++cf)
-        if (decltype(full)::value || cf < ncf)
+        if (NF == 0 ? cf < ncf : cf < NF)
 #pragma unroll
           for (int f = 0; f < RF; ++f) {
             float av;
@@ -686,45 +697,46 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
           }
   };
   // one slot of the pipeline: chunk c + i from ring entry i, loads for the chunks ahead
-  auto slot = [&](int c, auto ic, auto full, auto first) __attribute__((always_inline)) {
+  auto slot = [&](int c, auto ic, auto nf, auto first) __attribute__((always_inline)) {
     constexpr int i = decltype(ic)::value;
-    load_b(b[(i + 1) & 1], c + i + 1, full);
+    load_b(b[(i + 1) & 1], c + i + 1, nf);
     load_a(a[(i + kRingA - 1) % kRingA], c + i + kRingA - 1);
     __builtin_amdgcn_sched_barrier(0);
-    mma(a[i], b[i & 1], full, first);
+    mma(a[i], b[i & 1], nf, first);
     __builtin_amdgcn_sched_barrier(0);
   };
-  auto ring = [&](int c, auto full, auto first) __attribute__((always_inline)) {
+  auto ring = [&](int c, auto nf, auto first) __attribute__((always_inline)) {
     static_for<kRingA>([&](auto ic) __attribute__((always_inline)) {
-      slot(c, ic, full,
+      slot(c, ic, nf,
            std::integral_constant<bool, decltype(first)::value && decltype(ic)::value == 0>{});
     });
   };
-  auto run = [&](auto full) __attribute__((always_inline)) {
+  auto run = [&](auto nf) __attribute__((always_inline)) {
     if (nch < kRingA) {   // small task: a zero start and the tail alone
       zero_acc();
       if (nch == 0) return;   // empty task: the product is zero
     }
-    load_b(b[0], 0, full);
+    load_b(b[0], 0, nf);
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) load_a(a[i], i);
     int c = 0;
     if (nch >= kRingA) {
       // the first round is peeled so that the accumulators start in the matrix-core result
       // registers (a zero input to the first k-step) rather than as zeros carried into the loop
-      ring(0, full, std::true_type{});
-      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, full, std::false_type{});
+      ring(0, nf, std::true_type{});
+      for (c = kRingA; c + kRingA <= nch; c += kRingA) ring(c, nf, std::false_type{});
     }
     // fewer than kRingA chunks left: chunk c+i is in a[i], chunk c's right-hand side in b[0]
 #pragma unroll
     for (int i = 0; i + 1 < kRingA; ++i) {
       if (c + i >= nch) break;
-      if (i > 0) load_b(b[i & 1], c + i, full);
-      mma(a[i], b[i & 1], full, std::false_type{});
+      if (i > 0) load_b(b[i & 1], c + i, nf);
+      mma(a[i], b[i & 1], nf, std::false_type{});
     }
   };
-  if (ncf == kColGroup) run(std::true_type{});   // all column fragments present: no guards
-  else run(std::false_type{});
+  if (ncf == kColGroup) run(std::integral_constant<int, kColGroup>{});   // no guards
+  else if (ncf == kColGroup - 1) run(std::integral_constant<int, kColGroup - 1>{});
+  else run(std::integral_constant<int, 0>{});
 
   phit_w_store<VT, RF>(acc, t, d0, cf0, ncf, i16, g4, D, Rp, AV, V, alpha, colc, beta, map);
 }
