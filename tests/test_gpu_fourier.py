@@ -38,7 +38,7 @@ def _ragged(D, Ns, T=None, C=2, K=4, **kw):
                                            K=K, sigma=0.05, **kw))
 
 
-@pytest.mark.parametrize("D", [64, 128, 512, 4096])
+@pytest.mark.parametrize("D", [64, 128, 512, 1024, 2048, 4096])
 def test_operator_matches_oracle(D):
     """A V = beta Re(F^H Omega^T Omega F V) + alpha (.) V on ragged masks (empty, partial, every
     frequency, a quarter), odd and even log2 D, an odd column count (one column paired with
