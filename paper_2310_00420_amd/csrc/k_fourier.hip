@@ -66,10 +66,17 @@ __device__ inline void dft4(d2 x0, d2 x1, d2 x2, d2 x3, d2& u0, d2& u1, d2& u2, 
 // w = exp(-2 pi i / (R Ns))), transforms the R values and writes them to
 // dst[(j / Ns) R Ns + k + r Ns].  Ns is the length of the sub-transforms already done.  Every
 // thread of the block must call it; one barrier at the end publishes dst.
-template <int R, bool INV, int BS, int N>
-__device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns) {
+// With one butterfly per thread (N = R BS), butterfly j = threadIdx.x reads points j + r BS and,
+// when Ns = N / R, writes points j + r BS: the thread's own points in the natural order.  Then
+// IN_REGS takes the inputs from vin[r] instead of src, and SCALE multiplies output r by
+// hscale times the r-th byte of hc (the multiplier count of point j + r BS) before it is stored.
+template <int R, bool INV, int BS, int N, bool IN_REGS = false, bool SCALE = false>
+__device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns,
+                                 const d2* vin = nullptr, const uint32_t* hc = nullptr,
+                                 double hscale = 0.0) {
   constexpr int NBF = N / R;                       // butterflies
   constexpr int PER = NBF >= BS ? NBF / BS : 1;    // per thread
+  static_assert(!(IN_REGS || SCALE) || NBF == BS, "own points need one butterfly per thread");
   // one butterfly at a time: their registers would otherwise crowd out the columns' state
 #pragma unroll 1
   for (int i = 0; i < PER; ++i) {
@@ -77,8 +84,10 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns) {
     if (j < NBF) {
       d2 v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        v[r] = src[NBF % 16 == 0 ? pad(j) + r * (NBF + NBF / 16) : pad(j + r * NBF)];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (IN_REGS) v[r] = vin[r];
+        else v[r] = src[NBF % 16 == 0 ? pad(j) + r * (NBF + NBF / 16) : pad(j + r * NBF)];
+      }
       const int k = j & (Ns - 1);
       // w^k from the stage's table (conjugated for the inverse); its higher powers by FP64
       // complex products instead of more LDS reads
@@ -122,7 +131,10 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns) {
       }
       const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[pad(base + r * Ns)] = u[r];
+      for (int r = 0; r < R; ++r) {
+        if constexpr (SCALE) u[r] = u[r] * (hscale * (double)((hc[r / 4] >> (8 * (r % 4))) & 255u));
+        dst[pad(base + r * Ns)] = u[r];
+      }
     }
   }
   __syncthreads();
@@ -248,19 +260,44 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
   // first write goes to bufA: every thread has finished reading the previous step's result by
   // then (two block reductions lie in between).
   const d2* res = bufA;
+  // With radix 8 throughout and one butterfly per thread (D = 4096), the forward transform's
+  // first stage reads exactly the thread's own points and its last stage writes them: the first
+  // stage takes d from registers (no store of d, no barrier, no load) and the last applies the
+  // multiplier before its store (no separate pass).  The same operations in the same order.
+  constexpr bool kOwn = N == 8 * BS && first_radix<LOGN>() == 8;
   auto apply = [&](const bool* on) __attribute__((always_inline)) {
-#pragma unroll
-    for (int e = 0; e < E; ++e)
-      bufA[ptid + e * PBS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
-    __syncthreads();
     d2* in = bufA;
     d2* other = bufB;
-    fft<false, BS, LOGN>(&in, &other, tw);
+    if constexpr (kOwn) {
+      d2 v0[8];
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      in[ptid + e * PBS] =
-          in[ptid + e * PBS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
-    __syncthreads();
+      for (int e = 0; e < 8; ++e) v0[e] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
+      // bufB was last read by the previous step's inverse transform, before its final barrier
+      fft_stage<8, false, BS, N, true, false>(nullptr, bufB, tw, 1, v0);
+      in = bufB;
+      other = bufA;
+      const d2* t = tw + 1;
+      int Ns = 8;
+#pragma unroll 1
+      for (; Ns < N / 8; Ns *= 8) {
+        fft_stage<8, false, BS, N>(in, other, t, Ns);
+        d2* tmp = in; in = other; other = tmp;
+        t += Ns;
+      }
+      fft_stage<8, false, BS, N, false, true>(in, other, t, Ns, nullptr, hcp, hscale);
+      d2* tmp = in; in = other; other = tmp;
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        bufA[ptid + e * PBS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
+      __syncthreads();
+      fft<false, BS, LOGN>(&in, &other, tw);
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        in[ptid + e * PBS] =
+            in[ptid + e * PBS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
+      __syncthreads();
+    }
     fft<true, BS, LOGN>(&in, &other, tw);
     res = in;
   };
