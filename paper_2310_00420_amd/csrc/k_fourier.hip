@@ -68,15 +68,18 @@ __device__ inline void dft4(d2 x0, d2 x1, d2 x2, d2 x3, d2& u0, d2& u1, d2& u2, 
 // thread of the block must call it; one barrier at the end publishes dst.
 // With one butterfly per thread (N = R BS), butterfly j = threadIdx.x reads points j + r BS and,
 // when Ns = N / R, writes points j + r BS: the thread's own points in the natural order.  Then
-// IN_REGS takes the inputs from vin[r] instead of src, and SCALE multiplies output r by
-// hscale times the r-th byte of hc (the multiplier count of point j + r BS) before it is stored.
-template <int R, bool INV, int BS, int N, bool IN_REGS = false, bool SCALE = false>
+// IN_REGS takes the inputs from vin[r] instead of src, SCALE multiplies output r by hscale
+// times the r-th byte of hc (the multiplier count of point j + r BS), and OUT_REGS leaves the
+// outputs in vout[r] instead of storing them (no barrier then: nothing was written).
+template <int R, bool INV, int BS, int N, bool IN_REGS = false, bool SCALE = false,
+          bool OUT_REGS = false>
 __device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns,
                                  const d2* vin = nullptr, const uint32_t* hc = nullptr,
-                                 double hscale = 0.0) {
+                                 double hscale = 0.0, d2* vout = nullptr) {
   constexpr int NBF = N / R;                       // butterflies
   constexpr int PER = NBF >= BS ? NBF / BS : 1;    // per thread
-  static_assert(!(IN_REGS || SCALE) || NBF == BS, "own points need one butterfly per thread");
+  static_assert(!(IN_REGS || SCALE || OUT_REGS) || NBF == BS,
+                "own points need one butterfly per thread");
   // one butterfly at a time: their registers would otherwise crowd out the columns' state
 #pragma unroll 1
   for (int i = 0; i < PER; ++i) {
@@ -133,11 +136,12 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (SCALE) u[r] = u[r] * (hscale * (double)((hc[r / 4] >> (8 * (r % 4))) & 255u));
-        dst[pad(base + r * Ns)] = u[r];
+        if constexpr (OUT_REGS) vout[r] = u[r];
+        else dst[pad(base + r * Ns)] = u[r];
       }
     }
   }
-  __syncthreads();
+  if constexpr (!OUT_REGS) __syncthreads();
 }
 
 // Unnormalised DFT of the N points in *in (forward: exp(-2 pi i k d / N); inverse: conjugate),
@@ -260,22 +264,21 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
   // first write goes to bufA: every thread has finished reading the previous step's result by
   // then (two block reductions lie in between).
   const d2* res = bufA;
-  // With radix 8 throughout and one butterfly per thread (D = 4096), the forward transform's
-  // first stage reads exactly the thread's own points and its last stage writes them: the first
-  // stage takes d from registers (no store of d, no barrier, no load) and the last applies the
-  // multiplier before its store (no separate pass).  The same operations in the same order.
+  // With radix 8 throughout and one butterfly per thread (D = 4096), a stage with Ns = 1 reads
+  // exactly the thread's own points and one with Ns = N / 8 writes them.  So the forward
+  // transform's first stage takes d from registers, and its last stage, the multiplier and the
+  // inverse transform's first stage run on the same registers with no store, barrier or load in
+  // between.  The same operations in the same order.
   constexpr bool kOwn = N == 8 * BS && first_radix<LOGN>() == 8;
   auto apply = [&](const bool* on) __attribute__((always_inline)) {
     d2* in = bufA;
     d2* other = bufB;
     if constexpr (kOwn) {
-      d2 v0[8];
+      d2 v[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v0[e] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
-      // bufB was last read by the previous step's inverse transform, before its final barrier
-      fft_stage<8, false, BS, N, true, false>(nullptr, bufB, tw, 1, v0);
-      in = bufB;
-      other = bufA;
+      for (int e = 0; e < 8; ++e) v[e] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
+      // the previous step's result (bufA) was last read before the residual's block reduction
+      fft_stage<8, false, BS, N, true>(nullptr, bufA, tw, 1, v);
       const d2* t = tw + 1;
       int Ns = 8;
 #pragma unroll 1
@@ -284,8 +287,17 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
         d2* tmp = in; in = other; other = tmp;
         t += Ns;
       }
-      fft_stage<8, false, BS, N, false, true>(in, other, t, Ns, nullptr, hcp, hscale);
-      d2* tmp = in; in = other; other = tmp;
+      fft_stage<8, false, BS, N, false, true, true>(in, nullptr, t, Ns, nullptr, hcp, hscale, v);
+      // other was last read by the stage before, ahead of its barrier
+      fft_stage<8, true, BS, N, true>(nullptr, other, tw, 1, v);
+      { d2* tmp = in; in = other; other = tmp; }
+      t = tw + 1;
+#pragma unroll 1
+      for (Ns = 8; Ns < N; Ns *= 8) {
+        fft_stage<8, true, BS, N>(in, other, t, Ns);
+        d2* tmp = in; in = other; other = tmp;
+        t += Ns;
+      }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e)
@@ -297,8 +309,8 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
         in[ptid + e * PBS] =
             in[ptid + e * PBS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
       __syncthreads();
+      fft<true, BS, LOGN>(&in, &other, tw);
     }
-    fft<true, BS, LOGN>(&in, &other, tw);
     res = in;
   };
   auto ad_of = [&](int q, int e) __attribute__((always_inline)) {
