@@ -27,23 +27,27 @@ namespace {
 // Stages of the length-2^LOGN transform: one radix-2 or radix-4 stage for the factor that
 // radix 8 leaves, then radix 8.  Stage s (sub-transform length Ns before it, radix R) uses the
 // twiddles w^k = exp(-2 pi i k / (R Ns)), k < Ns, stored contiguously per stage, so that the
-// lanes of a butterfly row read consecutive entries.
+// lanes of a butterfly row read consecutive entries; each stage's table starts on a multiple of
+// 16 entries (256 bytes), so that 16 consecutive entries fill one aligned 256-byte block.
 template <int LOGN>
 constexpr int first_radix() { return LOGN % 3 == 1 ? 2 : LOGN % 3 == 2 ? 4 : 8; }
+constexpr int twiddle_stride(int ns) { return (ns + 15) & ~15; }
 template <int LOGN>
 constexpr int twiddle_len() {
   int n = 0;
-  for (int ns = 1, r = first_radix<LOGN>(); ns < (1 << LOGN); ns *= r, r = 8) n += ns;
+  for (int ns = 1, r = first_radix<LOGN>(); ns < (1 << LOGN); ns *= r, r = 8)
+    n += twiddle_stride(ns);
   return n;
 }
 
-// LDS slot of point i in a transform buffer: one unused slot after every 16 points, so that
-// the strided stores of the first radix-8 stage (stride 8 points) fall in distinct banks while
-// runs of consecutive points stay contiguous.  For a multiple m of 16, pad(i + m) =
-// pad(i) + pad(m).
-__device__ inline int pad(int i) { return i + (i >> 4); }
-template <int N>
-constexpr int padded_len() { return N + N / 16; }
+// LDS slot of point i in a transform buffer (16 bytes per slot): bits 0-2 of i XORed with bits
+// 3-5.  The slot stays in i's block of 16 (one aligned 256-byte block), so 16 lanes reading 16
+// consecutive points from a multiple of 16 read one aligned block, which is conflict-free on
+// gfx950; and 8 lanes storing points that differ in bits 0-2 with equal bits 3-5, or in bits
+// 3-5 with equal bits 0-2 (every stage's stores are one of the two), hit 8 different 16-byte
+// slots of a 128-byte bank row, also conflict-free.  For a multiple m of 64,
+// swz(i + m) = swz(i) + m.
+__device__ inline int swz(int i) { return i ^ ((i >> 3) & 7); }
 
 __device__ inline d2 cmul(d2 a, d2 b) {
   return d2{__builtin_fma(a[0], b[0], -a[1] * b[1]), __builtin_fma(a[0], b[1], a[1] * b[0])};
@@ -89,7 +93,7 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if constexpr (IN_REGS) v[r] = vin[r];
-        else v[r] = src[NBF % 16 == 0 ? pad(j) + r * (NBF + NBF / 16) : pad(j + r * NBF)];
+        else v[r] = src[NBF % 64 == 0 ? swz(j) + r * NBF : swz(j + r * NBF)];
       }
       const int k = j & (Ns - 1);
       // w^k from the stage's table (conjugated for the inverse); its higher powers by FP64
@@ -137,7 +141,7 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns,
       for (int r = 0; r < R; ++r) {
         if constexpr (SCALE) u[r] = u[r] * (hscale * (double)((hc[r / 4] >> (8 * (r % 4))) & 255u));
         if constexpr (OUT_REGS) vout[r] = u[r];
-        else dst[pad(base + r * Ns)] = u[r];
+        else dst[swz(base + r * Ns)] = u[r];
       }
     }
   }
@@ -154,7 +158,7 @@ __device__ inline void fft(d2** in, d2** other, const d2* tw) {
   if constexpr (first_radix<LOGN>() != 8) {
     fft_stage<first_radix<LOGN>(), INV, BS, N>(*in, *other, tw, Ns);
     d2* tmp = *in; *in = *other; *other = tmp;
-    tw += 1;
+    tw += twiddle_stride(1);
     Ns = first_radix<LOGN>();
   }
   // a runtime loop over the radix-8 stages: unrolled, the address arithmetic of every stage is
@@ -163,7 +167,7 @@ __device__ inline void fft(d2** in, d2** other, const d2* tw) {
   for (; Ns < N; Ns *= 8) {
     fft_stage<8, INV, BS, N>(*in, *other, tw, Ns);
     d2* tmp = *in; *in = *other; *other = tmp;
-    tw += Ns;
+    tw += twiddle_stride(Ns);
   }
 }
 
@@ -191,16 +195,16 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
     const uint64_t* __restrict__ keyp, const int8_t* __restrict__ probes, int crn, double beta,
     double tol2, int steps, int fixed, int T, int C, int R, int Rp) {
   constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>(), E = N / BS;
-  constexpr int NP = padded_len<N>();
+
   extern __shared__ double lds[];
-  d2* bufA = reinterpret_cast<d2*>(lds);           // two buffers of N complex points (padded)
-  d2* bufB = bufA + NP;
-  d2* tw = bufB + NP;                              // twiddles of every stage
+  d2* bufA = reinterpret_cast<d2*>(lds);           // two buffers of N complex points
+  d2* bufB = bufA + N;
+  d2* tw = bufB + N;                               // twiddles of every stage
   double* red = reinterpret_cast<double*>(tw + twiddle_len<LOGN>());   // 2 BS/64 partial sums
   const int tid = threadIdx.x;
-  // LDS slot of the thread's point e: pad(tid + e BS) (BS is a multiple of 16)
-  const int ptid = pad(tid);
-  constexpr int PBS = BS + BS / 16;
+  // LDS slot of the thread's point e: swz(tid + e BS) = swz(tid) + e BS
+  static_assert(BS % 64 == 0, "whole waves");
+  const int ptid = swz(tid);
   const int pairs = Rp / 2;
   const int t = blockIdx.x / pairs, p = blockIdx.x % pairs;
   const int j0 = 2 * p;
@@ -212,7 +216,7 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
         sincospi(2.0 * (double)k / (double)(r * ns), &sn, &cs);
         tw[off + k] = d2{cs, -sn};
       }
-      off += ns;
+      off += twiddle_stride(ns);
     }
   }
 
@@ -279,42 +283,42 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
       for (int e = 0; e < 8; ++e) v[e] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
       // the previous step's result (bufA) was last read before the residual's block reduction
       fft_stage<8, false, BS, N, true>(nullptr, bufA, tw, 1, v);
-      const d2* t = tw + 1;
+      const d2* t = tw + twiddle_stride(1);
       int Ns = 8;
 #pragma unroll 1
       for (; Ns < N / 8; Ns *= 8) {
         fft_stage<8, false, BS, N>(in, other, t, Ns);
         d2* tmp = in; in = other; other = tmp;
-        t += Ns;
+        t += twiddle_stride(Ns);
       }
       fft_stage<8, false, BS, N, false, true, true>(in, nullptr, t, Ns, nullptr, hcp, hscale, v);
       // other was last read by the stage before, ahead of its barrier
       fft_stage<8, true, BS, N, true>(nullptr, other, tw, 1, v);
       { d2* tmp = in; in = other; other = tmp; }
-      t = tw + 1;
+      t = tw + twiddle_stride(1);
 #pragma unroll 1
       for (Ns = 8; Ns < N; Ns *= 8) {
         fft_stage<8, true, BS, N>(in, other, t, Ns);
         d2* tmp = in; in = other; other = tmp;
-        t += Ns;
+        t += twiddle_stride(Ns);
       }
     } else {
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        bufA[ptid + e * PBS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
+        bufA[ptid + e * BS] = d2{on[0] ? dv[0][e] : 0.0, on[1] ? dv[1][e] : 0.0};
       __syncthreads();
       fft<false, BS, LOGN>(&in, &other, tw);
 #pragma unroll
       for (int e = 0; e < E; ++e)
-        in[ptid + e * PBS] =
-            in[ptid + e * PBS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
+        in[ptid + e * BS] =
+            in[ptid + e * BS] * (hscale * (double)((hcp[e / 4] >> (8 * (e % 4))) & 255u));
       __syncthreads();
       fft<true, BS, LOGN>(&in, &other, tw);
     }
     res = in;
   };
   auto ad_of = [&](int q, int e) __attribute__((always_inline)) {
-    return __builtin_fma((double)al[q][e], dv[q][e], res[ptid + e * PBS][q]);
+    return __builtin_fma((double)al[q][e], dv[q][e], res[ptid + e * BS][q]);
   };
 
   if (mode == 1) {
@@ -464,9 +468,9 @@ static hipError_t fourier_one(const Geometry& g, const CgState& s, const int* hc
                               const RhsSource& src, double tol2, int steps, int fixed,
                               hipStream_t st) {
   constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>();
-  // two padded buffers of N complex points, the twiddle tables, the reduction slots
+  // two buffers of N complex points, the twiddle tables, the reduction slots
   const size_t lds =
-      sizeof(double) * (4 * padded_len<N>() + 2 * twiddle_len<LOGN>() + 2 * (BS / 64));
+      sizeof(double) * (4 * N + 2 * twiddle_len<LOGN>() + 2 * (BS / 64));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_fourier_cg<LOGN>,
