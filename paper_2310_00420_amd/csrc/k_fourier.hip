@@ -97,20 +97,23 @@ __device__ inline void fft_stage(const d2* src, d2* dst, const d2* tw, int Ns,
       }
       const int k = j & (Ns - 1);
       // w^k from the stage's table (conjugated for the inverse); its higher powers by FP64
-      // complex products instead of more LDS reads
-      const d2 t1 = tw[k];
-      const d2 w1 = INV ? d2{t1[0], -t1[1]} : t1;
-      v[1] = cmul(v[1], w1);
-      if constexpr (R >= 4) {
-        const d2 w2 = cmul(w1, w1), w3 = cmul(w1, w2);
-        v[2] = cmul(v[2], w2);
-        v[3] = cmul(v[3], w3);
-        if constexpr (R == 8) {
-          const d2 w4 = cmul(w2, w2);
-          v[4] = cmul(v[4], w4);
-          v[5] = cmul(v[5], cmul(w1, w4));
-          v[6] = cmul(v[6], cmul(w2, w4));
-          v[7] = cmul(v[7], cmul(w3, w4));
+      // complex products instead of more LDS reads.  The first stage (Ns = 1) has only w^0 = 1
+      // and skips them (its calls pass Ns = 1 as a constant).
+      if (Ns > 1) {
+        const d2 t1 = tw[k];
+        const d2 w1 = INV ? d2{t1[0], -t1[1]} : t1;
+        v[1] = cmul(v[1], w1);
+        if constexpr (R >= 4) {
+          const d2 w2 = cmul(w1, w1), w3 = cmul(w1, w2);
+          v[2] = cmul(v[2], w2);
+          v[3] = cmul(v[3], w3);
+          if constexpr (R == 8) {
+            const d2 w4 = cmul(w2, w2);
+            v[4] = cmul(v[4], w4);
+            v[5] = cmul(v[5], cmul(w1, w4));
+            v[6] = cmul(v[6], cmul(w2, w4));
+            v[7] = cmul(v[7], cmul(w3, w4));
+          }
         }
       }
       d2 u[R];
