@@ -65,6 +65,45 @@ __device__ inline void dft4(d2 x0, d2 x1, d2 x2, d2 x3, d2& u0, d2& u1, d2& u2, 
   u3 = a1 - ma3;
 }
 
+// v taken from another lane by the DPP control CTRL (row_mask, bank_mask as in the
+// instruction); lanes the control leaves without a source, or outside row_mask, get 0.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ inline double dpp_take(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, BANK_MASK, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+// Sum of v over the wave, left in lane 63 (other lanes hold partial sums), through the
+// register crossbar only: pairs and quads (quad permutations), the four quads of a row (row
+// rotations by 4 and 8), then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15)
+// and rows 0-1 into rows 2-3 (broadcast of lane 31).  A fixed order of additions.
+__device__ inline double wave_sum_to_63(double v) {
+  v += dpp_take<0xB1>(v);          // quad_perm [1, 0, 3, 2]
+  v += dpp_take<0x4E>(v);          // quad_perm [2, 3, 0, 1]
+  v += dpp_take<0x124>(v);         // row_ror:4
+  v += dpp_take<0x128>(v);         // row_ror:8
+  v += dpp_take<0x142, 0xa>(v);    // row_bcast:15
+  v += dpp_take<0x143, 0xc>(v);    // row_bcast:31
+  return v;
+}
+
+// Block sums of (a, b), every thread receiving both.  One barrier: `sh` (2 BS/64 doubles) must
+// not be read by any thread any more, which holds when calls alternate between two areas (a
+// thread reads the partials of call n before it reaches the barrier of call n + 1).
+template <int BS>
+__device__ inline d2 block_sum2_alt(double a, double b, double* sh) {
+  a = wave_sum_to_63(a);
+  b = wave_sum_to_63(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 63) { sh[2 * w] = a; sh[2 * w + 1] = b; }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int i = 0; i < BS / 64; ++i) { sa += sh[2 * i]; sb += sh[2 * i + 1]; }
+  return d2{sa, sb};
+}
+
 // One Stockham stage of radix R (2, 4 or 8) over N points, out of place: butterfly j
 // (0 <= j < N/R) reads src[j + r N/R], multiplies input r by the twiddle w^(r k) (k = j mod Ns,
 // w = exp(-2 pi i / (R Ns))), transforms the R values and writes them to
@@ -203,7 +242,9 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
   d2* bufA = reinterpret_cast<d2*>(lds);           // two buffers of N complex points
   d2* bufB = bufA + N;
   d2* tw = bufB + N;                               // twiddles of every stage
-  double* red = reinterpret_cast<double*>(tw + twiddle_len<LOGN>());   // 2 BS/64 partial sums
+  // partial sums: two areas of 2 BS/64 doubles, alternated by successive reductions
+  double* red = reinterpret_cast<double*>(tw + twiddle_len<LOGN>());
+  double* red2 = red + 2 * (BS / 64);
   const int tid = threadIdx.x;
   // LDS slot of the thread's point e: swz(tid + e BS) = swz(tid) + e BS
   static_assert(BS % 64 == 0, "whole waves");
@@ -343,7 +384,7 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
     pr0 += rv[0][e] * rv[0][e];
     pr1 += rv[1][e] * rv[1][e];
   }
-  const d2 r0 = block_sum2<BS>(pr0, pr1, red);   // its barriers also publish the table
+  const d2 r0 = block_sum2_alt<BS>(pr0, pr1, red);   // its barrier also publishes the table
   double rr[2] = {r0[0], r0[1]}, thr[2];
   bool act[2];
   uint8_t st[2];
@@ -365,7 +406,7 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
       p0 += dv[0][e] * ad_of(0, e);
       p1 += dv[1][e] * ad_of(1, e);
     }
-    const d2 dAd = block_sum2<BS>(p0, p1, red);
+    const d2 dAd = block_sum2_alt<BS>(p0, p1, red2);
     double g[2] = {0.0, 0.0};
     bool upd[2];
 #pragma unroll
@@ -391,7 +432,7 @@ __global__ __launch_bounds__(fourier_bs<LOGN>()) void k_fourier_cg(
       p0 += rv[0][e] * rv[0][e];
       p1 += rv[1][e] * rv[1][e];
     }
-    const d2 rrn = block_sum2<BS>(p0, p1, red);
+    const d2 rrn = block_sum2_alt<BS>(p0, p1, red);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (!upd[q]) continue;
@@ -473,7 +514,7 @@ static hipError_t fourier_one(const Geometry& g, const CgState& s, const int* hc
   constexpr int N = 1 << LOGN, BS = fourier_bs<LOGN>();
   // two buffers of N complex points, the twiddle tables, the reduction slots
   const size_t lds =
-      sizeof(double) * (4 * N + 2 * twiddle_len<LOGN>() + 2 * (BS / 64));
+      sizeof(double) * (4 * N + 2 * twiddle_len<LOGN>() + 4 * (BS / 64));
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute((const void*)k_fourier_cg<LOGN>,
