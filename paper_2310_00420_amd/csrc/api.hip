@@ -98,6 +98,7 @@ struct cmtcs_handle_s {
   int max_rhs = 0, max_iters = 0, max_K = 0, Rp_max = 0;
   size_t vbytes = 8;
   std::vector<int64_t> row_off;
+  int64_t np16 = 0;   // sum over tasks of ceil(N_t / 16)
   const float* phi = nullptr;
   const float* phi_res = nullptr;   // MATH_MIXED: Phi of the FP32 true-residual products
   const float* y = nullptr;
@@ -271,6 +272,7 @@ struct cmtcs_handle_s {
     Geometry g;
     g.T = T; g.C = C; g.D = D; g.R = R; g.Rp = Rp;
     g.row_off = row_off_d; g.w_off = w_off_d;
+    g.fwd_split = fwd_split_of(np16, Rp, D);
     return g;
   }
 
@@ -886,6 +888,9 @@ cmtcs_status_t apply_noalloc(const cmtcs_problem_t* p, const float* alpha, int R
   Geometry g;
   g.T = T; g.C = C; g.D = D; g.R = R; g.Rp = Rp;
   g.row_off = row_off_d; g.w_off = w_off_d;
+  int64_t np16 = 0;
+  for (int t = 0; t < T; ++t) np16 += (p->row_off[t + 1] - p->row_off[t] + 15) / 16;
+  g.fwd_split = fwd_split_of(np16, Rp, D);
   hipLaunchKernelGGL((k_pad_cols<VT>), dim3(T * Rp, (D + 255) / 256), dim3(256), 0, st,
                      (const VT*)V, Dv, R, Rp, D);
   HIP_TRY(hipGetLastError(), "launch(pad_cols)");
@@ -975,6 +980,7 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   h->Rp_max = col_slots(p->max_rhs);
   h->vbytes = math == CMTCS_MATH_F64 ? 8 : 4;
   h->row_off.assign(p->row_off, p->row_off + p->T + 1);
+  for (int t = 0; t < p->T; ++t) h->np16 += (h->row_off[t + 1] - h->row_off[t] + 15) / 16;
   h->phi_dtype = (cmtcs_dtype_t)phi_dtype;
   h->phi = (const float*)p->phi;
   h->phi_res = p->phi_resid != nullptr ? p->phi_resid : (const float*)p->phi;

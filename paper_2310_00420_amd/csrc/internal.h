@@ -176,6 +176,8 @@ struct Geometry {
   int T, C, D, R, Rp;
   const int64_t* row_off;   // device [T+1]
   const int64_t* w_off;     // device [T+1]
+  // waves of a block that split the contraction of the FP32 forward product (fwd_split_of)
+  int fwd_split = 1;
 };
 
 // Wave tiles of the two operator products, one int4 per tile:
@@ -196,6 +198,16 @@ inline int col_slots(int R) {
 __host__ __device__ inline int group_width(int Rp) {
   const int frags = Rp / 16;
   return frags <= kColGroup ? frags : kColGroup;
+}
+
+// Forward products of FP32 right-hand sides split the contraction over d between the four waves
+// of a block when the problem has fewer 16-row tiles (over tasks and column groups) than the
+// chip has SIMDs (1024): with one wave per tile most SIMDs would idle.  The choice depends on
+// the problem alone, not on the tile height the autotuner picks, so that every tile height adds
+// the same partial sums in the same order.  np16: sum over tasks of ceil(N_t / 16).
+inline int fwd_split_of(int64_t np16, int Rp, int D) {
+  const int64_t groups = Rp / 16 / group_width(Rp);
+  return np16 * groups < 1024 && D >= 256 ? 4 : 1;
 }
 
 // Launchers (k_operator.hip).  `act` is the [T] count of active right-hand sides for the

@@ -111,7 +111,10 @@ int op_row_candidates(bool f64, int kind, int* rows) {
   return 3;
 }
 
-template <typename VT, int RF>
+// KSPL = 1: each wave of a block owns a tile.  KSPL = kOpWaves: the block owns one tile and its
+// waves split the contraction over d, wave w taking chunks [w nch / KSPL, (w + 1) nch / KSPL);
+// waves 1.. leave their sums in LDS and wave 0 adds them in wave order before the epilogue.
+template <typename VT, int RF, int KSPL = 1>
 __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict__ phi,
                                                const int64_t* __restrict__ row_off,
                                                const int64_t* __restrict__ w_off,
@@ -122,12 +125,17 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<VT, 4>::type vt4;
   constexpr int kRingA = ring_depth<VT>();
+  static_assert(KSPL == 1 || KSPL == kOpWaves, "one tile per wave or per block");
   __shared__ int cmap[kOpWaves][16 * kColGroup];
   const int lane = threadIdx.x & 63;
   const int i16 = lane & 15, g4 = lane >> 4;
   // tile fields are wave-uniform: keep them in scalar registers so that every branch on them
-  // is a scalar branch, not an exec-mask branch around matrix-core instructions
-  const int tile = uniform(xcd_block(blockIdx.x, gridDim.x) * kOpWaves + (threadIdx.x >> 6));
+  // is a scalar branch, not an exec-mask branch around matrix-core instructions.  With the
+  // split every return below is uniform over the block (its waves share the tile), so that
+  // all of them reach the barriers of the reduction or none does.
+  const int tile = KSPL > 1
+      ? uniform(xcd_block(blockIdx.x, gridDim.x))
+      : uniform(xcd_block(blockIdx.x, gridDim.x) * kOpWaves + (threadIdx.x >> 6));
   if (tile >= ntiles) return;
   const int4 tl = tiles[tile];
   const int t = uniform(tl.x), n0 = uniform(tl.y), cf0 = uniform(tl.z) * kColGroup;
@@ -179,11 +187,17 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   // present one.  In each slot the right-hand-side loads are issued before the Phi loads: the
   // memory counter completes in issue order, so waiting for a chunk's right-hand side then
   // does not also wait for the Phi loads of later chunks.
-  const int nch = D / 16;
+  // this wave's chunks: cb .. cb + nch - 1 (all D / 16 of them without the split)
+  const int wv = KSPL > 1 ? uniform(threadIdx.x >> 6) : 0;
+  const int cb = KSPL > 1 ? uniform(wv * (D / 16) / KSPL) : 0;
+  const int nch = KSPL > 1 ? uniform((wv + 1) * (D / 16) / KSPL) - cb : D / 16;
+  // a chunk index past the wave's last (or any, for a wave without chunks) re-reads the last
+  // one, or the range's first: in bounds, unused
+  const int clast = KSPL > 1 ? cb + max(nch - 1, 0) : nch - 1;
   f4 a[kRingA][RF];
   vt4 b[2][kColGroup];
   auto load_a = [&](f4 (&x)[RF], int c) __attribute__((always_inline)) {
-    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 64);
+    const uint32_t soff = (uint32_t)uniform(min(cb + c, clast) * 64);
 #pragma unroll
     for (int rf = 0; rf < RF; ++rf) x[rf] = buf_load<f4>(rphi, aoff[rf], soff);
   };
@@ -191,7 +205,7 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   // compaction), or 0 for any other count, then guarded at run time
   auto load_b = [&](vt4 (&x)[kColGroup], int c, auto nf) __attribute__((always_inline)) {
     constexpr int NF = decltype(nf)::value;
-    const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * 16 * (int)sizeof(VT));
+    const uint32_t soff = (uint32_t)uniform(min(cb + c, clast) * 16 * (int)sizeof(VT));
 #pragma unroll
     for (int cf = 0; cf < kColGroup; ++cf)
       if (NF == 0 || cf < NF) x[cf] = buf_load<vt4>(rv, boff[cf], soff);
@@ -252,6 +266,30 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phi_v(const float* __restrict
   if (ncf == kColGroup) run(std::integral_constant<int, kColGroup>{});   // no guards
   else if (ncf == kColGroup - 1) run(std::integral_constant<int, kColGroup - 1>{});
   else run(std::integral_constant<int, 0>{});
+
+  if constexpr (KSPL > 1) {
+    // wave 0 adds the sums of waves 1, 2, .. (in that order), one row fragment at a time;
+    // every wave passes the same 2 RF barriers
+    __shared__ acc_t red[(KSPL - 1) * kColGroup * 64];
+#pragma unroll
+    for (int rf = 0; rf < RF; ++rf) {
+      if (wv > 0) {
+#pragma unroll
+        for (int cf = 0; cf < kColGroup; ++cf)
+          if (cf < ncf) red[((wv - 1) * kColGroup + cf) * 64 + lane] = acc[rf][cf];
+      }
+      __syncthreads();
+      if (wv == 0) {
+#pragma unroll
+        for (int w = 1; w < KSPL; ++w)
+#pragma unroll
+          for (int cf = 0; cf < kColGroup; ++cf)
+            if (cf < ncf) acc[rf][cf] = acc[rf][cf] + red[((w - 1) * kColGroup + cf) * 64 + lane];
+      }
+      __syncthreads();
+    }
+    if (wv > 0) return;
+  }
 
   VT* Wt = W + w_off[t];
 #pragma unroll
@@ -956,6 +994,13 @@ template <typename VT, int RF>
 static hipError_t phi_v_rf(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                            const VT* V, VT* W, const int* act, const uint8_t* state,
                            hipStream_t st) {
+  if constexpr (sizeof(VT) == 4) {
+    if (g.fwd_split == kOpWaves) {   // one tile per block
+      hipLaunchKernelGGL((k_phi_v<VT, RF, kOpWaves>), dim3(ntiles), dim3(64 * kOpWaves), 0, st,
+                         phi, g.row_off, g.w_off, tiles, ntiles, V, W, act, state, g.D, g.Rp);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_phi_v<VT, RF>), dim3((ntiles + kOpWaves - 1) / kOpWaves), dim3(64 * kOpWaves), 0, st, phi,
                      g.row_off, g.w_off, tiles, ntiles, V, W, act, state, g.D, g.Rp);
   return hipGetLastError();
