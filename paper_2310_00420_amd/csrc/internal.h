@@ -83,18 +83,39 @@ __device__ inline double probe_entry(uint64_t key, int t, int c, int k, int d, i
 }
 
 // ---------------------------------------------------------------------------------------------
-// Fixed-order block reduction of two doubles at once; every thread receives both sums.  `sh`
-// needs 2 BS/64 doubles of shared memory.
+// v taken from another lane by the DPP control CTRL (row_mask, bank_mask as in the
+// instruction); lanes the control leaves without a source, or outside row_mask, get 0.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ inline double dpp_take(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, BANK_MASK, false),
+                          __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, BANK_MASK, false));
+}
+
+// Sum of v over the wave, left in lane 63 (other lanes hold partial sums), through the
+// register crossbar only: pairs and quads (quad permutations), the four quads of a row (row
+// rotations by 4 and 8), then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15)
+// and rows 0-1 into rows 2-3 (broadcast of lane 31).  A fixed order of additions.
+__device__ inline double wave_sum_to_63(double v) {
+  v += dpp_take<0xB1>(v);          // quad_perm [1, 0, 3, 2]
+  v += dpp_take<0x4E>(v);          // quad_perm [2, 3, 0, 1]
+  v += dpp_take<0x124>(v);         // row_ror:4
+  v += dpp_take<0x128>(v);         // row_ror:8
+  v += dpp_take<0x142, 0xa>(v);    // row_bcast:15
+  v += dpp_take<0x143, 0xc>(v);    // row_bcast:31
+  return v;
+}
+
+// Fixed-order block reduction of two doubles at once; every thread of the block must call it
+// (with every lane active) and receives both sums.  `sh` needs 2 BS/64 doubles of shared
+// memory; the first barrier lets consecutive calls share it.
 template <int BS>
 __device__ inline d2 block_sum2(double a, double b, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_xor(a, o, 64);
-    b += __shfl_xor(b, o, 64);
-  }
+  a = wave_sum_to_63(a);
+  b = wave_sum_to_63(b);
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) { sh[2 * w] = a; sh[2 * w + 1] = b; }
+  if ((threadIdx.x & 63) == 63) { sh[2 * w] = a; sh[2 * w + 1] = b; }
   __syncthreads();
   double sa = 0.0, sb = 0.0;
 #pragma unroll
@@ -106,11 +127,10 @@ __device__ inline d2 block_sum2(double a, double b, double* sh) {
 // must call it; every thread receives the sum.  `sh` needs BS/64 doubles of shared memory.
 template <int BS>
 __device__ inline double block_sum(double v, double* sh) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  v = wave_sum_to_63(v);
   const int w = threadIdx.x >> 6;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  if ((threadIdx.x & 63) == 63) sh[w] = v;
   __syncthreads();
   double s = 0.0;
 #pragma unroll

@@ -65,29 +65,6 @@ __device__ inline void dft4(d2 x0, d2 x1, d2 x2, d2 x3, d2& u0, d2& u1, d2& u2, 
   u3 = a1 - ma3;
 }
 
-// v taken from another lane by the DPP control CTRL (row_mask, bank_mask as in the
-// instruction); lanes the control leaves without a source, or outside row_mask, get 0.
-template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
-__device__ inline double dpp_take(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, BANK_MASK, false),
-                          __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, BANK_MASK, false));
-}
-
-// Sum of v over the wave, left in lane 63 (other lanes hold partial sums), through the
-// register crossbar only: pairs and quads (quad permutations), the four quads of a row (row
-// rotations by 4 and 8), then row 0 into row 1 and row 2 into row 3 (broadcast of lane 15)
-// and rows 0-1 into rows 2-3 (broadcast of lane 31).  A fixed order of additions.
-__device__ inline double wave_sum_to_63(double v) {
-  v += dpp_take<0xB1>(v);          // quad_perm [1, 0, 3, 2]
-  v += dpp_take<0x4E>(v);          // quad_perm [2, 3, 0, 1]
-  v += dpp_take<0x124>(v);         // row_ror:4
-  v += dpp_take<0x128>(v);         // row_ror:8
-  v += dpp_take<0x142, 0xa>(v);    // row_bcast:15
-  v += dpp_take<0x143, 0xc>(v);    // row_bcast:31
-  return v;
-}
-
 // Block sums of (a, b), every thread receiving both.  One barrier: `sh` (2 BS/64 doubles) must
 // not be read by any thread any more, which holds when calls alternate between two areas (a
 // thread reads the partials of call n before it reaches the barrier of call n + 1).
