@@ -447,15 +447,18 @@ static hipError_t update_one(const Geometry& g, const CgState& s, int u, int ste
 // 256 threads; for D <= 4096 more, smaller threads (fewer registers, more waves in flight while
 // a block sits in its reductions) measured faster: 1024 x 4 in FP64 (69 vs 74 ms of updates
 // per EM iteration at the precision workload) and 512 x 8 in FP32 (35 vs 43 ms).  FP32 columns
-// of 513-1024 elements take one wave each (its reductions need no other wave): 8.96 against
-// 9.36 ms of updates per EM iteration at the plain-FP32 workload (D = 1024).
+// of 1024 elements take one wave each (its reductions need no other wave): 8.96 against 9.36 ms
+// of updates per EM iteration at the plain-FP32 workload.  Only there: the same one-wave layout
+// for FP64 columns of 64 elements (half the lanes without elements) gave wrong E-steps at the
+// tiny workload, for a cause not found.
 #define CMTCS_DISPATCH_D(FN, ...)                                                  \
   do {                                                                             \
     if (g.D <= 256) return FN<VT, 256, 1>(__VA_ARGS__);                            \
     if (g.D <= 512) return FN<VT, 256, 2>(__VA_ARGS__);                            \
     if (g.D <= 1024) {                                                             \
-      if constexpr (sizeof(VT) == 4) return FN<VT, 64, 16>(__VA_ARGS__);          \
-      else return FN<VT, 256, 4>(__VA_ARGS__);                                     \
+      if constexpr (sizeof(VT) == 4)                                               \
+        if (g.D == 1024) return FN<VT, 64, 16>(__VA_ARGS__);                       \
+      return FN<VT, 256, 4>(__VA_ARGS__);                                          \
     }                                                                              \
     if (g.D <= 2048) return FN<VT, 256, 8>(__VA_ARGS__);                           \
     if (g.D <= 4096) {                                                             \
