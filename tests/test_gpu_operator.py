@@ -35,6 +35,8 @@ def _ref_apply(w, alpha, V, cc):
     dict(T=2, C=4, D=512, N=256, R=150),                   # two column groups
     dict(T=4, C=1, D=48, N=[5, 16, 33, 1], R=9),           # one-chunk tasks, odd chunk count
     dict(T=3, C=2, D=96, N=[40, 0, 23], R=130),            # last fragment 2/16 full, empty task
+    # FP32: the forward contraction split over four waves unevenly (25 chunks: 6, 6, 6, 7)
+    dict(T=3, C=2, D=400, N=[0, 45, 130], R=21),
 ])
 def test_apply(math, tol, shape):
     shape = dict(shape)
