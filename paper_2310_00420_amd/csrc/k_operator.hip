@@ -793,7 +793,6 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
     const float* __restrict__ alpha, const int* __restrict__ colc, double beta,
     const int* __restrict__ act, const uint8_t* __restrict__ state, int D, int Rp) {
   typedef typename Mfma<VT>::acc_t acc_t;
-  typedef typename VecOf<VT, 4>::type vt4;
   typedef typename VecOf<float, RF>::type frf;
   typedef LdsChunk<VT> L;
   typedef typename L::piece_t piece_t;
