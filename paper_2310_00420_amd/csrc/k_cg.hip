@@ -446,7 +446,8 @@ static hipError_t update_one(const Geometry& g, const CgState& s, int u, int ste
 // Dispatch on D: the column is split over BS threads with EPT elements each.  Up to D = 2048,
 // 256 threads; for D <= 4096 more, smaller threads (fewer registers, more waves in flight while
 // a block sits in its reductions) measured faster: 1024 x 4 in FP64 (69 vs 74 ms of updates
-// per EM iteration at the precision workload) and 512 x 8 in FP32 (35 vs 43 ms).  FP32 columns
+// per EM iteration at the precision workload against 256 x 16; 512 x 8 ran 67.2 against
+// 66.6 ms) and 512 x 8 in FP32 (35 vs 43 ms).  FP32 columns
 // of 1024 elements take one wave each (its reductions need no other wave): 8.96 against 9.36 ms
 // of updates per EM iteration at the plain-FP32 workload.  Only there: the same one-wave layout
 // for FP64 columns of 64 elements (half the lanes without elements) gave wrong E-steps at the
