@@ -99,6 +99,12 @@ struct cmtcs_handle_s {
   size_t vbytes = 8;
   std::vector<int64_t> row_off;
   int64_t np16 = 0;   // sum over tasks of ceil(N_t / 16)
+  // FP64 problems: Phi transposed per task for the LDS-staged adjoint product, rebuilt from Phi
+  // at the start of every call that multiplies (so that a caller may change Phi in place)
+  float* phiT = nullptr;
+  int64_t* pt_off_d = nullptr;
+  std::vector<int64_t> pt_off;   // [T + 1]: sum over earlier tasks of N_t rounded up to 16
+  int max_np = 0;
   const float* phi = nullptr;
   const float* phi_res = nullptr;   // MATH_MIXED: Phi of the FP32 true-residual products
   const float* y = nullptr;
@@ -273,7 +279,17 @@ struct cmtcs_handle_s {
     g.T = T; g.C = C; g.D = D; g.R = R; g.Rp = Rp;
     g.row_off = row_off_d; g.w_off = w_off_d;
     g.fwd_split = fwd_split_of(np16, Rp, D);
+    g.phiT = phiT;
     return g;
+  }
+
+  // Geometry of an operator call, with phiT rebuilt from Phi first
+  cmtcs_status_t op_geom(int R, int Rp, Geometry* g) {
+    *g = geom(R, Rp);
+    if (phiT != nullptr)
+      HIP_TRY(launch_transpose_phi(phi, row_off_d, pt_off_d, phiT, T, D, max_np, st),
+              "launch(transpose_phi)");
+    return CMTCS_OK;
   }
 
   Geometry geom16(int R, int Rp) const {
@@ -550,7 +566,9 @@ struct cmtcs_handle_s {
     }
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
-    const Geometry g = geom(R, Rp);
+    Geometry g;
+    rs = op_geom(R, Rp, &g);
+    if (rs != CMTCS_OK) return rs;
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
     RhsSource src;
     src.kind = 1; src.b = nullptr; src.B = V; src.K = 0; src.keyp = nullptr; src.probes = nullptr;
@@ -592,7 +610,9 @@ struct cmtcs_handle_s {
     const int K = o.K, R = C * (K + 1), Rp = col_slots(R);
     cmtcs_status_t rs = fourier ? CMTCS_OK : prepare(Rp);
     if (rs != CMTCS_OK) return rs;
-    const Geometry g = geom(R, Rp);
+    Geometry g;
+    rs = op_geom(R, Rp, &g);
+    if (rs != CMTCS_OK) return rs;
     const uint64_t key = probe_key(o.seed, o.em_iter);
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
@@ -679,7 +699,9 @@ struct cmtcs_handle_s {
     const int K = o.K, R = C * (K + 1), Rp = col_slots(R);
     cmtcs_status_t rs = prepare(Rp);
     if (rs != CMTCS_OK) return rs;
-    const Geometry g = geom(R, Rp);
+    Geometry g;
+    rs = op_geom(R, Rp, &g);
+    if (rs != CMTCS_OK) return rs;
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, K, nullptr, st), "launch(fill_colc)");
@@ -722,7 +744,9 @@ struct cmtcs_handle_s {
     const int Rp = col_slots(R);
     cmtcs_status_t rs = fourier ? CMTCS_OK : prepare(Rp);
     if (rs != CMTCS_OK) return rs;
-    const Geometry g = geom(R, Rp);
+    Geometry g;
+    rs = op_geom(R, Rp, &g);
+    if (rs != CMTCS_OK) return rs;
     const int fixed = o.fixed_iters > 0 ? 1 : 0;
     const int steps = fixed ? o.fixed_iters : o.max_iters;
     HIP_TRY(launch_fill_colc(colc, T, R, Rp, 0, col_cluster, st), "launch(fill_colc)");
@@ -1045,6 +1069,16 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   } else {
     A(&h->Rv, vec); A(&h->Dv, vec); A(&h->AD, vec);
     A(&h->W, Rpm * np_sum * h->vbytes);
+    if (f64) {
+      h->pt_off.assign(T + 1, 0);
+      for (size_t t = 0; t < T; ++t) {
+        const int np = round16((int)(h->row_off[t + 1] - h->row_off[t]));
+        h->pt_off[t + 1] = h->pt_off[t] + np;
+        h->max_np = std::max(h->max_np, np);
+      }
+      A(&h->phiT, sizeof(float) * D * np_sum);
+      A(&h->pt_off_d, sizeof(int64_t) * (T + 1));
+    }
     A(&h->mbase, sizeof(double) * T * D);
     A(&h->mdiag, sizeof(double) * T * C * D);
     A(&h->slogm, sizeof(double) * T * C);
@@ -1096,6 +1130,9 @@ cmtcs_status_t cmtcs_create(cmtcs_handle_t* out, const cmtcs_problem_t* p, void*
   }
   e = hipMemcpyAsync(h->row_off_d, h->row_off.data(), sizeof(int64_t) * (T + 1),
                      hipMemcpyHostToDevice, h->st);
+  if (e == hipSuccess && h->pt_off_d != nullptr)   // from the handle's own vector
+    e = hipMemcpyAsync(h->pt_off_d, h->pt_off.data(), sizeof(int64_t) * (T + 1),
+                       hipMemcpyHostToDevice, h->st);
   int bad = 0;
   if (e == hipSuccess) {
     const Geometry g = h->geom(1, 16);

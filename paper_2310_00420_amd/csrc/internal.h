@@ -198,6 +198,9 @@ struct Geometry {
   const int64_t* w_off;     // device [T+1]
   // waves of a block that split the contraction of the FP32 forward product (fwd_split_of)
   int fwd_split = 1;
+  // Phi transposed per task (launch_transpose_phi) for the FP64 LDS-staged adjoint product, or
+  // null (that product then reads Phi itself)
+  const float* phiT = nullptr;
 };
 
 // Wave tiles of the two operator products, one int4 per tile:
@@ -237,6 +240,11 @@ inline int fwd_split_of(int64_t np16, int Rp, int D) {
 // adjoint product of one step take the same `state`), without it every slot is multiplied.
 // `rows` is the output rows per wave tile the tile table was built for (one of
 // op_row_candidates).
+// phiT <- Phi_t transposed for every task: task t at element D pt_off[t], D rows of
+// np_t = pt_off[t + 1] - pt_off[t] elements (np_t >= N_t; rows n >= N_t written as zeros).
+// max_np: the largest np_t.  Reads Phi once and writes phiT once.
+hipError_t launch_transpose_phi(const float* phi, const int64_t* row_off, const int64_t* pt_off,
+                                float* phiT, int T, int D, int max_np, hipStream_t st);
 template <typename VT>
 hipError_t launch_phi_v(const Geometry& g, const float* phi, const int4* tiles, int ntiles,
                         const VT* V, VT* W, const int* act, const uint8_t* state, int rows,

@@ -785,13 +785,19 @@ __global__ __launch_bounds__(64 * kOpWaves) void k_phit_w(const float* __restric
 // buffer, and the Phi operand (four rows of n per lane and chunk, RF consecutive d each) is
 // prefetched per wave in a register ring, through a per-chunk descriptor as in k_phit_w.  The
 // k-steps, accumulation order and epilogue are those of k_phit_w, so the results are the same.
-template <typename VT, int RF>
+// TR (RF = 1): the Phi operand comes from phiT, Phi_t transposed (D rows of np_t elements, rows
+// N_t.. of Phi zero; task t at element D w_off[t] / Rp): the four rows of n a lane needs per
+// chunk are then four consecutive elements, one 16-byte load instead of four 4-byte ones.  The
+// same values reach the same matrix-core steps, so the results do not change.
+template <typename VT, int RF, bool TR = false>
 __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void k_phit_w_lds(
     const float* __restrict__ phi, const int64_t* __restrict__ row_off,
     const int64_t* __restrict__ w_off, const int4* __restrict__ tiles, int ntiles,
     const VT* __restrict__ W, const VT* __restrict__ V, VT* __restrict__ AV,
     const float* __restrict__ alpha, const int* __restrict__ colc, double beta,
-    const int* __restrict__ act, const uint8_t* __restrict__ state, int D, int Rp) {
+    const int* __restrict__ act, const uint8_t* __restrict__ state, int D, int Rp,
+    const float* __restrict__ phiT) {
+  static_assert(!TR || RF == 1, "the transposed operand serves one row per lane");
   typedef typename Mfma<VT>::acc_t acc_t;
   typedef typename VecOf<float, RF>::type frf;
   typedef LdsChunk<VT> L;
@@ -866,12 +872,23 @@ __global__ __launch_bounds__(64 * kOpWaves, (lds_waves_per_simd<VT, RF>())) void
 
   frf a[kRingA][KS];
   piece_t stg[L::kPerThread];
+  // TR: row dl of the task's transposed block; rows past N_t hold zeros there
+  const rsrc_t rT = TR ? make_rsrc(phiT + (w_off[t] / Rp) * (int64_t)D,
+                                   (uint32_t)((int64_t)np * D * 4))
+                       : make_rsrc(phi, 0u);   // unused
+  const uint32_t aoffT = (uint32_t)(((int64_t)(dl < D ? dl : 0) * np + KS * g4) * 4);
   auto load_a = [&](frf (&x)[KS], int c) __attribute__((always_inline)) {
     const int nb = uniform(min(c, nch - 1) * KC);
-    const rsrc_t ra = make_rsrc(phit + (int64_t)nb * D,
-                                (uint32_t)((int64_t)max(nt - nb, 0) * D * 4));
+    if constexpr (TR) {
+      const f4 v = buf_load<f4>(rT, aoffT, (uint32_t)(nb * 4));
 #pragma unroll
-    for (int s = 0; s < KS; ++s) x[s] = buf_load<frf>(ra, aoff0, (uint32_t)(s * D * 4));
+      for (int s = 0; s < KS; ++s) x[s] = v[s];
+    } else {
+      const rsrc_t ra = make_rsrc(phit + (int64_t)nb * D,
+                                  (uint32_t)((int64_t)max(nt - nb, 0) * D * 4));
+#pragma unroll
+      for (int s = 0; s < KS; ++s) x[s] = buf_load<frf>(ra, aoff0, (uint32_t)(s * D * 4));
+    }
   };
   auto stage_load = [&](int c) __attribute__((always_inline)) {
     const uint32_t soff = (uint32_t)uniform(min(c, nch - 1) * KC * (int)sizeof(VT));
@@ -1030,9 +1047,52 @@ static hipError_t phit_w_lds_rf(const Geometry& g, const float* phi, const int4*
                                 int ntiles, const VT* W, const VT* V, VT* AV, const float* alpha,
                                 const int* colc, double beta, const int* act,
                             const uint8_t* state, hipStream_t st) {
+  if constexpr (RF == 1) {
+    if (g.phiT != nullptr) {
+      hipLaunchKernelGGL((k_phit_w_lds<VT, RF, true>), dim3(ntiles), dim3(64 * kOpWaves), 0, st,
+                         phi, g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act,
+                         state, g.D, g.Rp, g.phiT);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_phit_w_lds<VT, RF>), dim3(ntiles), dim3(64 * kOpWaves), 0, st, phi,
                      g.row_off, g.w_off, tiles, ntiles, W, V, AV, alpha, colc, beta, act, state,
-                     g.D, g.Rp);
+                     g.D, g.Rp, nullptr);
+  return hipGetLastError();
+}
+
+// Phi_t transposed into phiT (task t at element D pt_off[t]: D rows of np_t = pt_off[t + 1] -
+// pt_off[t] elements, np_t >= N_t, the rows n >= N_t zero).  One block per 64 x 64 tile of
+// (n, d), through LDS so that both the reads (along d) and the writes (along n) are coalesced.
+__global__ __launch_bounds__(256) void k_transpose_phi(const float* __restrict__ phi,
+                                                      const int64_t* __restrict__ row_off,
+                                                      const int64_t* __restrict__ pt_off,
+                                                      float* __restrict__ phiT, int D) {
+  __shared__ float tile[64][65];
+  const int t = blockIdx.z;
+  const int n0 = blockIdx.y * 64, d0 = blockIdx.x * 64;
+  const int64_t np = pt_off[t + 1] - pt_off[t];
+  if (n0 >= np) return;   // uniform over the block
+  const int64_t nt = row_off[t + 1] - row_off[t];
+  const float* src = phi + row_off[t] * (int64_t)D;
+  float* dst = phiT + pt_off[t] * (int64_t)D;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 64 x 4
+  for (int i = ty; i < 64; i += 4) {
+    const int n = n0 + i, d = d0 + tx;
+    tile[i][tx] = (n < nt && d < D) ? src[(int64_t)n * D + d] : 0.0f;
+  }
+  __syncthreads();
+  for (int i = ty; i < 64; i += 4) {
+    const int d = d0 + i, n = n0 + tx;
+    if (d < D && n < np) dst[(int64_t)d * np + n] = tile[tx][i];
+  }
+}
+
+hipError_t launch_transpose_phi(const float* phi, const int64_t* row_off, const int64_t* pt_off,
+                                float* phiT, int T, int D, int max_np, hipStream_t st) {
+  if (T == 0 || max_np == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_transpose_phi, dim3((D + 63) / 64, (max_np + 63) / 64, T), dim3(256), 0,
+                     st, phi, row_off, pt_off, phiT, D);
   return hipGetLastError();
 }
 
