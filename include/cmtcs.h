@@ -109,7 +109,10 @@ typedef struct {
                                whole 144-column groups past 144) must each stay below 4 GiB,
                                else CMTCS_E_UNSUPPORTED                                     */
   const void* phi;          /* device [row_off[T]][D] float: the stacked Phi_t (OP_DENSE;
-                               ignored for OP_PARTIAL_FOURIER)                              */
+                               ignored for OP_PARTIAL_FOURIER).  With MATH_F64 the workspace
+                               also holds Phi_t transposed (round16(N_t)*D*4 bytes per
+                               task), rebuilt from phi by every call that applies the
+                               operator                                                     */
   cmtcs_dtype_t phi_dtype;  /* F32 for MATH_F64 / MATH_F32; for MATH_MIXED the 16-bit type
                                (BF16 or F16) the library stores Phi in                      */
   const float* phi_resid;   /* MATH_MIXED only: optional device [row_off[T]][D] float Phi
